@@ -1,0 +1,26 @@
+"""Build the oracle's shared library (TEST INFRASTRUCTURE).
+
+The parity build uses ``-O2 -ffp-contract=off`` so that no fused multiply-add
+changes the rounding of the plain definition.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pkh_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(force=True):
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-Wno-unused-function", SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())

@@ -1,0 +1,227 @@
+"""Seeded synthetic inputs: leaf lists and initial states.
+
+This module holds no arithmetic of the hydro method: it only builds block
+lists and initial conditions, which the GPU path and the CPU oracle then
+receive identically. It imports nothing from the rest of the package.
+
+Random numbers come from a counter-based generator: SplitMix64 (Steele,
+Lea & Flood 2014) keyed by (seed, field, global cell index), mapped to
+uniforms in (0, 1) and to normals by Box-Muller. The initial state is
+therefore independent of how the domain is cut into blocks.
+
+State layout: ``[nleaves][5][n3][n2][n1]`` conserved variables
+(rho, Mx, My, Mz, E), x fastest, leaves in the order given.
+"""
+import numpy as np
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _splitmix64(x):
+    x = (x + np.uint64(0x9E3779B97F4A7C15)) & _M64
+    z = x
+    z = ((z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)) & _M64
+    z = ((z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)) & _M64
+    return z ^ (z >> np.uint64(31))
+
+
+def uniforms(seed, field, index):
+    """Uniform deviates in (0, 1) for integer cell indices (any shape)."""
+    with np.errstate(over="ignore"):
+        k = _splitmix64(np.uint64(seed))
+        k = _splitmix64(k ^ np.uint64(field))
+        x = _splitmix64(np.asarray(index, dtype=np.uint64) ^ k)
+    return ((x >> np.uint64(11)).astype(np.float64) + 0.5) * (1.0 / 9007199254740992.0)
+
+
+def normals(seed, field, index):
+    """Standard normal deviates by Box-Muller from two keyed streams."""
+    index = np.asarray(index, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        u1 = uniforms(seed, 2 * field, index)
+        u2 = uniforms(seed, 2 * field + 1, index)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+# ---------------------------------------------------------------------------
+# Leaf lists
+# ---------------------------------------------------------------------------
+
+def uniform_leaves(nrb):
+    """All level-0 blocks of a root grid of nrb = (bx, by, bz) blocks."""
+    bx, by, bz = nrb
+    return np.array([(0, x, y, z) for z in range(bz) for y in range(by) for x in range(bx)],
+                    dtype=np.int32)
+
+
+def sphere_refined_leaves(nrb, center=(0.5, 0.5, 0.5), radius=0.25, xmin=(0, 0, 0),
+                          xmax=(1, 1, 1)):
+    """Level-0 blocks, with every block whose open interior meets the open
+    ball |x - center| < radius replaced by its 8 level-1 children."""
+    out = []
+    for z in range(nrb[2]):
+        for y in range(nrb[1]):
+            for x in range(nrb[0]):
+                lo = [xmin[d] + (v) * (xmax[d] - xmin[d]) / nrb[d] for d, v in enumerate((x, y, z))]
+                hi = [xmin[d] + (v + 1) * (xmax[d] - xmin[d]) / nrb[d] for d, v in enumerate((x, y, z))]
+                near = [min(max(center[d], lo[d]), hi[d]) for d in range(3)]
+                dist2 = sum((near[d] - center[d]) ** 2 for d in range(3))
+                if dist2 < radius * radius:
+                    for c in range(8):
+                        out.append((1, 2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + ((c >> 2) & 1)))
+                else:
+                    out.append((0, x, y, z))
+    return np.array(out, dtype=np.int32)
+
+
+def cell_centers(leaf, n, nrb, xmin=(0.0, 0.0, 0.0), xmax=(1.0, 1.0, 1.0)):
+    """Cell-centre coordinates (x, y, z), each shaped [n3][n2][n1]."""
+    lev, lx, ly, lz = (int(v) for v in leaf)
+    axes = []
+    for d, l in enumerate((lx, ly, lz)):
+        N = nrb[d] * n[d] * (1 << lev)
+        dx = (xmax[d] - xmin[d]) / N
+        axes.append(xmin[d] + (l * n[d] + np.arange(n[d]) + 0.5) * dx)
+    z, y, x = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return x, y, z
+
+
+def global_index(leaf, n, nrb):
+    """Global cell index (k*N2 + j)*N1 + i at the leaf's level, [n3][n2][n1]."""
+    lev, lx, ly, lz = (int(v) for v in leaf)
+    N1 = nrb[0] * n[0] << lev
+    N2 = nrb[1] * n[1] << lev
+    i = lx * n[0] + np.arange(n[0], dtype=np.int64)
+    j = ly * n[1] + np.arange(n[1], dtype=np.int64)
+    k = lz * n[2] + np.arange(n[2], dtype=np.int64)
+    K, J, I = np.meshgrid(k, j, i, indexing="ij")
+    return ((K * N2 + J) * N1 + I).astype(np.uint64)
+
+
+def _to_conserved(rho, vx, vy, vz, p, gamma):
+    out = np.empty((5,) + np.shape(rho))
+    out[0] = rho
+    out[1] = rho * vx
+    out[2] = rho * vy
+    out[3] = rho * vz
+    out[4] = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Initial conditions
+# ---------------------------------------------------------------------------
+
+def sound_wave(leaves, n, nrb, amp=1e-6, noise=1e-8, seed=1, gamma=5.0 / 3.0, rho0=1.0,
+               p0=0.6, kvec=(1, 0, 0), xmin=(0, 0, 0), xmax=(1, 1, 1)):
+    """Right-going linear sound wave on a uniform background plus keyed
+    white noise on each conserved field.
+
+    With rho0 = 1, p0 = 0.6, gamma = 5/3 the sound speed is 1 and the
+    eigenvector is (1, 1, 0, 0, 1.5) along kvec = (1, 0, 0)."""
+    cs = np.sqrt(gamma * p0 / rho0)
+    kv = np.asarray(kvec, dtype=np.float64)
+    khat = kv / np.linalg.norm(kv)
+    h0 = (p0 / (gamma - 1.0) + p0) / rho0
+    eig = np.array([1.0, cs * khat[0], cs * khat[1], cs * khat[2], h0])
+    U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    for b, lf in enumerate(leaves):
+        x, y, z = cell_centers(lf, n, nrb, xmin, xmax)
+        phase = 2.0 * np.pi * (kv[0] * x + kv[1] * y + kv[2] * z)
+        bg = _to_conserved(np.full_like(x, rho0), 0 * x, 0 * x, 0 * x, np.full_like(x, p0), gamma)
+        s = np.sin(phase)
+        U[b] = bg + amp * eig[:, None, None, None] * s[None]
+        if noise:
+            gi = global_index(lf, n, nrb)
+            for v in range(5):
+                U[b, v] += noise * normals(seed, v, gi)
+    return U
+
+
+def uniform_state(leaves, n, rho=1.0, v=(0.0, 0.0, 0.0), p=1.0, gamma=5.0 / 3.0):
+    U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    one = np.ones((n[2], n[1], n[0]))
+    U[:] = _to_conserved(rho * one, v[0] * one, v[1] * one, v[2] * one, p * one, gamma)[None]
+    return U
+
+
+def _smoothed_field(N, seed, field, sigma=4.0, trunc=12):
+    """Unit-variance, zero-mean periodic field: keyed white noise convolved
+    with a separable Gaussian (sigma cells, truncated at +-trunc cells)."""
+    N1, N2, N3 = N
+    idx = np.arange(N1 * N2 * N3, dtype=np.uint64).reshape(N3, N2, N1)
+    w = normals(seed, field, idx)
+    spec = np.fft.rfftn(w)
+    kern = []
+    for Nd in (N3, N2, N1):
+        k = np.zeros(Nd)
+        offs = np.arange(-trunc, trunc + 1)
+        wts = np.exp(-0.5 * (offs / sigma) ** 2)
+        wts /= wts.sum()
+        np.add.at(k, offs % Nd, wts)
+        kern.append(np.fft.fft(k))
+    K3 = kern[0][:, None, None] * kern[1][None, :, None] * kern[2][None, None, : N1 // 2 + 1]
+    g = np.fft.irfftn(spec * K3, s=(N3, N2, N1), axes=(0, 1, 2))
+    g -= g.mean()
+    g /= g.std()
+    return g
+
+
+def _scatter(fields, leaves, n):
+    U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    for b, (lev, lx, ly, lz) in enumerate(leaves):
+        assert lev == 0
+        U[b] = fields[:, lz * n[2]:(lz + 1) * n[2], ly * n[1]:(ly + 1) * n[1], lx * n[0]:(lx + 1) * n[0]]
+    return U
+
+
+def turbulent_box(leaves, n, nrb, seed=2, gamma=5.0 / 3.0, sigma_ln=0.5, mach=0.5, p0=1.0):
+    """Log-normal density rho = exp(sigma g - sigma^2/2) from a smoothed
+    unit-variance field g, uniform pressure p0, and a velocity of three
+    independent smoothed fields scaled to rms |v| = mach * sqrt(gamma p0)."""
+    N = (nrb[0] * n[0], nrb[1] * n[1], nrb[2] * n[2])
+    g = _smoothed_field(N, seed, 0)
+    rho = np.exp(sigma_ln * g - 0.5 * sigma_ln * sigma_ln)
+    del g
+    scale = mach * np.sqrt(gamma * p0) / np.sqrt(3.0)
+    vel = [scale * _smoothed_field(N, seed, 1 + d) for d in range(3)]
+    fields = _to_conserved(rho, vel[0], vel[1], vel[2], p0 * np.ones_like(rho), gamma)
+    del vel, rho
+    return _scatter(fields, leaves, n)
+
+
+def blast(leaves, n, nrb, p_in=100.0, p_out=0.1, r=0.1, rho0=1.0, center=(0.5, 0.5, 0.5),
+          gamma=5.0 / 3.0, xmin=(0, 0, 0), xmax=(1, 1, 1)):
+    """Spherical blast: uniform density at rest, pressure p_in where the cell
+    centre lies within r of the centre, else p_out."""
+    U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    for b, lf in enumerate(leaves):
+        x, y, z = cell_centers(lf, n, nrb, xmin, xmax)
+        d2 = (x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2
+        p = np.where(d2 < r * r, p_in, p_out)
+        U[b] = _to_conserved(rho0 + 0 * x, 0 * x, 0 * x, 0 * x, p, gamma)
+    return U
+
+
+def smooth_density(leaves, n, nrb, seed=5, amp=1e-3, kmax=4, rho0=1.0, p0=0.6,
+                   gamma=5.0 / 3.0):
+    """rho = rho0 + delta, delta a sum of Fourier modes 1 <= |k|_inf <= kmax
+    with N(0,1) cosine and sine coefficients (keyed by mode index), rescaled
+    to max |delta| = amp on the cells given; gas at rest, pressure p0."""
+    ks = [(kx, ky, kz) for kz in range(-kmax, kmax + 1) for ky in range(-kmax, kmax + 1)
+          for kx in range(-kmax, kmax + 1) if 1 <= max(abs(kx), abs(ky), abs(kz))]
+    coef = normals(seed, 0, np.arange(2 * len(ks), dtype=np.uint64)).reshape(len(ks), 2)
+    deltas = []
+    for lf in leaves:
+        x, y, z = cell_centers(lf, n, nrb)
+        dl = np.zeros_like(x)
+        for (kx, ky, kz), (a, bcoef) in zip(ks, coef):
+            ph = 2.0 * np.pi * (kx * x + ky * y + kz * z)
+            dl += a * np.cos(ph) + bcoef * np.sin(ph)
+        deltas.append(dl)
+    mx = max(np.abs(d).max() for d in deltas)
+    U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    for b, dl in enumerate(deltas):
+        rho = rho0 + amp * dl / mx
+        U[b] = _to_conserved(rho, 0 * rho, 0 * rho, 0 * rho, p0 + 0 * rho, gamma)
+    return U

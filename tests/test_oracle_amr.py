@@ -1,0 +1,255 @@
+"""Pins of the oracle's multilevel pieces: tiling and 2:1 validation, ghost
+values by copy / restriction / prolongation, flux correction, regridding.
+CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleError, OracleMesh
+from paper_2202_12309_amd import inputs
+
+N8 = (8, 8, 8)
+NRB4 = (4, 4, 4)
+
+
+def _amr_mesh(max_level=1, **kw):
+    leaves = inputs.sphere_refined_leaves(NRB4, radius=0.2)
+    return OracleMesh(N8, NRB4, leaves, max_level=max_level, **kw)
+
+
+def test_sphere_refinement_counts():
+    # 8^3 root blocks, the central 4^3 refined: 960 leaves of which 512 fine
+    lv = inputs.sphere_refined_leaves((8, 8, 8))
+    assert len(lv) == 960 and (lv[:, 0] == 1).sum() == 512
+    m = _amr_mesh()
+    assert m.nleaves == 56 + 64
+
+
+def test_invalid_tilings_rejected():
+    nrb = (2, 2, 2)
+    lv = inputs.uniform_leaves(nrb).tolist()
+    with pytest.raises(OracleError):  # gap
+        OracleMesh(N8, nrb, lv[:-1])
+    with pytest.raises(OracleError):  # overlap: a block and its child
+        OracleMesh(N8, nrb, lv + [[1, 0, 0, 0]], max_level=1)
+    # root block (0,0,0) refined once and its child at the high corner once
+    # more: those level-2 blocks touch the level-0 roots across x = 1/2
+    lv2 = [l for l in lv if l != [0, 0, 0, 0]]
+    for c in range(8):
+        ch = [1, c & 1, (c >> 1) & 1, (c >> 2) & 1]
+        if ch == [1, 1, 1, 1]:
+            for g in range(8):
+                lv2.append([2, 2 + (g & 1), 2 + ((g >> 1) & 1), 2 + ((g >> 2) & 1)])
+        else:
+            lv2.append(ch)
+    with pytest.raises(OracleError):
+        OracleMesh(N8, nrb, lv2, max_level=2)
+    # the same two-level refinement is valid once every root is refined once
+    lv3 = [[1, x, y, z] for z in range(4) for y in range(4) for x in range(4) if (x, y, z) != (1, 1, 1)]
+    lv3 += [[2, 2 + (g & 1), 2 + ((g >> 1) & 1), 2 + ((g >> 2) & 1)] for g in range(8)]
+    OracleMesh(N8, nrb, lv3, max_level=2)
+
+
+def test_uniform_preserved_bitwise_on_two_levels():
+    m = _amr_mesh()
+    U0 = inputs.uniform_state(m.leaves(), N8, rho=1.37, v=(0.31, -0.52, 0.11), p=0.83)
+    m.set_state(U0)
+    m.step(3)
+    assert np.array_equal(m.state(), U0)
+
+
+def test_ghosts_reproduce_linear_field():
+    """A field linear in x, sampled at cell centres on every level, restricts
+    to the coarse centres and prolongates to the fine centres exactly (up to
+    rounding): every ghost away from the periodic wrap equals the field at
+    its centre, whichever of copy / restriction / prolongation filled it."""
+    m = _amr_mesh()
+    lv = m.leaves()
+    a, b = 2.0, 0.75
+    U = np.empty(m.shape())
+    for k, lf in enumerate(lv):
+        x, _, _ = inputs.cell_centers(lf, N8, NRB4)
+        U[k] = (a + b * x)[None] * np.array([1.0, 0.3, -0.2, 0.1, 5.0])[:, None, None, None]
+    m.set_state(U)
+    checked = 0
+    kinds = set()
+    for k, lf in enumerate(lv):
+        P = m.padded(k)
+        lev = lf[0]
+        h = 1.0 / (NRB4[0] * N8[0] * (1 << lev))
+        xs = (lf[1] * N8[0] + np.arange(-2, N8[0] + 2) + 0.5) * h
+        want = (a + b * xs)[None, None, None, :] * np.array([1.0, 0.3, -0.2, 0.1, 5.0])[:, None, None, None]
+        ok = (xs > 0) & (xs < 1)
+        err = np.abs(P[..., ok] - np.broadcast_to(want, P.shape)[..., ok]).max()
+        assert err <= 1e-13, (k, lf, err)
+        checked += 1
+        kinds.add(int(lev))
+    assert checked == len(lv) and kinds == {0, 1}
+
+
+def test_prolongation_and_restriction_not_trivial():
+    """On non-linear data the coarse ghosts of a fine block differ from plain
+    injection (slopes are used) and the fine ghosts of a coarse block are the
+    8-cell means."""
+    m = _amr_mesh()
+    lv = m.leaves()
+    U = np.empty(m.shape())
+    for k, lf in enumerate(lv):
+        x, y, z = inputs.cell_centers(lf, N8, NRB4)
+        f = 1.0 + 0.1 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.05 * z * z
+        U[k] = f[None]
+    m.set_state(U)
+    # a coarse block face-adjacent to the refined region (which spans blocks 1..2)
+    kc = [k for k, lf in enumerate(lv) if tuple(lf) == (0, 0, 1, 1)][0]
+    P = m.padded(kc)
+    # its x-high ghosts lie in fine blocks (level 1, lx = 2)
+    fine = {tuple(lf): k for k, lf in enumerate(lv)}
+    for jj in range(8):
+        for kk in range(8):
+            for gi in range(2):
+                gx, gy, gz = 8 + gi, jj, kk  # ghost cell in coarse block coords
+                X = 0 * 8 + gx  # coarse global cell index (block lx = 0)
+                Y, Z = 8 + gy, 8 + gz
+                fx, fy, fz = 2 * X, 2 * Y, 2 * Z
+                kf = fine[(1, fx // 8, fy // 8, fz // 8)]
+                blk = U[kf, 0, fz % 8:fz % 8 + 2, fy % 8:fy % 8 + 2, fx % 8:fx % 8 + 2]
+                assert abs(P[0, gz + 2, gy + 2, gx + 2] - blk.mean()) <= 1e-15
+    # a fine block's coarse-side ghost is not the injected coarse value
+    kf = [k for k, lf in enumerate(lv) if tuple(lf) == (1, 2, 3, 3)][0]
+    P = m.padded(kf)
+    kcoarse = [k for k, lf in enumerate(lv) if tuple(lf) == (0, 0, 1, 1)][0]
+    inj = U[kcoarse, 0, 7, 7, 7]
+    assert abs(P[0, 2 + 7, 2 + 7, 1] - inj) > 1e-6
+
+
+@pytest.mark.parametrize("ic", ["turbulent", "blast"])
+def test_amr_conservation(ic):
+    m = _amr_mesh()
+    lv = m.leaves()
+    if ic == "blast":
+        U0 = inputs.blast(lv, N8, NRB4)
+    else:
+        U0 = np.empty(m.shape())
+        for k, lf in enumerate(lv):
+            x, y, z = inputs.cell_centers(lf, N8, NRB4)
+            rho = 1.0 + 0.3 * np.sin(2 * np.pi * x) * np.sin(4 * np.pi * y + 0.3) * np.cos(2 * np.pi * z)
+            vx = 0.4 * np.cos(2 * np.pi * y)
+            vy = -0.3 * np.sin(2 * np.pi * z)
+            vz = 0.2 * np.sin(2 * np.pi * x)
+            p = 1.0 + 0.2 * np.cos(2 * np.pi * (x + y))
+            U0[k] = [rho, rho * vx, rho * vy, rho * vz, p / (2 / 3) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)]
+    m.set_state(U0)
+    T0, A0 = m.totals()
+    m.step(10)
+    T1, A1 = m.totals()
+    A = np.maximum(A0, A1)  # momentum of the blast starts at exactly zero
+    assert np.all(np.abs(T1 - T0) <= 1e-14 * A * 10), np.abs(T1 - T0) / A
+
+
+def test_amr_wave_error_bracketed():
+    """A sound wave through a two-level mesh: its error after a quarter
+    period lies between the all-fine error and the all-coarse error at the
+    same timestep (all levels share the fine level's dt, which makes the
+    coarse cells run at half the Courant number)."""
+    T = 0.25
+
+    def run(leaves, max_level, cfl=0.3):
+        m = OracleMesh(N8, NRB4, leaves, max_level=max_level, cfl=cfl)
+        U0 = inputs.sound_wave(m.leaves(), N8, NRB4, amp=1e-6, noise=0.0)
+        m.set_state(U0)
+        while m.time()[0] < T:
+            m.step(1, T)
+        U = m.state()
+        err, vol = 0.0, 0.0
+        for k, lf in enumerate(m.leaves()):
+            x, _, _ = inputs.cell_centers(lf, N8, NRB4)
+            dV = (1.0 / (32 << int(lf[0]))) ** 3
+            exact = 1.0 + 1e-6 * np.sin(2 * np.pi * (x - T))
+            err += np.abs(U[k, 0] - exact).sum() * dV
+            vol += x.size * dV
+        assert abs(vol - 1.0) < 1e-12
+        return err
+    e_c = run(inputs.uniform_leaves(NRB4), 0, cfl=0.15)
+    e_f = run([(1, x, y, z) for z in range(8) for y in range(8) for x in range(8)], 1)
+    e_m = run(inputs.sphere_refined_leaves(NRB4, radius=0.2), 1)
+    assert e_f < e_m < e_c, (e_f, e_m, e_c)
+
+
+def test_regrid_round_trip_is_identity():
+    nrb = (2, 2, 2)
+    m = OracleMesh(N8, nrb, inputs.uniform_leaves(nrb), max_level=1)
+    U0 = inputs.turbulent_box(m.leaves(), N8, nrb, seed=9)
+    m.set_state(U0)
+    T0, A0 = m.totals()
+    m.regrid(np.ones(m.nleaves, dtype=np.int8))
+    assert m.nleaves == 64 and set(m.leaves()[:, 0]) == {1}
+    T1, _ = m.totals()
+    assert np.all(np.abs(T1 - T0) <= 1e-15 * A0)
+    m.regrid(-np.ones(m.nleaves, dtype=np.int8))
+    assert m.nleaves == 8
+    np.testing.assert_array_equal(m.leaves(), OracleMesh(N8, nrb, inputs.uniform_leaves(nrb)).leaves())
+    U1 = m.state()
+    assert np.abs(U1 - U0).max() <= 4 * np.finfo(float).eps * np.abs(U0).max()
+    # the other order is not an identity on non-linear data
+    m.regrid(np.ones(m.nleaves, dtype=np.int8))
+    Uf = m.state().copy()
+    m.regrid(-np.ones(m.nleaves, dtype=np.int8))
+    m.regrid(np.ones(m.nleaves, dtype=np.int8))
+    assert np.allclose(m.state(), Uf, rtol=1e-12)  # R(P(.)) = id on the coarse data
+    m2 = OracleMesh(N8, nrb, [(1, x, y, z) for z in range(4) for y in range(4) for x in range(4)],
+                    max_level=1)
+    # leaves at level 1 of a 2-block root grid = a 4-block level-0 grid
+    as_root = [(0, x, y, z) for _, x, y, z in m2.leaves()]
+    Ufine = inputs.turbulent_box(as_root, N8, (4, 4, 4), seed=9)
+    m2.set_state(Ufine)
+    m2.regrid(-np.ones(m2.nleaves, dtype=np.int8))
+    m2.regrid(np.ones(m2.nleaves, dtype=np.int8))
+    assert np.abs(m2.state() - Ufine).max() > 1e-3  # P(R(f)) != f
+
+
+def test_regrid_enforces_balance():
+    """Refining a fine block at the edge of the refined region to level 2
+    forces its coarse neighbours to level 1."""
+    m = _amr_mesh(max_level=2)
+    lv = m.leaves()
+    flags = np.zeros(len(lv), dtype=np.int8)
+    target = [k for k, lf in enumerate(lv) if tuple(lf) == (1, 2, 2, 2)][0]
+    flags[target] = 1
+    m.regrid(flags)
+    new = {tuple(l) for l in m.leaves()}
+    assert (2, 4, 4, 4) in new
+    # the level-0 block (0, 0, 0, 0) touches the corner of (1, 2, 2, 2) and must now be refined
+    assert (0, 0, 0, 0) not in new and (1, 1, 1, 1) in new
+    assert all(l[0] <= 2 for l in new)
+    # the mesh after regrid is a valid balanced tiling (re-creating it validates)
+    OracleMesh(N8, NRB4, m.leaves(), max_level=2)
+
+
+def test_derefine_rejected_when_unbalanced():
+    m = _amr_mesh(max_level=2)
+    lv = m.leaves()
+    flags = np.zeros(len(lv), dtype=np.int8)
+    # refine one fine block to level 2, derefine all fine blocks: the
+    # sibling group containing the refined block cannot merge, nor can any
+    # group touching the new level-2 blocks
+    target = [k for k, lf in enumerate(lv) if tuple(lf) == (1, 2, 2, 2)][0]
+    flags[lv[:, 0] == 1] = -1
+    flags[target] = 1
+    m.regrid(flags)
+    new = m.leaves()
+    assert (new[:, 0] == 2).sum() == 8
+    assert (new[:, 0] == 1).sum() > 0
+    OracleMesh(N8, NRB4, new, max_level=2)
+
+
+def test_regrid_conserves_totals():
+    m = _amr_mesh()
+    m.set_state(inputs.blast(m.leaves(), N8, NRB4))
+    m.step(3)
+    T0, A0 = m.totals()
+    lv = m.leaves()
+    flags = np.where(lv[:, 0] == 1, -1, 1).astype(np.int8)
+    m.regrid(flags)
+    T1, _ = m.totals()
+    assert np.all(np.abs(T1 - T0) <= 1e-14 * A0)
