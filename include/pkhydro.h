@@ -1,0 +1,190 @@
+/*
+ * pkhydro.h -- C-ABI of the MI355X (gfx950) hot path of Parthenon-hydro's
+ * block-AMR Euler cycle.
+ *
+ * The problem statement these calls follow (Parthenon, arXiv:2202.12309):
+ *   - Sec. 2.1: the domain is tiled by same-size MeshBlocks that are the
+ *     leaves of an oct-tree; each leaf has a refinement level and a logical
+ *     location; every point of the domain lies in exactly one leaf; blocks
+ *     may be split into 8 children or 8 siblings merged, and the tree is
+ *     rebuilt when that happens.
+ *   - Sec. 3.1/3.6: block data lives in device memory; one kernel covers all
+ *     blocks of a pack.
+ *   - Sec. 3.7: ghost zones are filled from neighbouring blocks (copy at the
+ *     same level, restriction from finer, prolongation from coarser) and
+ *     fluxes are corrected at fine-coarse faces.
+ *   - Sec. 3.8: derefinement is only applied periodically.
+ *   - Sec. 3.10: global reductions (CFL timestep, sums).
+ *   - Sec. 4.1: the update is a two-stage second-order finite-volume scheme
+ *     with piecewise-linear reconstruction and the HLLE Riemann solver.
+ *
+ * Conventions for every call:
+ *   - Return value: PKH_OK (0) or a negative PKH_E* code; the message of the
+ *     last failure on the calling thread is returned by pkh_last_error().
+ *   - Unphysical states (rho <= 0, P <= 0 or non-finite values) are latched
+ *     by the kernels in a device word and reported as PKH_EPHYS by the next
+ *     call that synchronises (download, totals, get_time, sync). The latch is
+ *     cleared by pkh_state_upload.
+ *   - A mesh handle is not thread-safe. All device work is enqueued on the
+ *     handle's HIP stream, in call order; calls that return host data
+ *     synchronise that stream.
+ *   - The library owns the device arrays it allocates; the caller owns every
+ *     host array and every device pointer it passes in.
+ *   - State layout ("upload layout"): conserved variables
+ *     (rho, M1, M2, M3, E), double precision, [nblocks][5][n3][n2][n1] with
+ *     x (index 1) fastest, active cells only, blocks in storage order
+ *     (pkh_mesh_blocks).
+ */
+#ifndef PKHYDRO_H
+#define PKHYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pkh_status {
+  PKH_OK = 0,
+  PKH_EINVAL = -1,   /* bad argument or configuration */
+  PKH_ETILING = -2,  /* leaves overlap or leave a gap */
+  PKH_EBALANCE = -3, /* neighbouring leaves differ by more than one level */
+  PKH_ENOMEM = -4,   /* device allocation failed */
+  PKH_EHIP = -5,     /* a HIP runtime call failed */
+  PKH_EPHYS = -6,    /* unphysical state latched by a kernel */
+  PKH_ESTATE = -7    /* call not valid in the handle's current state */
+};
+
+enum { PKH_BC_PERIODIC = 0 };
+enum { PKH_RECON_DC = 0, PKH_RECON_PLM = 1 };
+enum { PKH_LIMITER_MC = 0 };
+/* pkh_config.flags */
+enum { PKH_FLAG_GRAPH = 1u /* replay captured cycles with hipGraphs */ };
+
+/* Mesh configuration.
+ *   nroot[d]   level-0 cells along d; a multiple of nblock[d].
+ *   nblock[d]  cells per block along d (same for every block, Sec. 2.1).
+ *              nblock[0] is 8, 16, 32 or 64; nblock[1], nblock[2] are
+ *              multiples of the kernel's row tile (8 for nblock[0] <= 32,
+ *              4 for 64) and at least 4; with max_level > 0 every nblock[d]
+ *              is at least 8.
+ *   nghost     must be 2 (PLM needs two cells on each side of a face).
+ *   max_level  deepest refinement level (0..7).
+ *   xmin/xmax  domain extent; gamma the ideal-gas ratio; cfl the Courant
+ *              number of the timestep.
+ *   bc[6]      boundary kind per face (x-, x+, y-, y+, z-, z+); only
+ *              PKH_BC_PERIODIC is accepted.
+ *   stage1_recon PKH_RECON_DC (predictor-corrector, default) or PKH_RECON_PLM.
+ *   limiter    PKH_LIMITER_MC.
+ *   regrid_every  informational: the caller's derefinement cadence.
+ *   flags      PKH_FLAG_* bits. */
+typedef struct {
+  int32_t nroot[3];
+  int32_t nblock[3];
+  int32_t nghost;
+  int32_t max_level;
+  double xmin[3];
+  double xmax[3];
+  double gamma;
+  double cfl;
+  int32_t bc[6];
+  int32_t stage1_recon;
+  int32_t limiter;
+  int32_t regrid_every;
+  uint32_t flags;
+} pkh_config;
+
+/* Logical location of a leaf (Sec. 2.1): its level and its block
+   coordinates at that level, 0 <= lx_d < (nroot[d]/nblock[d]) << level. */
+typedef struct {
+  int32_t level, lx1, lx2, lx3;
+} pkh_loc;
+
+/* Device-memory callbacks. alloc returns device memory of at least `bytes`
+   usable on `stream` (NULL on failure); free releases it. Pass NULL for both
+   to use hipMalloc / hipFree. */
+typedef void *(*pkh_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*pkh_free_fn)(void *ptr, void *stream, void *ctx);
+
+typedef struct pkh_mesh pkh_mesh;
+
+/* Create a mesh from a leaf list (Sec. 2.1). Validates that the leaves tile
+   the domain exactly once (PKH_ETILING) and that leaves touching across a
+   face, edge or corner differ by at most one level (PKH_EBALANCE). Leaves
+   are stored in Morton (Z) order of their deepest-level corner; read the
+   order back with pkh_mesh_blocks. `hip_stream` (a hipStream_t, may be NULL
+   for the null stream) receives all of the handle's work. The state is
+   zero until uploaded. */
+int pkh_mesh_create(const pkh_config *cfg, const pkh_loc *blocks, int64_t nblocks,
+                    void *hip_stream, pkh_alloc_fn alloc, pkh_free_fn free_fn,
+                    void *alloc_ctx, pkh_mesh **out);
+
+/* Synchronise the stream and release every device array of the handle. */
+int pkh_mesh_destroy(pkh_mesh *mesh);
+
+/* Current leaves in storage order. Writes min(cap, count) entries to out
+   (out may be NULL when cap is 0) and the count to *n. */
+int pkh_mesh_blocks(const pkh_mesh *mesh, pkh_loc *out, int64_t cap, int64_t *n);
+
+/* Copy a state in the upload layout into the mesh (asynchronous on the
+   stream when src is device memory; a host src is staged and the call
+   returns after the copy is enqueued and the host buffer is consumed).
+   Marks ghosts and the timestep stale; they are recomputed by
+   pkh_exchange_boundaries or at the start of pkh_step. */
+int pkh_state_upload(pkh_mesh *mesh, const double *src, int32_t src_on_device);
+
+/* Copy the active state out in the upload layout; synchronises. */
+int pkh_state_download(pkh_mesh *mesh, double *dst, int32_t dst_on_device);
+
+/* Fill every ghost zone from the leaves' active data (Sec. 3.7: copy,
+   restriction, prolongation, all 26 neighbour regions, periodic wrap) and
+   recompute the CFL timestep from the active data (Sec. 3.10). */
+int pkh_exchange_boundaries(pkh_mesh *mesh);
+
+/* Advance n_cycles full cycles (Sec. 4.1). Each cycle:
+     dt  = CFL timestep of the current state, clamped to t_end - t when
+           t_end is finite;
+     U*  = U^n - dt/2 D(U^n)   (donor-cell or PLM faces, HLLE fluxes);
+     ghost fill of U*, with fine-coarse flux correction on multilevel meshes;
+     U^{n+1} = U^n - dt D_PLM(U*) (MC-limited PLM on primitives, HLLE);
+     ghost fill of U^{n+1}; t += dt; the next dt is reduced on the device.
+   No host synchronisation. With PKH_FLAG_GRAPH the cycles are replayed
+   from a captured hipGraph. */
+int pkh_step(pkh_mesh *mesh, int32_t n_cycles, double t_end);
+
+/* Simulation time, the CFL timestep the next cycle will use (before any
+   t_end clamp) and the cycle count; synchronises. */
+int pkh_get_time(pkh_mesh *mesh, double *t, double *dt, int64_t *cycle);
+/* Set time and cycle (resume); the timestep is recomputed at the next step. */
+int pkh_set_time(pkh_mesh *mesh, double t, int64_t cycle);
+
+/* Per-leaf refinement flags in storage order: -1 derefine, 0 keep,
+   +1 refine (Sec. 2.1, Sec. 3.8). Applied by pkh_regrid. */
+int pkh_set_refinement_flags(pkh_mesh *mesh, const int8_t *flags, int64_t n);
+
+/* Apply the flags: +1 splits a leaf below max_level into 8 children; a
+   refinement that would break 2:1 also refines the touching coarser
+   leaves, to a fixed point; 8 siblings all flagged -1 (none refining) merge
+   when the merged block keeps 2:1. New children get the prolongation of
+   the composite field at the parent's level, a merged parent the
+   restriction of its children. The tree and all tables are rebuilt on the
+   host, the data moved on the device, ghosts and the timestep recomputed.
+   Flags are cleared. Synchronises. */
+int pkh_regrid(pkh_mesh *mesh);
+
+/* Conserved totals sum_leaves sum_active U_v dV (Sec. 3.10 reduction);
+   fixed-order device reduction; synchronises. out[5]. */
+int pkh_conserved_totals(pkh_mesh *mesh, double out[5]);
+
+/* Wait for the handle's stream and report any latched PKH_EPHYS. */
+int pkh_sync(pkh_mesh *mesh);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *pkh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PKHYDRO_H */

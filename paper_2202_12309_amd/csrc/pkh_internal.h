@@ -1,0 +1,109 @@
+// pkh_internal.h -- types shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pkh {
+
+constexpr int NV = 5;  // rho, M1, M2, M3, E
+constexpr int NG = 2;  // ghost width (PLM needs two cells beside a face)
+
+// Face slots of a block: 2*d + s, d = 0 (x), 1 (y), 2 (z); s = 0 low, 1 high.
+enum : int { XLO = 0, XHI = 1, YLO = 2, YHI = 3, ZLO = 4, ZHI = 5 };
+
+// Per-leaf data the kernels read.
+struct BlockInfo {
+  int32_t level, lx, ly, lz;
+  double idx[3];        // 1 / dx_d at the leaf's level
+  // Face-buffer slot (in units of one face of n_t1 x n_t2 x 5 doubles) where
+  // the stage kernels store this leaf's fluxes on each face; -1 where the
+  // face is not a fine-coarse face.
+  int32_t fslot[6];
+  // bit f set: face f borders finer leaves (this leaf's flux there is
+  // replaced by the restricted fine flux after each stage).
+  int32_t finer_mask;
+};
+
+// Device-resident clock of a mesh; only kernels write it during a step.
+struct DevTime {
+  double t;            // simulation time
+  double dt;           // timestep of the current cycle (after the t_end clamp)
+  double dt_next;      // CFL timestep of the current state (before the clamp)
+  double cfl;
+  unsigned long long smax_bits;  // running max of (|v_d| + c) / dx_d, as bits of a
+                                 // non-negative double (ordered like integers)
+  long long cycle;
+  int err;             // latched PKH_EPHYS (1) / table error (2)
+  int pad;
+};
+
+// Level maps: dense arrays, one per level, block location -> leaf id or -1.
+struct LevelMaps {
+  const int32_t* map;   // concatenated
+  int64_t off[9];       // start of each level
+  int32_t nb[9][3];     // blocks per dim at each level
+  int32_t maxl;
+};
+
+// Geometry every kernel needs.
+struct Geom {
+  int32_t n1, n2, n3;   // active cells per block
+  int32_t p1, p2, p3;   // padded extents (n + 4)
+  int64_t vstride;      // doubles per variable of one padded block
+  int64_t bstride;      // doubles per padded block (5 * vstride)
+  int32_t nrb[3];       // level-0 blocks per dim
+  double gamma;
+};
+
+// Coarse-face correction record: one per (coarse leaf, face bordering finer).
+struct FineFace {
+  int32_t block;        // coarse leaf id
+  int32_t face;         // face slot 0..5
+  int32_t own_slot;     // face-buffer slot holding the coarse leaf's flux
+  int32_t fine_slot[4]; // face-buffer slots of the 4 fine leaves, quadrant (h1 + 2*h2)
+};
+
+// ---- launch wrappers (defined in pkh_kernels.hip) ----
+struct StageLaunch {
+  const double* uin;
+  const double* ubase;
+  double* uout;
+  const BlockInfo* blocks;
+  int32_t nblocks;
+  Geom g;
+  DevTime* tm;
+  double beta;
+  int32_t recon;      // 0 DC, 1 PLM
+  int32_t do_dt;      // accumulate the CFL reduction from the updated state
+  double* fbuf;       // face buffers (may be null on single-level meshes)
+  int32_t tj;         // rows per tile (0: default)
+};
+
+hipError_t launch_stage(const StageLaunch& a, hipStream_t s);
+hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                       const LevelMaps& maps, DevTime* tm, hipStream_t s);
+hipError_t launch_flux_correct(double* u, const BlockInfo* blocks, const FineFace* ff,
+                               const int32_t* ff_first, const int32_t* cblocks, int32_t ncblocks,
+                               const Geom& g, DevTime* tm, double beta, int32_t do_dt,
+                               const double* fbuf, hipStream_t s);
+hipError_t launch_dt(const double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                     DevTime* tm, hipStream_t s);
+hipError_t launch_clock(DevTime* tm, int32_t mode, double t_end, hipStream_t s);
+hipError_t launch_scatter(double* u, const double* src, int32_t nblocks, const Geom& g,
+                          hipStream_t s);
+hipError_t launch_gather(double* dst, const double* u, int32_t nblocks, const Geom& g,
+                         hipStream_t s);
+hipError_t launch_totals(double* partial, double* out, const double* u, const BlockInfo* blocks,
+                         int32_t nblocks, const Geom& g, hipStream_t s);
+// Regrid: new leaf r takes kind[r] (0 copy, 1 child of a refined leaf,
+// 2 merged parent) from old leaf src[r].
+hipError_t launch_regrid_data(double* unew, const BlockInfo* bnew, const int32_t* kind,
+                              const int32_t* src, int32_t nnew, const double* uold,
+                              const BlockInfo* bold, const LevelMaps& old_maps, const Geom& g,
+                              DevTime* tm, hipStream_t s);
+
+// Clock modes
+enum : int { CLOCK_END = 1, CLOCK_BEGIN = 2, CLOCK_FROM_SMAX = 4 };
+
+}  // namespace pkh

@@ -1,0 +1,803 @@
+// pkh_mesh.cpp -- host runtime behind the C-ABI of include/pkhydro.h.
+//
+// Owns the leaf list (Parthenon Sec. 2.1: same-size blocks, leaves of an
+// oct-tree, Morton order), validates tilings and 2:1 balance, builds the
+// device tables the kernels read (leaf info, per-level location maps,
+// fine-coarse face records), manages device memory through the caller's
+// callbacks, and enqueues the per-cycle kernel sequence on the handle's
+// stream. No host synchronisation happens inside pkh_step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pkhydro.h"
+#include "pkh_internal.h"
+
+using namespace pkh;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PKH_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+  } while (0)
+
+constexpr int MAXL = 7;
+
+int64_t wrapl(int64_t a, int64_t n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+uint64_t spread_bits(uint64_t x) {
+  uint64_t r = 0;
+  for (int b = 0; b < 21; ++b) r |= ((x >> b) & 1ull) << (3 * b);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Leaf set with per-level dense location maps.
+// ---------------------------------------------------------------------------
+struct Tree {
+  int32_t nrb[3] = {1, 1, 1};
+  int32_t maxl = 0;
+  std::vector<pkh_loc> leaves;
+  std::vector<std::vector<int32_t>> map;  // per level
+
+  int64_t nbd(int L, int d) const { return (int64_t)nrb[d] << L; }
+
+  int32_t at(int L, int64_t x, int64_t y, int64_t z) const {
+    if (L < 0 || L > maxl) return -1;
+    x = wrapl(x, nbd(L, 0));
+    y = wrapl(y, nbd(L, 1));
+    z = wrapl(z, nbd(L, 2));
+    return map[L][(z * nbd(L, 1) + y) * nbd(L, 0) + x];
+  }
+  // Leaf at a coarser level containing block (x,y,z) of level L.
+  int32_t coarser(int L, int64_t x, int64_t y, int64_t z, int* lc) const {
+    x = wrapl(x, nbd(L, 0));
+    y = wrapl(y, nbd(L, 1));
+    z = wrapl(z, nbd(L, 2));
+    for (int c = L - 1; c >= 0; --c) {
+      int s = L - c;
+      int32_t id = at(c, x >> s, y >> s, z >> s);
+      if (id >= 0) {
+        *lc = c;
+        return id;
+      }
+    }
+    return -1;
+  }
+
+  uint64_t key(const pkh_loc& l) const {
+    int s = maxl - l.level;
+    return spread_bits((uint64_t)l.lx1 << s) | (spread_bits((uint64_t)l.lx2 << s) << 1) |
+           (spread_bits((uint64_t)l.lx3 << s) << 2);
+  }
+
+  void sort_morton() {
+    std::stable_sort(leaves.begin(), leaves.end(), [&](const pkh_loc& a, const pkh_loc& b) {
+      uint64_t ka = key(a), kb = key(b);
+      return ka != kb ? ka < kb : a.level < b.level;
+    });
+  }
+
+  // Build the maps; check exact tiling and 2:1 balance over all 26
+  // neighbour directions.
+  int build() {
+    map.assign(maxl + 1, {});
+    for (int L = 0; L <= maxl; ++L) map[L].assign(nbd(L, 0) * nbd(L, 1) * nbd(L, 2), -1);
+    const int64_t f0 = nbd(maxl, 0), f1 = nbd(maxl, 1), f2 = nbd(maxl, 2);
+    std::vector<uint8_t> occ(f0 * f1 * f2, 0);
+    for (size_t b = 0; b < leaves.size(); ++b) {
+      const pkh_loc& l = leaves[b];
+      if (l.level < 0 || l.level > maxl)
+        return fail(PKH_EINVAL, "leaf %zu: level %d outside [0, %d]", b, l.level, maxl);
+      const int64_t c[3] = {l.lx1, l.lx2, l.lx3};
+      for (int d = 0; d < 3; ++d)
+        if (c[d] < 0 || c[d] >= nbd(l.level, d))
+          return fail(PKH_EINVAL, "leaf %zu: location out of range", b);
+      map[l.level][(c[2] * nbd(l.level, 1) + c[1]) * nbd(l.level, 0) + c[0]] = (int32_t)b;
+      const int s = maxl - l.level;
+      for (int64_t z = c[2] << s; z < (c[2] + 1) << s; ++z)
+        for (int64_t y = c[1] << s; y < (c[1] + 1) << s; ++y)
+          for (int64_t x = c[0] << s; x < (c[0] + 1) << s; ++x) {
+            uint8_t& o = occ[(z * f1 + y) * f0 + x];
+            if (o) return fail(PKH_ETILING, "leaf %zu overlaps another leaf", b);
+            o = 1;
+          }
+    }
+    for (uint8_t o : occ)
+      if (!o) return fail(PKH_ETILING, "the leaves leave part of the domain uncovered");
+    for (size_t b = 0; b < leaves.size(); ++b) {
+      const pkh_loc& l = leaves[b];
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (!dx && !dy && !dz) continue;
+            const int64_t x = l.lx1 + dx, y = l.lx2 + dy, z = l.lx3 + dz;
+            if (at(l.level, x, y, z) >= 0) continue;
+            int lc;
+            if (coarser(l.level, x, y, z, &lc) >= 0) {
+              if (lc < l.level - 1) return fail(PKH_EBALANCE, "leaf %zu: coarser neighbour two levels up", b);
+              continue;
+            }
+            const int del[3] = {dx, dy, dz};
+            for (int ch = 0; ch < 8; ++ch) {
+              const int o[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
+              bool touch = true;
+              for (int e = 0; e < 3; ++e)
+                if ((del[e] < 0 && o[e] == 0) || (del[e] > 0 && o[e] == 1)) touch = false;
+              if (!touch) continue;
+              const int64_t w[3] = {wrapl(x, nbd(l.level, 0)), wrapl(y, nbd(l.level, 1)),
+                                    wrapl(z, nbd(l.level, 2))};
+              if (at(l.level + 1, 2 * w[0] + o[0], 2 * w[1] + o[1], 2 * w[2] + o[2]) < 0)
+                return fail(PKH_EBALANCE, "leaf %zu: finer neighbour two levels down", b);
+            }
+          }
+    }
+    return PKH_OK;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The mesh handle.
+// ---------------------------------------------------------------------------
+struct pkh_mesh {
+  pkh_config cfg{};
+  hipStream_t stream = nullptr;
+  pkh_alloc_fn af = nullptr;
+  pkh_free_fn ffn = nullptr;
+  void* actx = nullptr;
+  Tree tree;
+  Geom g{};
+  // device arrays
+  double* A = nullptr;  // U^n / U^{n+1} with ghosts
+  double* B = nullptr;  // U* with ghosts
+  BlockInfo* d_blocks = nullptr;
+  int32_t* d_map = nullptr;
+  LevelMaps maps{};
+  DevTime* d_time = nullptr;
+  double* d_fbuf = nullptr;
+  FineFace* d_ff = nullptr;
+  int32_t* d_ff_first = nullptr;
+  int32_t* d_cblocks = nullptr;
+  int32_t ncblocks = 0;
+  double* d_partial = nullptr;
+  double* d_tot = nullptr;
+  size_t partial_cap = 0;
+  std::vector<BlockInfo> h_blocks;
+  std::vector<int8_t> flags;
+  bool ghosts_valid = false;
+  int32_t tj = 0;
+  // captured cycles
+  hipGraphExec_t gexec = nullptr;
+  int32_t g_cycles = 0;
+  double g_tend = NAN;
+  bool g_valid = false;
+
+  int64_t nb() const { return (int64_t)tree.leaves.size(); }
+  size_t state_bytes() const { return (size_t)nb() * g.bstride * sizeof(double); }
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (af) return af(bytes, stream, actx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    if (ffn)
+      ffn(p, stream, actx);
+    else
+      (void)hipFree(p);
+  }
+};
+
+namespace {
+
+void drop_graph(pkh_mesh* m) {
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  m->gexec = nullptr;
+  m->g_valid = false;
+}
+
+void free_tables(pkh_mesh* m) {
+  m->dfree(m->d_blocks);
+  m->dfree(m->d_map);
+  m->dfree(m->d_fbuf);
+  m->dfree(m->d_ff);
+  m->dfree(m->d_ff_first);
+  m->dfree(m->d_cblocks);
+  m->d_blocks = nullptr;
+  m->d_map = nullptr;
+  m->d_fbuf = nullptr;
+  m->d_ff = nullptr;
+  m->d_ff_first = nullptr;
+  m->d_cblocks = nullptr;
+  m->ncblocks = 0;
+}
+
+template <class T>
+int upload_vec(pkh_mesh* m, T** dptr, const std::vector<T>& h) {
+  *dptr = (T*)m->dalloc(std::max<size_t>(h.size(), 1) * sizeof(T));
+  if (!*dptr) return fail(PKH_ENOMEM, "device allocation of %zu bytes failed", h.size() * sizeof(T));
+  if (!h.empty())
+    HIPCHK(hipMemcpyAsync(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, m->stream));
+  return PKH_OK;
+}
+
+// Build BlockInfo, level maps and fine-coarse face records for the current
+// leaf list, and upload them. The tree maps must be built.
+int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelMaps& lm) {
+  const Tree& t = m->tree;
+  const int64_t nb = m->nb();
+  hb.assign(nb, BlockInfo{});
+  for (int64_t b = 0; b < nb; ++b) {
+    const pkh_loc& l = t.leaves[b];
+    BlockInfo& bi = hb[b];
+    bi.level = l.level;
+    bi.lx = l.lx1;
+    bi.ly = l.lx2;
+    bi.lz = l.lx3;
+    for (int d = 0; d < 3; ++d) {
+      const double ncell = (double)((int64_t)m->cfg.nroot[d] << l.level);
+      bi.idx[d] = ncell / (m->cfg.xmax[d] - m->cfg.xmin[d]);
+    }
+    for (int f = 0; f < 6; ++f) bi.fslot[f] = -1;
+    bi.finer_mask = 0;
+  }
+  // fine-coarse faces: a coarse leaf's face borders finer leaves when the
+  // same-level neighbour location is neither a leaf nor inside a coarser one
+  std::vector<FineFace> ff;
+  std::vector<int32_t> ff_first, cblocks;
+  int32_t nslot = 0;
+  std::vector<std::array<int32_t, 6>> slot_of(nb);
+  for (auto& s : slot_of) s.fill(-1);
+  auto slot = [&](int64_t b, int f) {
+    if (slot_of[b][f] < 0) slot_of[b][f] = nslot++;
+    return slot_of[b][f];
+  };
+  for (int64_t b = 0; b < nb; ++b) {
+    const pkh_loc& l = t.leaves[b];
+    bool any = false;
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1, s = f & 1;
+      int64_t c[3] = {l.lx1, l.lx2, l.lx3};
+      c[d] += s ? 1 : -1;
+      for (int e = 0; e < 3; ++e) c[e] = wrapl(c[e], t.nbd(l.level, e));
+      if (t.at(l.level, c[0], c[1], c[2]) >= 0) continue;
+      int lc;
+      if (t.coarser(l.level, c[0], c[1], c[2], &lc) >= 0) continue;
+      // finer: the 4 children of c touching this face
+      FineFace rec{};
+      rec.block = (int32_t)b;
+      rec.face = f;
+      rec.own_slot = slot(b, f);
+      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      for (int h2 = 0; h2 < 2; ++h2)
+        for (int h1 = 0; h1 < 2; ++h1) {
+          int64_t ch[3];
+          ch[d] = 2 * c[d] + (s ? 0 : 1);
+          ch[t1] = 2 * c[t1] + h1;
+          ch[t2] = 2 * c[t2] + h2;
+          const int32_t fid = t.at(l.level + 1, ch[0], ch[1], ch[2]);
+          if (fid < 0) return fail(PKH_EBALANCE, "fine face without fine leaves");
+          rec.fine_slot[h1 + 2 * h2] = slot(fid, f ^ 1);
+        }
+      if (!any) {
+        ff_first.push_back((int32_t)ff.size());
+        cblocks.push_back((int32_t)b);
+        any = true;
+      }
+      hb[b].finer_mask |= 1 << f;
+      ff.push_back(rec);
+    }
+  }
+  ff_first.push_back((int32_t)ff.size());
+  for (int64_t b = 0; b < nb; ++b)
+    for (int f = 0; f < 6; ++f) hb[b].fslot[f] = slot_of[b][f];
+  // level maps
+  std::vector<int32_t> flat;
+  for (int L = 0; L <= t.maxl; ++L) {
+    lm.off[L] = (int64_t)flat.size();
+    for (int d = 0; d < 3; ++d) lm.nb[L][d] = (int32_t)t.nbd(L, d);
+    flat.insert(flat.end(), t.map[L].begin(), t.map[L].end());
+  }
+  lm.maxl = t.maxl;
+  int rc;
+  if ((rc = upload_vec(m, dmap, flat))) return rc;
+  lm.map = *dmap;
+  // per-mesh AMR tables (only the current mesh's are kept)
+  if (dmap == &m->d_map) {
+    if ((rc = upload_vec(m, &m->d_blocks, hb))) return rc;
+    const size_t fsz = (size_t)NV *
+                       std::max({m->g.n1 * m->g.n2, m->g.n1 * m->g.n3, m->g.n2 * m->g.n3});
+    m->d_fbuf = (double*)m->dalloc(std::max<size_t>(nslot, 1) * fsz * sizeof(double));
+    if (!m->d_fbuf) return fail(PKH_ENOMEM, "face buffer allocation failed");
+    if ((rc = upload_vec(m, &m->d_ff, ff))) return rc;
+    if ((rc = upload_vec(m, &m->d_ff_first, ff_first))) return rc;
+    if ((rc = upload_vec(m, &m->d_cblocks, cblocks))) return rc;
+    m->ncblocks = (int32_t)cblocks.size();
+  }
+  // the host vectors above are sources of asynchronous copies
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return PKH_OK;
+}
+
+int ensure_partials(pkh_mesh* m) {
+  const size_t need = (size_t)m->nb() * NV;
+  if (m->partial_cap >= need && m->d_partial) return PKH_OK;
+  m->dfree(m->d_partial);
+  m->d_partial = (double*)m->dalloc(need * sizeof(double));
+  if (!m->d_partial) return fail(PKH_ENOMEM, "partial-sum allocation failed");
+  m->partial_cap = need;
+  return PKH_OK;
+}
+
+int check_err(pkh_mesh* m) {
+  DevTime h;
+  HIPCHK(hipMemcpyAsync(&h, m->d_time, sizeof h, hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (h.err & 2) return fail(PKH_EBALANCE, "a ghost or regrid lookup found no covering leaf");
+  if (h.err & 1) return fail(PKH_EPHYS, "unphysical state (rho <= 0, P <= 0 or non-finite)");
+  return PKH_OK;
+}
+
+int do_exchange(pkh_mesh* m) {
+  HIPCHK(launch_fill(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->maps, m->d_time, m->stream));
+  HIPCHK(hipMemsetAsync(&m->d_time->smax_bits, 0, sizeof(unsigned long long), m->stream));
+  HIPCHK(launch_dt(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->d_time, m->stream));
+  HIPCHK(launch_clock(m->d_time, CLOCK_FROM_SMAX, NAN, m->stream));
+  m->ghosts_valid = true;
+  return PKH_OK;
+}
+
+// One cycle's kernels (the clock BEGIN of the cycle has been enqueued).
+int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end) {
+  const int32_t nb = (int32_t)m->nb();
+  StageLaunch s{};
+  s.blocks = m->d_blocks;
+  s.nblocks = nb;
+  s.g = m->g;
+  s.tm = m->d_time;
+  s.fbuf = m->d_fbuf;
+  s.tj = m->tj;
+  // predictor: U* = U^n - dt/2 D(U^n)
+  s.uin = m->A;
+  s.ubase = m->A;
+  s.uout = m->B;
+  s.beta = 0.5;
+  s.recon = m->cfg.stage1_recon;
+  s.do_dt = 0;
+  HIPCHK(launch_stage(s, m->stream));
+  HIPCHK(launch_flux_correct(m->B, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks, m->ncblocks,
+                             m->g, m->d_time, 0.5, 0, m->d_fbuf, m->stream));
+  HIPCHK(launch_fill(m->B, m->d_blocks, nb, m->g, m->maps, m->d_time, m->stream));
+  // corrector: U^{n+1} = U^n - dt D_PLM(U*), in place; CFL reduction fused
+  s.uin = m->B;
+  s.ubase = m->A;
+  s.uout = m->A;
+  s.beta = 1.0;
+  s.recon = PKH_RECON_PLM;
+  s.do_dt = 1;
+  HIPCHK(launch_stage(s, m->stream));
+  HIPCHK(launch_flux_correct(m->A, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks, m->ncblocks,
+                             m->g, m->d_time, 1.0, 1, m->d_fbuf, m->stream));
+  HIPCHK(launch_fill(m->A, m->d_blocks, nb, m->g, m->maps, m->d_time, m->stream));
+  HIPCHK(launch_clock(m->d_time, mode_after, t_end, m->stream));
+  return PKH_OK;
+}
+
+int check_config(const pkh_config* c) {
+  if (c->nghost != 2) return fail(PKH_EINVAL, "nghost must be 2");
+  if (c->max_level < 0 || c->max_level > MAXL) return fail(PKH_EINVAL, "max_level must be in [0, %d]", MAXL);
+  const int n1 = c->nblock[0];
+  if (n1 != 8 && n1 != 16 && n1 != 32 && n1 != 64)
+    return fail(PKH_EINVAL, "nblock[0] must be 8, 16, 32 or 64 (got %d)", n1);
+  const int tj = n1 == 64 ? 4 : 8;
+  for (int d = 0; d < 3; ++d) {
+    if (c->nblock[d] < 4 || c->nroot[d] % c->nblock[d])
+      return fail(PKH_EINVAL, "nroot[%d]=%d must be a multiple of nblock[%d]=%d >= 4", d, c->nroot[d], d,
+                  c->nblock[d]);
+    if (c->max_level > 0 && (c->nblock[d] < 8 || (c->nblock[d] & 1)))
+      return fail(PKH_EINVAL, "multilevel meshes need even nblock >= 8");
+    if (!(c->xmax[d] > c->xmin[d])) return fail(PKH_EINVAL, "xmax must exceed xmin");
+  }
+  if (c->nblock[1] % tj) return fail(PKH_EINVAL, "nblock[1] must be a multiple of %d", tj);
+  for (int f = 0; f < 6; ++f)
+    if (c->bc[f] != PKH_BC_PERIODIC) return fail(PKH_EINVAL, "only periodic boundaries are supported");
+  if (c->stage1_recon != PKH_RECON_DC && c->stage1_recon != PKH_RECON_PLM)
+    return fail(PKH_EINVAL, "stage1_recon must be PKH_RECON_DC or PKH_RECON_PLM");
+  if (c->limiter != PKH_LIMITER_MC) return fail(PKH_EINVAL, "only the MC limiter is supported");
+  if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return fail(PKH_EINVAL, "need gamma > 1 and cfl > 0");
+  return PKH_OK;
+}
+
+int alloc_state(pkh_mesh* m) {
+  m->A = (double*)m->dalloc(m->state_bytes());
+  m->B = (double*)m->dalloc(m->state_bytes());
+  if (!m->A || !m->B) return fail(PKH_ENOMEM, "state allocation of 2 x %zu bytes failed", m->state_bytes());
+  HIPCHK(hipMemsetAsync(m->A, 0, m->state_bytes(), m->stream));
+  HIPCHK(hipMemsetAsync(m->B, 0, m->state_bytes(), m->stream));
+  return PKH_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* pkh_last_error(void) { return g_err.c_str(); }
+
+int pkh_mesh_create(const pkh_config* cfg, const pkh_loc* blocks, int64_t nblocks, void* hip_stream,
+                    pkh_alloc_fn alloc, pkh_free_fn free_fn, void* alloc_ctx, pkh_mesh** out) {
+  g_err.clear();
+  if (!cfg || !blocks || !out || nblocks <= 0) return fail(PKH_EINVAL, "null argument or no blocks");
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return fail(PKH_EINVAL, "alloc and free go together");
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  pkh_mesh* m = new pkh_mesh();
+  m->cfg = *cfg;
+  m->stream = (hipStream_t)hip_stream;
+  m->af = alloc;
+  m->ffn = free_fn;
+  m->actx = alloc_ctx;
+  for (int d = 0; d < 3; ++d) m->tree.nrb[d] = cfg->nroot[d] / cfg->nblock[d];
+  m->tree.maxl = cfg->max_level;
+  m->tree.leaves.assign(blocks, blocks + nblocks);
+  m->tree.sort_morton();
+  if ((rc = m->tree.build())) {
+    delete m;
+    return rc;
+  }
+  Geom& g = m->g;
+  g.n1 = cfg->nblock[0];
+  g.n2 = cfg->nblock[1];
+  g.n3 = cfg->nblock[2];
+  g.p1 = g.n1 + 2 * NG;
+  g.p2 = g.n2 + 2 * NG;
+  g.p3 = g.n3 + 2 * NG;
+  g.vstride = (int64_t)g.p1 * g.p2 * g.p3;
+  g.bstride = NV * g.vstride;
+  for (int d = 0; d < 3; ++d) g.nrb[d] = m->tree.nrb[d];
+  g.gamma = cfg->gamma;
+  m->d_time = (DevTime*)m->dalloc(sizeof(DevTime));
+  if (!m->d_time) {
+    delete m;
+    return fail(PKH_ENOMEM, "allocation failed");
+  }
+  DevTime h{};
+  h.cfl = cfg->cfl;
+  if (hipMemcpyAsync(m->d_time, &h, sizeof h, hipMemcpyHostToDevice, m->stream) != hipSuccess ||
+      (rc = alloc_state(m)) || (rc = build_tables(m, m->h_blocks, &m->d_map, m->maps)) ||
+      (rc = ensure_partials(m))) {
+    if (!rc) rc = fail(PKH_EHIP, "device setup failed");
+    pkh_mesh_destroy(m);
+    return rc;
+  }
+  m->d_tot = (double*)m->dalloc(NV * sizeof(double));
+  if (!m->d_tot) {
+    pkh_mesh_destroy(m);
+    return fail(PKH_ENOMEM, "allocation failed");
+  }
+  m->flags.assign(m->nb(), 0);
+  if (hipStreamSynchronize(m->stream) != hipSuccess) {
+    pkh_mesh_destroy(m);
+    return fail(PKH_EHIP, "stream synchronisation failed");
+  }
+  *out = m;
+  return PKH_OK;
+}
+
+int pkh_mesh_destroy(pkh_mesh* m) {
+  if (!m) return PKH_OK;
+  (void)hipStreamSynchronize(m->stream);
+  drop_graph(m);
+  free_tables(m);
+  m->dfree(m->A);
+  m->dfree(m->B);
+  m->dfree(m->d_time);
+  m->dfree(m->d_partial);
+  m->dfree(m->d_tot);
+  delete m;
+  return PKH_OK;
+}
+
+int pkh_mesh_blocks(const pkh_mesh* m, pkh_loc* out, int64_t cap, int64_t* n) {
+  if (!m || !n || (cap > 0 && !out)) return fail(PKH_EINVAL, "null argument");
+  const int64_t nb = m->nb();
+  *n = nb;
+  std::copy(m->tree.leaves.begin(), m->tree.leaves.begin() + std::min(cap, nb), out);
+  return PKH_OK;
+}
+
+int pkh_state_upload(pkh_mesh* m, const double* src, int32_t src_on_device) {
+  if (!m || !src) return fail(PKH_EINVAL, "null argument");
+  const size_t bytes = (size_t)m->nb() * NV * m->g.n1 * m->g.n2 * m->g.n3 * sizeof(double);
+  const double* dsrc = src;
+  double* stage = nullptr;
+  if (!src_on_device) {
+    stage = (double*)m->dalloc(bytes);
+    if (!stage) return fail(PKH_ENOMEM, "staging allocation failed");
+    HIPCHK(hipMemcpyAsync(stage, src, bytes, hipMemcpyHostToDevice, m->stream));
+    dsrc = stage;
+  }
+  HIPCHK(launch_scatter(m->A, dsrc, (int32_t)m->nb(), m->g, m->stream));
+  HIPCHK(hipMemsetAsync(&m->d_time->err, 0, sizeof(int), m->stream));
+  if (stage) {
+    HIPCHK(hipStreamSynchronize(m->stream));
+    m->dfree(stage);
+  }
+  m->ghosts_valid = false;
+  return PKH_OK;
+}
+
+int pkh_state_download(pkh_mesh* m, double* dst, int32_t dst_on_device) {
+  if (!m || !dst) return fail(PKH_EINVAL, "null argument");
+  const size_t bytes = (size_t)m->nb() * NV * m->g.n1 * m->g.n2 * m->g.n3 * sizeof(double);
+  double* ddst = dst;
+  double* stage = nullptr;
+  if (!dst_on_device) {
+    stage = (double*)m->dalloc(bytes);
+    if (!stage) return fail(PKH_ENOMEM, "staging allocation failed");
+    ddst = stage;
+  }
+  HIPCHK(launch_gather(ddst, m->A, (int32_t)m->nb(), m->g, m->stream));
+  if (stage) HIPCHK(hipMemcpyAsync(dst, stage, bytes, hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (stage) m->dfree(stage);
+  return check_err(m);
+}
+
+int pkh_exchange_boundaries(pkh_mesh* m) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  return do_exchange(m);
+}
+
+int pkh_step(pkh_mesh* m, int32_t n_cycles, double t_end) {
+  if (!m || n_cycles < 0) return fail(PKH_EINVAL, "bad argument");
+  if (n_cycles == 0) return PKH_OK;
+  int rc;
+  if (!m->ghosts_valid && (rc = do_exchange(m))) return rc;
+  HIPCHK(launch_clock(m->d_time, CLOCK_BEGIN, t_end, m->stream));
+  const bool graph = (m->cfg.flags & PKH_FLAG_GRAPH) != 0;
+  if (!graph) {
+    for (int c = 0; c < n_cycles; ++c)
+      if ((rc = enqueue_cycle(m, c + 1 < n_cycles ? (CLOCK_END | CLOCK_BEGIN) : CLOCK_END, t_end)))
+        return rc;
+    return PKH_OK;
+  }
+  // Graph path: one captured cycle (ending with END|BEGIN) replayed; the
+  // last cycle is enqueued eagerly so that it ends with END only.
+  const bool same_tend = (std::isnan(t_end) && std::isnan(m->g_tend)) || t_end == m->g_tend;
+  if (!m->g_valid || !same_tend) {
+    drop_graph(m);
+    hipGraph_t graph_h = nullptr;
+    HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_cycle(m, CLOCK_END | CLOCK_BEGIN, t_end);
+    hipError_t e = hipStreamEndCapture(m->stream, &graph_h);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(PKH_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&m->gexec, graph_h, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph_h);
+    if (e != hipSuccess) return fail(PKH_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    m->g_tend = t_end;
+    m->g_valid = true;
+  }
+  for (int c = 0; c + 1 < n_cycles; ++c) HIPCHK(hipGraphLaunch(m->gexec, m->stream));
+  return enqueue_cycle(m, CLOCK_END, t_end);
+}
+
+int pkh_get_time(pkh_mesh* m, double* t, double* dt, int64_t* cycle) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  if (!m->ghosts_valid) {
+    int rc = do_exchange(m);
+    if (rc) return rc;
+  }
+  DevTime h;
+  HIPCHK(hipMemcpyAsync(&h, m->d_time, sizeof h, hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (t) *t = h.t;
+  if (dt) *dt = h.dt_next;
+  if (cycle) *cycle = h.cycle;
+  if (h.err & 1) return fail(PKH_EPHYS, "unphysical state (rho <= 0, P <= 0 or non-finite)");
+  if (h.err & 2) return fail(PKH_EBALANCE, "a ghost or regrid lookup found no covering leaf");
+  return PKH_OK;
+}
+
+int pkh_set_time(pkh_mesh* m, double t, int64_t cycle) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  DevTime h;
+  HIPCHK(hipMemcpyAsync(&h, m->d_time, sizeof h, hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  h.t = t;
+  h.cycle = cycle;
+  HIPCHK(hipMemcpyAsync(m->d_time, &h, sizeof h, hipMemcpyHostToDevice, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return PKH_OK;
+}
+
+int pkh_set_refinement_flags(pkh_mesh* m, const int8_t* flags, int64_t n) {
+  if (!m || !flags || n != m->nb()) return fail(PKH_EINVAL, "need one flag per leaf");
+  for (int64_t b = 0; b < n; ++b)
+    if (flags[b] < -1 || flags[b] > 1) return fail(PKH_EINVAL, "flags must be -1, 0 or +1");
+  m->flags.assign(flags, flags + n);
+  return PKH_OK;
+}
+
+int pkh_regrid(pkh_mesh* m) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  const Tree& t = m->tree;
+  const int64_t nl = m->nb();
+  std::vector<char> ref(nl, 0), der(nl, 0);
+  for (int64_t b = 0; b < nl; ++b) ref[b] = m->flags[b] > 0 && t.leaves[b].level < t.maxl;
+  // a refining leaf forces every touching coarser leaf to refine
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int64_t b = 0; b < nl; ++b) {
+      if (!ref[b]) continue;
+      const pkh_loc& l = t.leaves[b];
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (!dx && !dy && !dz) continue;
+            int lc;
+            const int32_t c = t.coarser(l.level, l.lx1 + dx, l.lx2 + dy, l.lx3 + dz, &lc);
+            if (c >= 0 && !ref[c]) {
+              ref[c] = 1;
+              changed = true;
+            }
+          }
+    }
+  }
+  // merges: complete sibling groups all flagged -1, none refining, and the
+  // parent keeps 2:1 with the refined mesh
+  for (int64_t b = 0; b < nl; ++b) {
+    const pkh_loc& l = t.leaves[b];
+    if (l.level == 0 || (l.lx1 & 1) || (l.lx2 & 1) || (l.lx3 & 1)) continue;
+    int32_t sib[8];
+    bool ok = true;
+    for (int c = 0; c < 8 && ok; ++c) {
+      sib[c] = t.at(l.level, l.lx1 + (c & 1), l.lx2 + ((c >> 1) & 1), l.lx3 + ((c >> 2) & 1));
+      if (sib[c] < 0 || m->flags[sib[c]] >= 0 || ref[sib[c]]) ok = false;
+    }
+    if (!ok) continue;
+    const int L = l.level;
+    const int64_t p[3] = {l.lx1 >> 1, l.lx2 >> 1, l.lx3 >> 1};
+    for (int dz = -1; dz <= 1 && ok; ++dz)
+      for (int dy = -1; dy <= 1 && ok; ++dy)
+        for (int dx = -1; dx <= 1 && ok; ++dx) {
+          if (!dx && !dy && !dz) continue;
+          int64_t q[3] = {p[0] + dx, p[1] + dy, p[2] + dz};
+          for (int e = 0; e < 3; ++e) q[e] = wrapl(q[e], t.nbd(L - 1, e));
+          int lc;
+          if (t.at(L - 1, q[0], q[1], q[2]) >= 0 || t.coarser(L - 1, q[0], q[1], q[2], &lc) >= 0) continue;
+          const int del[3] = {dx, dy, dz};
+          for (int c = 0; c < 8 && ok; ++c) {
+            const int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+            bool touch = true;
+            for (int e = 0; e < 3; ++e)
+              if ((del[e] < 0 && o[e] == 0) || (del[e] > 0 && o[e] == 1)) touch = false;
+            if (!touch) continue;
+            const int32_t cid = t.at(L, 2 * q[0] + o[0], 2 * q[1] + o[1], 2 * q[2] + o[2]);
+            if (cid < 0 || ref[cid]) ok = false;
+          }
+        }
+    if (ok)
+      for (int c = 0; c < 8; ++c) der[sib[c]] = c == 0 ? 2 : 1;
+  }
+  bool any = false;
+  for (int64_t b = 0; b < nl; ++b) any |= ref[b] || der[b];
+  std::fill(m->flags.begin(), m->flags.end(), 0);
+  if (!any) return PKH_OK;
+  // new leaves with their source: kind 0 copy, 1 child, 2 merged parent
+  struct NewLeaf {
+    pkh_loc loc;
+    int32_t kind, src;
+  };
+  std::vector<NewLeaf> nv;
+  for (int64_t b = 0; b < nl; ++b) {
+    const pkh_loc& l = t.leaves[b];
+    if (ref[b]) {
+      for (int c = 0; c < 8; ++c)
+        nv.push_back({{l.level + 1, 2 * l.lx1 + (c & 1), 2 * l.lx2 + ((c >> 1) & 1), 2 * l.lx3 + ((c >> 2) & 1)},
+                      1, (int32_t)b});
+    } else if (der[b] == 2) {
+      nv.push_back({{l.level - 1, l.lx1 >> 1, l.lx2 >> 1, l.lx3 >> 1}, 2, (int32_t)b});
+    } else if (der[b] == 0) {
+      nv.push_back({l, 0, (int32_t)b});
+    }
+  }
+  Tree nt;
+  std::copy(t.nrb, t.nrb + 3, nt.nrb);
+  nt.maxl = t.maxl;
+  std::stable_sort(nv.begin(), nv.end(), [&](const NewLeaf& a, const NewLeaf& b) {
+    uint64_t ka = t.key(a.loc), kb = t.key(b.loc);
+    return ka != kb ? ka < kb : a.loc.level < b.loc.level;
+  });
+  for (auto& x : nv) nt.leaves.push_back(x.loc);
+  int rc = nt.build();
+  if (rc) return rc;
+  // device: new state from the old one
+  std::vector<int32_t> kind(nv.size()), src(nv.size());
+  for (size_t r = 0; r < nv.size(); ++r) {
+    kind[r] = nv[r].kind;
+    src[r] = nv[r].src;
+  }
+  drop_graph(m);
+  double* oldA = m->A;
+  double* oldB = m->B;
+  BlockInfo* old_blocks = m->d_blocks;
+  int32_t* old_map = m->d_map;
+  LevelMaps old_maps = m->maps;
+  m->d_blocks = nullptr;
+  m->d_map = nullptr;
+  m->dfree(m->d_fbuf);
+  m->dfree(m->d_ff);
+  m->dfree(m->d_ff_first);
+  m->dfree(m->d_cblocks);
+  m->d_fbuf = nullptr;
+  m->d_ff = nullptr;
+  m->d_ff_first = nullptr;
+  m->d_cblocks = nullptr;
+  m->tree = std::move(nt);
+  int32_t *d_kind = nullptr, *d_src = nullptr;
+  if ((rc = build_tables(m, m->h_blocks, &m->d_map, m->maps)) || (rc = alloc_state(m)) ||
+      (rc = upload_vec(m, &d_kind, kind)) || (rc = upload_vec(m, &d_src, src)))
+    return rc;
+  HIPCHK(launch_regrid_data(m->A, m->d_blocks, d_kind, d_src, (int32_t)m->nb(), oldA, old_blocks,
+                            old_maps, m->g, m->d_time, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  m->dfree(d_kind);
+  m->dfree(d_src);
+  m->dfree(oldA);
+  m->dfree(oldB);
+  m->dfree(old_blocks);
+  m->dfree(old_map);
+  m->flags.assign(m->nb(), 0);
+  if ((rc = ensure_partials(m)) || (rc = do_exchange(m))) return rc;
+  return check_err(m);
+}
+
+int pkh_conserved_totals(pkh_mesh* m, double out[5]) {
+  if (!m || !out) return fail(PKH_EINVAL, "null argument");
+  HIPCHK(launch_totals(m->d_partial, m->d_tot, m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->stream));
+  HIPCHK(hipMemcpyAsync(out, m->d_tot, NV * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return check_err(m);
+}
+
+int pkh_sync(pkh_mesh* m) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  return check_err(m);
+}
+
+}  // extern "C"

@@ -1,0 +1,246 @@
+"""Parity of the HIP path against the CPU oracle, element by element, on
+seeded inputs; invariants that hold at any size. Runs on an MI355X."""
+import math
+
+import numpy as np
+import pytest
+
+from _helpers import print_case, rel_err
+from oracle.oracle import OracleMesh
+from paper_2202_12309_amd import inputs
+
+pytestmark = pytest.mark.gpu
+G = 5.0 / 3.0
+
+
+def _pair(nroot, n, leaves, max_level=0, **kw):
+    from paper_2202_12309_amd.binding import Mesh
+    nrb = tuple(nroot[d] // n[d] for d in range(3))
+    gm = Mesh(nroot, n, leaves, max_level=max_level, **kw)
+    kw.pop("graph", None)
+    om = OracleMesh(n, nrb, leaves, max_level=max_level, **kw)
+    assert np.array_equal(gm.leaves(), om.leaves())  # same Morton storage order
+    return gm, om, nrb
+
+
+def _run_both(gm, om, U0, cycles, t_end=math.inf):
+    gm.upload(U0)
+    om.set_state(U0)
+    gm.step(cycles, t_end)
+    om.step(cycles, t_end)
+    return gm.download(), om.state()
+
+
+def test_upload_download_round_trip_bitwise():
+    print_case("round trip 32^3 8x16^3")
+    n = (16, 16, 16)
+    gm, om, nrb = _pair((32, 32, 32), n, inputs.uniform_leaves((2, 2, 2)))
+    U0 = inputs.turbulent_box(gm.leaves(), n, nrb, seed=3)
+    gm.upload(U0)
+    assert np.array_equal(gm.download(), U0)
+
+
+@pytest.mark.parametrize("blk", [8, 16, 32, 64])
+def test_uniform_state_preserved_bitwise(blk):
+    print_case(f"uniform preservation blk={blk}")
+    N = 64
+    n = (blk, blk, blk)
+    nrb = (N // blk,) * 3
+    gm, om, _ = _pair((N, N, N), n, inputs.uniform_leaves(nrb))
+    U0 = inputs.uniform_state(gm.leaves(), n, rho=1.37, v=(0.31, -0.52, 0.11), p=0.83)
+    gm.upload(U0)
+    gm.step(3)
+    assert np.array_equal(gm.download(), U0)
+
+
+@pytest.mark.parametrize("cycles,tol", [(1, 1e-12), (10, 1e-12)])
+def test_sound_wave_64cube_8_blocks(cycles, tol):
+    """64^3 periodic as 8 blocks of 32^3: sound wave amplitude 1e-6 plus
+    white noise 1e-8, gamma 5/3, CFL 0.3."""
+    print_case(f"sound wave 64^3 cycles={cycles}")
+    n = (32, 32, 32)
+    gm, om, nrb = _pair((64, 64, 64), n, inputs.uniform_leaves((2, 2, 2)))
+    U0 = inputs.sound_wave(gm.leaves(), n, nrb, seed=1)
+    Ug, Uo = _run_both(gm, om, U0, cycles)
+    err = rel_err(Ug, Uo, G)
+    print("rel err", err)
+    assert np.all(err <= tol), err
+    tg, dtg, cg = gm.time()
+    to, _, co = om.time()
+    assert cg == co == cycles
+    assert abs(tg - to) <= 1e-14 * to
+    assert abs(dtg - om.dt()) <= 1e-14 * dtg
+    Tg = gm.totals()
+    To, Ao = om.totals()
+    assert np.all(np.abs(Tg - To) <= 1e-13 * Ao + 1e-300), (Tg - To) / Ao
+
+
+@pytest.mark.parametrize("blk", [8, 16, 32, 64])
+def test_turbulent_box_block_sizes(blk):
+    """Log-normal density, rms Mach 0.5: one recipe, four block sizes."""
+    print_case(f"turbulent box 64^3 blk={blk}")
+    N = 64
+    n = (blk, blk, blk)
+    nrb = (N // blk,) * 3
+    gm, om, _ = _pair((N, N, N), n, inputs.uniform_leaves(nrb))
+    U0 = inputs.turbulent_box(gm.leaves(), n, nrb, seed=2)
+    Ug, Uo = _run_both(gm, om, U0, 3)
+    err = rel_err(Ug, Uo, G)
+    print("rel err", err)
+    assert np.all(err <= 1e-12), err
+
+
+def test_turbulent_box_100_cycles():
+    print_case("turbulent box 32^3 8x16^3 100 cycles")
+    n = (16, 16, 16)
+    gm, om, nrb = _pair((32, 32, 32), n, inputs.uniform_leaves((2, 2, 2)))
+    U0 = inputs.turbulent_box(gm.leaves(), n, nrb, seed=2)
+    Ug, Uo = _run_both(gm, om, U0, 100)
+    err = rel_err(Ug, Uo, G)
+    print("rel err", err)
+    assert np.all(err <= 1e-9), err
+    assert abs(gm.time()[0] - om.time()[0]) <= 1e-12 * om.time()[0]
+
+
+def test_rk2_variant_plm_predictor():
+    print_case("stage-1 PLM variant")
+    n = (16, 16, 16)
+    gm, om, nrb = _pair((32, 32, 32), n, inputs.uniform_leaves((2, 2, 2)), stage1_recon=1)
+    U0 = inputs.turbulent_box(gm.leaves(), n, nrb, seed=4)
+    Ug, Uo = _run_both(gm, om, U0, 3)
+    assert np.all(rel_err(Ug, Uo, G) <= 1e-12)
+
+
+def test_t_end_clamp():
+    print_case("t_end clamp")
+    n = (16, 16, 16)
+    gm, om, nrb = _pair((32, 32, 32), n, inputs.uniform_leaves((2, 2, 2)))
+    U0 = inputs.sound_wave(gm.leaves(), n, nrb)
+    Ug, Uo = _run_both(gm, om, U0, 6, t_end=0.02)
+    assert gm.time()[0] == pytest.approx(0.02, rel=1e-15)
+    assert np.all(rel_err(Ug, Uo, G) <= 1e-12)
+
+
+def test_graph_replay_equals_eager():
+    print_case("graph replay vs eager")
+    from paper_2202_12309_amd.binding import Mesh
+    n = (16, 16, 16)
+    lv = inputs.uniform_leaves((2, 2, 2))
+    U0 = inputs.turbulent_box(lv, n, (2, 2, 2), seed=6)
+    a = Mesh((32, 32, 32), n, lv)
+    b = Mesh((32, 32, 32), n, lv, graph=True)
+    a.upload(U0)
+    b.upload(U0)
+    for rep in range(3):  # several replays with host work in between
+        a.step(4)
+        b.step(4)
+        assert np.array_equal(a.download(), b.download()), rep
+        assert a.time() == b.time()
+
+
+def test_deterministic_repeat():
+    print_case("determinism")
+    from paper_2202_12309_amd.binding import Mesh
+    n = (32, 32, 32)
+    lv = inputs.uniform_leaves((2, 2, 2))
+    U0 = inputs.turbulent_box(lv, n, (2, 2, 2), seed=8)
+    outs = []
+    for _ in range(2):
+        m = Mesh((64, 64, 64), n, lv)
+        m.upload(U0)
+        m.step(5)
+        outs.append((m.download(), m.totals(), m.time()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+def test_unphysical_state_latched():
+    print_case("EPHYS latch")
+    from paper_2202_12309_amd.binding import Mesh, PkhError
+    n = (16, 16, 16)
+    lv = inputs.uniform_leaves((1, 1, 1))
+    m = Mesh((16, 16, 16), n, lv)
+    U = inputs.uniform_state(lv, n)
+    U[0, 4, 3, 3, 3] = -1.0
+    m.upload(U)
+    m.step(1)
+    with pytest.raises(PkhError) as e:
+        m.sync()
+    assert e.value.name == "PKH_EPHYS"
+    m.upload(inputs.uniform_state(lv, n))  # the latch clears on upload
+    m.step(1)
+    m.sync()
+
+
+def test_invalid_meshes_rejected():
+    print_case("invalid meshes")
+    from paper_2202_12309_amd.binding import Mesh, PkhError
+    n = (8, 8, 8)
+    lv = inputs.uniform_leaves((2, 2, 2)).tolist()
+    with pytest.raises(PkhError) as e:
+        Mesh((16, 16, 16), n, lv[:-1])
+    assert e.value.name == "PKH_ETILING"
+    with pytest.raises(PkhError) as e:
+        Mesh((16, 16, 16), (12, 8, 8), lv)
+    assert e.value.name == "PKH_EINVAL"
+
+
+# ---------------------------------------------------------------------------
+# Multilevel meshes
+# ---------------------------------------------------------------------------
+
+def _amr_pair(nrb=(4, 4, 4), n=(16, 16, 16), radius=0.2, max_level=1):
+    leaves = inputs.sphere_refined_leaves(nrb, radius=radius)
+    nroot = tuple(nrb[d] * n[d] for d in range(3))
+    return _pair(nroot, n, leaves, max_level=max_level)
+
+
+@pytest.mark.parametrize("cycles", [1, 10])
+def test_amr_blast_parity(cycles):
+    print_case(f"AMR blast cycles={cycles}")
+    gm, om, nrb = _amr_pair()
+    U0 = inputs.blast(gm.leaves(), gm.n, nrb)
+    Ug, Uo = _run_both(gm, om, U0, cycles)
+    err = rel_err(Ug, Uo, G)
+    print("rel err", err)
+    assert np.all(err <= 1e-12), err
+    To, Ao = om.totals()
+    Tg = gm.totals()
+    assert np.all(np.abs(Tg - To) <= 1e-13 * np.maximum(Ao, 1.0))
+
+
+def test_amr_uniform_preserved_and_conservative():
+    print_case("AMR uniform + conservation")
+    gm, om, nrb = _amr_pair(n=(8, 8, 8))
+    U0 = inputs.uniform_state(gm.leaves(), gm.n, rho=1.37, v=(0.31, -0.52, 0.11), p=0.83)
+    gm.upload(U0)
+    gm.step(3)
+    assert np.array_equal(gm.download(), U0)
+    U1 = inputs.sound_wave(gm.leaves(), gm.n, nrb, amp=1e-2, noise=1e-3)
+    gm.upload(U1)
+    om.set_state(U1)
+    T0, A0 = om.totals()
+    gm.step(10)
+    T1 = gm.totals()
+    assert np.all(np.abs(T1 - T0) <= 1e-14 * 10 * A0)
+
+
+def test_amr_regrid_parity():
+    print_case("AMR regrid")
+    gm, om, nrb = _amr_pair(n=(8, 8, 8), max_level=2)
+    U0 = inputs.blast(gm.leaves(), gm.n, nrb)
+    Ug, Uo = _run_both(gm, om, U0, 2)
+    lv = om.leaves()
+    flags = np.zeros(len(lv), dtype=np.int8)
+    flags[lv[:, 0] == 1] = -1
+    flags[[k for k, l in enumerate(lv) if tuple(l) == (1, 3, 3, 3)]] = 1
+    flags[[k for k, l in enumerate(lv) if tuple(l) == (0, 0, 0, 0)]] = 1
+    gm.regrid(flags)
+    om.regrid(flags)
+    assert np.array_equal(gm.leaves(), om.leaves())
+    Ug, Uo = gm.download(), om.state()
+    assert np.all(rel_err(Ug, Uo, G) <= 1e-12)
+    gm.step(3)
+    om.step(3)
+    assert np.all(rel_err(gm.download(), om.state(), G) <= 1e-12)
