@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the hydro hot path on one MI355X.
+
+One step = one full VL2 cycle (predictor, ghost fill, corrector with the
+fused CFL reduction, ghost fill, device clock) over every block of the
+256^3 FP64 periodic mesh cut into 512 blocks of 32^3 (log-normal density,
+rms Mach 0.5; seeded, synthetic). Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--block 32]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-cycles/s & %HBM peak (256^3 FP64 hydro); adjoint/forward cost ratio"
+HBM_PEAK_GBS = 8000.0
+N = 256
+KERNEL_SRC = os.path.join(ROOT, "paper_2202_12309_amd", "csrc", "pkh_kernels.hip")
+
+
+def algorithmic_bytes(n):
+    """Bytes per zone for the corrector kernel and for the whole cycle, FP64,
+    5 variables, ghost width 2, ghosts materialised in memory.
+
+    Corrector: read U* with ghosts (r_g * 40 B), read U^n (40 B), write
+    U^{n+1} (40 B), r_g = (n+4)^3 / n^3. Cycle: predictor (r_g*40 + 40),
+    corrector (r_g*40 + 80), two ghost fills ((r_g - 1)*40 read + write each)
+    = 240 r_g - 40."""
+    rg = (n + 4) ** 3 / n ** 3
+    return rg * 40.0 + 80.0, 240.0 * rg - 40.0
+
+
+def traffic_from_profile(kernel_sha):
+    """Measured HBM bytes per corrector launch from the committed rocprofv3
+    counter summary, when it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "corrector_256cube_32blocks_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_source_sha256") != kernel_sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(blk, cycles=2):
+    """The oracle, as it stands, on the same 256^3 workload for a bounded
+    number of cycles on this host's cores."""
+    from oracle import oracle as orc
+    from paper_2202_12309_amd import inputs
+    n = (blk,) * 3
+    nrb = (N // blk,) * 3
+    lv = inputs.uniform_leaves(nrb)
+    om = orc.OracleMesh(n, nrb, lv)
+    om.set_state(inputs.turbulent_box(om.leaves(), n, nrb, seed=2))
+    t0 = time.perf_counter()
+    om.step(cycles)
+    el = time.perf_counter() - t0
+    return {"value": N ** 3 * cycles / el, "unit": "zone-cycles/s", "cores": orc.threads(),
+            "kind": "oracle",
+            "sample": f"{cycles} full cycles of the same 256^3 mesh ({N**3 * cycles} zone-cycles, "
+                      f"{el:.1f} s wall)"}
+
+
+def adjoint_ratio(cycles=50, ckpt=10):
+    """Reverse mode on 128^3 FP64 as 64 blocks of 32^3: 50 cycles from a
+    smooth seeded density perturbation (amplitude 1e-3, |k|_inf <= 4),
+    checkpoint every 10 cycles; loss = L2 misfit of the final density to a
+    seeded target. Returns the per-cycle cost of the reverse sweep (the
+    adjoint stage kernels only) and of the whole gradient (recomputation
+    included) relative to one forward cycle."""
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+    Nn, blk = 128, 32
+    n = (blk,) * 3
+    nrb = (Nn // blk,) * 3
+    mesh = Mesh((Nn,) * 3, n, inputs.uniform_leaves(nrb))
+    lv = mesh.leaves()
+    U0 = inputs.smooth_density(lv, n, nrb, seed=5)
+    tgt = torch.tensor(inputs.smooth_density(lv, n, nrb, seed=6)[:, 0], device="cuda")
+    tape = mesh.tape(ckpt)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for rep in range(2):  # the second repetition is timed
+        mesh.upload(U0)
+        mesh.sync()
+        ev[0].record(mesh.stream)
+        tape.forward(cycles)
+        ev[1].record(mesh.stream)
+        UN = mesh.download(device=True)
+        lam = torch.zeros_like(UN)
+        lam[:, 0] = (UN[:, 0] - tgt) / Nn ** 3
+        torch.cuda.synchronize()
+        mesh.kernel_timing(Mesh.KT_ADJOINT)
+        ev[2].record(mesh.stream)
+        tape.adjoint(lam)
+        ev[3].record(mesh.stream)
+        ev[3].synchronize()
+        kt = mesh.kernel_times()
+        mesh.kernel_timing(0)
+    t_fwd = ev[0].elapsed_time(ev[1]) / cycles
+    t_adj = ev[2].elapsed_time(ev[3]) / cycles
+    t_rev = kt["adjoint"][0] / cycles
+    return {"workload": "128^3 FP64, 64 blocks of 32^3, 50 cycles, checkpoint every 10",
+            "forward_ms_per_cycle": round(t_fwd, 4), "reverse_sweep_ms_per_cycle": round(t_rev, 4),
+            "gradient_ms_per_cycle": round(t_adj, 4),
+            "reverse_sweep_over_forward": round(t_rev / t_fwd, 3),
+            "gradient_over_forward": round(t_adj / t_fwd, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--block", type=int, default=32, choices=[16, 32, 64])
+    ap.add_argument("--graph", action="store_true", help="replay captured cycles")
+    ap.add_argument("--tile-rows", type=int, default=0, help="stage-kernel tile rows (0: default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (the HBM-counter calibration kernel)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
+              "described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+
+    blk = args.block
+    n = (blk,) * 3
+    nrb = (N // blk,) * 3
+    lv = inputs.uniform_leaves(nrb)
+    mesh = Mesh((N, N, N), n, lv, graph=args.graph)
+    mesh.set_tuning(args.tile_rows)
+    mesh.upload(inputs.turbulent_box(mesh.leaves(), n, nrb, seed=2))
+    mesh.step(args.warmup)
+    mesh.sync()
+
+    kinds = Mesh.KT_PREDICTOR | Mesh.KT_CORRECTOR | Mesh.KT_FILL
+    mesh.kernel_timing(kinds)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(mesh.stream)
+    mesh.step(args.steps)
+    ev1.record(mesh.stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    mesh.sync()
+    kt = mesh.kernel_times()
+    t, dt, cyc = mesh.time()
+
+    zc = N ** 3 * args.steps / (ms / 1e3)
+    b_corr, b_cycle = algorithmic_bytes(blk)
+    cells = N ** 3
+    avg = {k: (v[0] / v[1] if v[1] else None) for k, v in kt.items()}
+    corr_ms = avg["corrector"]
+    roof = None
+    if corr_ms:
+        ach = b_corr * cells / (corr_ms / 1e3) / 1e9
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        roof = {"bound": "hbm", "kernel": "stage_kernel<PLM> (corrector)",
+                "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profile(sha),
+                "algorithmic_bytes_per_launch": int(b_corr * cells),
+                "avg_launch_ms": round(corr_ms, 4)}
+    out = {
+        "metric": METRIC,
+        "value": zc,
+        "unit": "zone-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"hydro 256^3 FP64 periodic, {len(lv)} blocks of {blk}^3, one pack; "
+                               "log-normal density (sigma 0.5), P=1, rms Mach 0.5, seed 2; VL2 "
+                               "PLM-MC + HLLE, CFL 0.3",
+                   "cells": cells, "block": blk, "blocks": len(lv), "graph": bool(args.graph),
+                   "tile_rows": mesh.tuning()["tile_rows"]},
+        "hbm_frac_cycle": round(zc * b_cycle / (HBM_PEAK_GBS * 1e9), 4),
+        "bytes_per_zone_cycle": round(b_cycle, 2),
+        "kernel_avg_ms": {k: (round(v, 4) if v else None) for k, v in avg.items()},
+        "sim_time": t,
+        "adjoint_forward_ratio": None,
+        "adjoint": None,
+        "roofline": roof,
+    }
+    if not args.no_adjoint:
+        adj = adjoint_ratio()
+        out["adjoint"] = adj
+        out["adjoint_forward_ratio"] = adj["reverse_sweep_over_forward"]
+    if not args.no_cpu_baseline:
+        del mesh
+        out["cpu_baseline"] = cpu_baseline(blk)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

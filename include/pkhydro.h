@@ -65,10 +65,10 @@ enum { PKH_FLAG_GRAPH = 1u /* replay captured cycles with hipGraphs */ };
 /* Mesh configuration.
  *   nroot[d]   level-0 cells along d; a multiple of nblock[d].
  *   nblock[d]  cells per block along d (same for every block, Sec. 2.1).
- *              nblock[0] is 8, 16, 32 or 64; nblock[1], nblock[2] are
- *              multiples of the kernel's row tile (8 for nblock[0] <= 32,
- *              4 for 64) and at least 4; with max_level > 0 every nblock[d]
- *              is at least 8.
+ *              nblock[0] is 8, 16, 32 or 64; nblock[1] is a multiple of
+ *              the default row tile (8 for nblock[0] <= 32, 4 for 64);
+ *              nblock[2] is at least 4; with max_level > 0 every nblock[d]
+ *              is even and at least 8.
  *   nghost     must be 2 (PLM needs two cells on each side of a face).
  *   max_level  deepest refinement level (0..7).
  *   xmin/xmax  domain extent; gamma the ideal-gas ratio; cfl the Courant
@@ -176,6 +176,69 @@ int pkh_regrid(pkh_mesh *mesh);
 /* Conserved totals sum_leaves sum_active U_v dV (Sec. 3.10 reduction);
    fixed-order device reduction; synchronises. out[5]. */
 int pkh_conserved_totals(pkh_mesh *mesh, double out[5]);
+
+/* ---- Reverse mode (gradient of a final-state loss w.r.t. the initial
+   state), single-level meshes. A tape records the timestep of every cycle
+   and the state every `ckpt_every` cycles; the adjoint recomputes each
+   segment forward from its checkpoint, keeping the ghost-filled inputs of
+   both stages, and sweeps it in reverse: per cycle the transposes of the
+   ghost fill, the corrector, the ghost fill and the predictor, with the
+   timestep frozen at its recorded value and limiter / wave-speed branches
+   frozen at those the forward pass takes. ---- */
+typedef struct pkh_tape pkh_tape;
+
+/* Tape for the mesh; ckpt_every >= 1. Device memory: one active-state copy
+   per checkpoint (allocated as cycles are recorded) plus 2*ckpt_every + 2
+   ghost-filled states for recomputation. PKH_EINVAL on multilevel meshes. */
+int pkh_tape_create(pkh_mesh *mesh, int32_t ckpt_every, pkh_tape **out);
+int pkh_tape_destroy(pkh_tape *tape);
+
+/* Advance n_cycles exactly like pkh_step (no t_end clamp) while recording
+   into the tape. A second call discards the previous recording. */
+int pkh_forward_taped(pkh_mesh *mesh, pkh_tape *tape, int32_t n_cycles);
+
+/* Advance the mesh's current state by the recorded number of cycles using
+   the recorded timesteps (not the CFL timesteps of the current state): the
+   map whose derivative pkh_adjoint computes, e.g. for finite-difference
+   checks. Records nothing. */
+int pkh_tape_replay(pkh_mesh *mesh, pkh_tape *tape);
+
+/* Given lam_final = dL/dU at the end of the recorded cycles (device,
+   upload layout), write dL/dU at their start to grad_init (device, upload
+   layout; may alias lam_final). The mesh's own state is not touched.
+   Enqueued on the mesh's stream; synchronises at the end. */
+int pkh_adjoint(pkh_mesh *mesh, pkh_tape *tape, const double *lam_final, double *grad_init);
+
+/* Launch tuning of the stage kernels (set by the caller or an autotuner).
+   tile_rows: rows of cells per workgroup tile (0 = default). Compiled
+   choices: n1 = 8: 8; n1 = 16: 8, 16, 4; n1 = 32: 8, 4, 16; n1 = 64: 4, 2.
+   It must divide nblock[1]. The results do not depend on it (each face
+   flux is computed by the same arithmetic whatever the tile). */
+typedef struct {
+  int32_t tile_rows;
+  int32_t reserved[3];
+} pkh_tuning;
+int pkh_set_tuning(pkh_mesh *mesh, const pkh_tuning *tuning);
+int pkh_get_tuning(const pkh_mesh *mesh, pkh_tuning *tuning);
+
+/* Kernel timing with HIP events on the handle's stream (a measurement aid
+   for the roofline report). `kinds` is a mask of PKH_KT_* bits; while it is
+   non-zero, pkh_step (eager path; graph replays are not bracketed) records
+   an event pair around every launch of those kinds. Setting a new mask
+   discards earlier records. */
+enum {
+  PKH_KT_PREDICTOR = 1u, /* stage-1 kernel */
+  PKH_KT_CORRECTOR = 2u, /* stage-2 kernel (with the fused CFL reduction) */
+  PKH_KT_FILL = 4u,      /* ghost exchange kernel */
+  PKH_KT_FLUXCORR = 8u,  /* fine-coarse flux correction kernel */
+  PKH_KT_ADJOINT = 16u   /* reverse sweep of one stage (pkh_adjoint) */
+};
+int pkh_kernel_timing(pkh_mesh *mesh, uint32_t kinds);
+/* Per kind index (0 predictor, 1 corrector, 2 fill, 3 flux correction,
+   4 adjoint stage): summed bracketed duration in milliseconds and the
+   number of launches since the mask was set. ms[5], count[5].
+   Synchronises. */
+int pkh_kernel_times(pkh_mesh *mesh, double *ms, int64_t *count);
 
 /* Wait for the handle's stream and report any latched PKH_EPHYS. */
 int pkh_sync(pkh_mesh *mesh);

@@ -50,6 +50,7 @@ def lib():
         L.orc_minmod.restype = C.c_double
         L.orc_hlle.argtypes = [_D, _D, C.c_int, C.c_double, _D]
         L.orc_prim.argtypes = [_D, C.c_double, _D]
+        L.orc_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -60,6 +61,11 @@ def _dp(a):
 
 class OracleError(RuntimeError):
     pass
+
+
+def threads():
+    """OpenMP threads the oracle uses."""
+    return int(lib().orc_threads())
 
 
 def mc(dl, dr):

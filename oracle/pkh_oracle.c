@@ -872,3 +872,7 @@ int orc_regrid(void *h, const int8_t *flags, int64_t nflags) {
   free(der);
   return build_maps(m);
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }

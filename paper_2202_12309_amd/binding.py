@@ -35,6 +35,10 @@ class Config(C.Structure):
                 ("flags", C.c_uint32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("tile_rows", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
 class Loc(C.Structure):
     _fields_ = [("level", C.c_int32), ("lx1", C.c_int32), ("lx2", C.c_int32), ("lx3", C.c_int32)]
 
@@ -61,7 +65,16 @@ _SIGS = {
     "pkh_regrid": (C.c_int, [C.c_void_p]),
     "pkh_conserved_totals": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pkh_sync": (C.c_int, [C.c_void_p]),
+    "pkh_kernel_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "pkh_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
+    "pkh_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
+    "pkh_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "pkh_last_error": (C.c_char_p, []),
+    "pkh_tape_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "pkh_tape_destroy": (C.c_int, [C.c_void_p]),
+    "pkh_forward_taped": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "pkh_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pkh_tape_replay": (C.c_int, [C.c_void_p, C.c_void_p]),
 }
 
 
@@ -253,6 +266,34 @@ class Mesh:
         _check(lib().pkh_conserved_totals(self._h, out))
         return np.array(out[:])
 
+    def set_tuning(self, tile_rows=0):
+        t = Tuning()
+        t.tile_rows = int(tile_rows)
+        _check(lib().pkh_set_tuning(self._h, C.byref(t)))
+
+    def tuning(self):
+        t = Tuning()
+        _check(lib().pkh_get_tuning(self._h, C.byref(t)))
+        return {"tile_rows": t.tile_rows}
+
+    KT_PREDICTOR, KT_CORRECTOR, KT_FILL, KT_FLUXCORR, KT_ADJOINT = 1, 2, 4, 8, 16
+
+    def kernel_timing(self, kinds):
+        _check(lib().pkh_kernel_timing(self._h, int(kinds)))
+
+    def kernel_times(self):
+        """{kind: (total ms, launches)} for predictor, corrector, fill,
+        fluxcorr and adjoint (one reverse stage)."""
+        ms = (C.c_double * 5)()
+        cnt = (C.c_int64 * 5)()
+        _check(lib().pkh_kernel_times(self._h, ms, cnt))
+        names = ("predictor", "corrector", "fill", "fluxcorr", "adjoint")
+        return {names[k]: (ms[k], cnt[k]) for k in range(5)}
+
+    # -- reverse mode ------------------------------------------------------------
+    def tape(self, ckpt_every):
+        return Tape(self, ckpt_every)
+
     def set_flags(self, flags):
         f = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
         _check(lib().pkh_set_refinement_flags(self._h, f.ctypes.data_as(C.POINTER(C.c_int8)), len(f)))
@@ -261,3 +302,79 @@ class Mesh:
         if flags is not None:
             self.set_flags(flags)
         _check(lib().pkh_regrid(self._h))
+
+
+class Tape:
+    """Recording of taped cycles for the reverse mode (single-level meshes)."""
+
+    def __init__(self, mesh, ckpt_every):
+        self.mesh = mesh
+        h = C.c_void_p()
+        _check(lib().pkh_tape_create(mesh._h, int(ckpt_every), C.byref(h)))
+        self._h = h
+
+    def forward(self, n_cycles):
+        _check(lib().pkh_forward_taped(self.mesh._h, self._h, int(n_cycles)))
+
+    def replay(self):
+        """Advance the mesh's current state with the recorded timesteps."""
+        _check(lib().pkh_tape_replay(self.mesh._h, self._h))
+
+    def adjoint(self, lam_final):
+        """lam_final: float64 CUDA tensor in the upload layout; returns dL/dU0."""
+        torch = self.mesh.torch
+        lam = lam_final.contiguous()
+        assert lam.dtype == torch.float64 and lam.is_cuda and tuple(lam.shape) == self.mesh.shape()
+        self.mesh.stream.wait_stream(torch.cuda.current_stream(lam.device))
+        out = torch.empty_like(lam)
+        _check(lib().pkh_adjoint(self.mesh._h, self._h, C.c_void_p(lam.data_ptr()),
+                                 C.c_void_p(out.data_ptr())))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pkh_tape_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _euler_vl2_function():
+    import torch
+
+    class EulerVL2(torch.autograd.Function):
+        """U_N = n_cycles of the VL2 cycle applied to U_0 on the GPU mesh;
+        backward runs the hand-written adjoint with checkpointing (timesteps
+        frozen at the forward's values)."""
+
+        @staticmethod
+        def forward(ctx, U0, mesh, n_cycles, ckpt_every):
+            mesh.upload(U0)
+            tape = mesh.tape(ckpt_every)
+            tape.forward(n_cycles)
+            UN = mesh.download(device=True)
+            ctx.tape = tape
+            return UN
+
+        @staticmethod
+        def backward(ctx, gUN):
+            g0 = ctx.tape.adjoint(gUN.to(torch.float64))
+            return g0, None, None, None
+
+    return EulerVL2
+
+
+_EULER_FN = None
+
+
+def euler_vl2(U0, mesh, n_cycles, ckpt_every=10):
+    """Differentiable n-cycle update of a state tensor [nleaves][5][n3][n2][n1]
+    (float64, on the mesh's GPU) -- see EulerVL2."""
+    global _EULER_FN
+    if _EULER_FN is None:
+        _EULER_FN = _euler_vl2_function()
+    return _EULER_FN.apply(U0, mesh, int(n_cycles), int(ckpt_every))

@@ -77,16 +77,26 @@ struct StageLaunch {
   int32_t recon;      // 0 DC, 1 PLM
   int32_t do_dt;      // accumulate the CFL reduction from the updated state
   double* fbuf;       // face buffers (may be null on single-level meshes)
+  // Same-level neighbour of each leaf per direction, [leaf][27] with index
+  // (dz+1)*9 + (dy+1)*3 + (dx+1), -1 where the neighbour is not a same-level
+  // leaf. The stage kernel writes every updated cell that a same-level
+  // neighbour needs as a ghost straight into that neighbour's ghost zone.
+  const int32_t* nbr;
   int32_t tj;         // rows per tile (0: default)
 };
 
 hipError_t launch_stage(const StageLaunch& a, hipStream_t s);
+// Rows per workgroup tile actually used for a block of n1 x n2 cells and a
+// requested value (0: default); -1 if no compiled variant fits.
+int stage_tile_rows(int n1, int n2, int tj);
+// skip_same: leave ghost cells whose source is a same-level leaf alone
+// (the stage kernels already wrote them).
 hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
-                       const LevelMaps& maps, DevTime* tm, hipStream_t s);
+                       const LevelMaps& maps, DevTime* tm, int32_t skip_same, hipStream_t s);
 hipError_t launch_flux_correct(double* u, const BlockInfo* blocks, const FineFace* ff,
                                const int32_t* ff_first, const int32_t* cblocks, int32_t ncblocks,
                                const Geom& g, DevTime* tm, double beta, int32_t do_dt,
-                               const double* fbuf, hipStream_t s);
+                               const double* fbuf, const int32_t* nbr, hipStream_t s);
 hipError_t launch_dt(const double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                      DevTime* tm, hipStream_t s);
 hipError_t launch_clock(DevTime* tm, int32_t mode, double t_end, hipStream_t s);
@@ -102,6 +112,17 @@ hipError_t launch_regrid_data(double* unew, const BlockInfo* bnew, const int32_t
                               const int32_t* src, int32_t nnew, const double* uold,
                               const BlockInfo* bold, const LevelMaps& old_maps, const Geom& g,
                               DevTime* tm, hipStream_t s);
+
+// Reverse mode of one stage U_out = U_base - beta*dt*D(U_in) w.r.t. U_in
+// (same-level meshes): out = add0 + add1 + (dD/dU_in)^T-term of lam;
+// U is the padded, ghost-filled U_in; wbar a padded scratch array; dt is
+// read from dtp on the device.
+hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar,
+                            const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                            const int32_t* nbr, const double* dtp, double beta, double* out,
+                            const double* add0, const double* add1, hipStream_t s);
+// record: dts[c] = tm->dt; else tm->dt = dts[c].
+hipError_t launch_tape_dt(DevTime* tm, double* dts, int32_t c, int32_t record, hipStream_t s);
 
 // Clock modes
 enum : int { CLOCK_END = 1, CLOCK_BEGIN = 2, CLOCK_FROM_SMAX = 4 };

@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include "pkh_internal.h"
+#include "pkh_physics.h"
 
 namespace pkh {
 
@@ -22,99 +23,70 @@ namespace pkh {
 // Pointwise physics
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool to_prim(const double u[NV], double gam, double w[NV]) {
-  const double ir = 1.0 / u[0];
-  w[0] = u[0];
-  w[1] = u[1] * ir;
-  w[2] = u[2] * ir;
-  w[3] = u[3] * ir;
-  w[4] = (gam - 1.0) * (u[4] - 0.5 * (u[1] * w[1] + u[2] * w[2] + u[3] * w[3]));
-  return (w[0] > 0.0) && (w[4] > 0.0);  // false also for NaN
-}
-
-// Monotonised-central limited slope (van Leer 1977).
-__device__ __forceinline__ double mc_slope(double dl, double dr) {
-  const double m = fmin(fmin(2.0 * fabs(dl), 2.0 * fabs(dr)), 0.5 * fabs(dl + dr));
-  return (dl * dr > 0.0) ? copysign(m, dl) : 0.0;
-}
-
-__device__ __forceinline__ double minmod(double a, double b) {
-  const double m = fmin(fabs(a), fabs(b));
-  return (a * b > 0.0) ? copysign(m, a) : 0.0;
-}
-
-// HLLE flux normal to direction D from primitive states; Einfeldt (1988)
-// bounds b+ = max(u_roe + a_roe, u_R + c_R, 0), b- = min(u_roe - a_roe,
-// u_L - c_L, 0).
-template <int D>
-__device__ __forceinline__ void hlle(const double wl[NV], const double wr[NV], double gam,
-                                     double f[NV]) {
-  const double gm1 = gam - 1.0;
-  const double igm1 = 1.0 / gm1;
-  const double rl = wl[0], pl = wl[4], rr = wr[0], pr = wr[4];
-  const double ul = wl[1 + D], ur = wr[1 + D];
-  const double irl = 1.0 / rl, irr = 1.0 / rr;
-  const double v2l = wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3];
-  const double v2r = wr[1] * wr[1] + wr[2] * wr[2] + wr[3] * wr[3];
-  const double el = pl * igm1 + 0.5 * rl * v2l;
-  const double er = pr * igm1 + 0.5 * rr * v2r;
-  const double hl = (el + pl) * irl, hr = (er + pr) * irr;
-  const double cl = sqrt(gam * pl * irl), cr = sqrt(gam * pr * irr);
-  const double sl = sqrt(rl), sr = sqrt(rr);
-  const double r = sl / (sl + sr), r1 = 1.0 - r;
-  const double vb0 = r * wl[1] + r1 * wr[1];
-  const double vb1 = r * wl[2] + r1 * wr[2];
-  const double vb2 = r * wl[3] + r1 * wr[3];
-  const double hb = r * hl + r1 * hr;
-  const double ab = sqrt(gm1 * (hb - 0.5 * (vb0 * vb0 + vb1 * vb1 + vb2 * vb2)));
-  const double vbn = D == 0 ? vb0 : (D == 1 ? vb1 : vb2);
-  const double bp = fmax(fmax(vbn + ab, ur + cr), 0.0);
-  const double bm = fmin(fmin(vbn - ab, ul - cl), 0.0);
-  const double ib = 1.0 / (bp - bm);
-  const double bpm = bp * bm;
-  const double ml = rl * ul, mr = rr * ur;  // mass fluxes
-  // mass
-  f[0] = (bp * ml - bm * mr + bpm * (rr - rl)) * ib;
-  // momentum
+// Write an updated active cell (i, j, k) of a leaf into the ghost zones of
+// the same-level neighbours that need it (cells within 2 of a face, edge or
+// corner). nb27: the leaf's neighbour row.
+__device__ __forceinline__ void push_ghosts(double* u, const int32_t* nb27, const Geom& g, int i,
+                                            int j, int k, const double val[NV]) {
+  const int dx = i < NG ? -1 : (i >= g.n1 - NG ? 1 : 0);
+  const int dy = j < NG ? -1 : (j >= g.n2 - NG ? 1 : 0);
+  const int dz = k < NG ? -1 : (k >= g.n3 - NG ? 1 : 0);
+  auto put = [&](int ex, int ey, int ez) {
+    const int32_t nb = nb27[(ez + 1) * 9 + (ey + 1) * 3 + (ex + 1)];
+    if (nb < 0) return;
+    double* d = u + (int64_t)nb * g.bstride +
+                ((int64_t)(k - ez * g.n3 + NG) * g.p2 + (j - ey * g.n2 + NG)) * g.p1 + (i - ex * g.n1 + NG);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double fl = ml * wl[1 + c], fr = mr * wr[1 + c];
-    if (c == D) {
-      fl += pl;
-      fr += pr;
-    }
-    f[1 + c] = (bp * fl - bm * fr + bpm * (rr * wr[1 + c] - rl * wl[1 + c])) * ib;
+    for (int v = 0; v < NV; ++v) d[v * g.vstride] = val[v];
+  };
+  if (dx) put(dx, 0, 0);
+  if (dy) {
+    put(0, dy, 0);
+    if (dx) put(dx, dy, 0);
   }
-  // energy
-  f[4] = (bp * (el + pl) * ul - bm * (er + pr) * ur + bpm * (er - el)) * ib;
+  if (dz) {
+    put(0, 0, dz);
+    if (dx) put(dx, 0, dz);
+    if (dy) {
+      put(0, dy, dz);
+      if (dx) put(dx, dy, dz);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Stage kernel: U_out = U_base - beta*dt * D(U_in) over every block.
 //
 // A workgroup owns TJ rows of N1 cells of one block and streams through z.
-// Per z-plane it stages the plane's primitives (TJ+4 rows incl. halo, full
-// padded row width, one contiguous run of memory per variable) in LDS,
-// computes every x- and y-face flux of the plane once (LDS), and keeps a
-// register window of the column's primitives for the z faces. A cell is
-// finished once its upper z face is known; its x/y divergence waits in a
-// short register queue.
+// Each thread loads its own cell of every plane (and, with the others, the
+// 2-cell halo of the tile), keeps its column's states in a register window
+// for the z faces, and stages the plane's face-state inputs in LDS for the
+// x and y faces, each of which is solved once. The predictor (donor cell)
+// stages per-cell HLLE inputs (sqrt(rho), c, h) so no face recomputes them;
+// the corrector stages primitives and reconstructs per face (PLM-MC). A
+// cell is finished once its upper z face is known; its x/y divergence waits
+// in a short register queue. Finished cells a same-level neighbour needs as
+// ghosts are written into that neighbour's ghost zone here.
 // ---------------------------------------------------------------------------
 
 template <int RECON, int N1, int TJ>
-__global__ void __launch_bounds__(N1 * TJ) stage_kernel(StageLaunch a) {
+// At most 168 VGPRs so that three waves fit per SIMD (no spills).
+__global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
   constexpr int NT = N1 * TJ;
   constexpr int P1 = N1 + 2 * NG;
   constexpr int RW = TJ + 2 * NG;
   constexpr int PLANE = RW * P1;
+  constexpr int NHALO = PLANE - NT;
   constexpr int NX = TJ * (N1 + 1);
   constexpr int NY = (TJ + 1) * N1;
   constexpr int LAG = RECON ? 1 : 0;  // z face m is computed at plane m + LAG
   constexpr int WN = RECON ? 4 : 2;   // z window length
   constexpr int QN = 1 + LAG;         // x/y divergence queue length
+  constexpr int UQN = RECON ? 1 : 2;  // predictor: conserved own-cell queue length
+  constexpr int NQ = RECON ? 5 : 8;   // staged values per cell
   constexpr int NWAVE = (NT + 63) / 64;
 
-  __shared__ double sW[NV][PLANE];
+  __shared__ double sQ[NQ][PLANE];
   __shared__ double sFx[NV][NX];
   __shared__ double sFy[NV][NY];
   __shared__ double sRed[NWAVE];
@@ -126,6 +98,7 @@ __global__ void __launch_bounds__(N1 * TJ) stage_kernel(StageLaunch a) {
   // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; map
   // consecutive tiles of a block (which share halo rows) to one XCD's L2.
   if ((nwg & 7) == 0) wg = (wg & 7) * (nwg >> 3) + (wg >> 3);
+  static_assert(NT % 64 == 0, "whole waves");
   const int blk = wg / ntj;
   if (blk >= a.nblocks) return;
   const int j0 = (wg - blk * ntj) * TJ;
@@ -134,6 +107,8 @@ __global__ void __launch_bounds__(N1 * TJ) stage_kernel(StageLaunch a) {
 
   const BlockInfo bi = a.blocks[blk];
   const double gam = g.gamma;
+  const double gm1 = gam - 1.0;
+  const double igm1 = 1.0 / gm1;
   const double coef = a.beta * a.tm->dt;
   const int64_t vs = g.vstride;
   const double* __restrict__ in = a.uin + (int64_t)blk * g.bstride;
@@ -143,61 +118,138 @@ __global__ void __launch_bounds__(N1 * TJ) stage_kernel(StageLaunch a) {
   const int j = j0 + tj;
   const int fsz = NV * max(max(g.n1 * n2, g.n1 * n3), n2 * n3);  // face slot stride
   double* fbuf = a.fbuf;
+  const int32_t* nb27 = a.nbr ? a.nbr + (int64_t)blk * 27 : nullptr;
+  const int own = (tj + NG) * P1 + ti + NG;  // this thread's cell in the LDS plane
 
-  double w[WN][NV];
-  double dq[QN][NV];
+  FState w[WN];       // z window (column states)
+  double uq[UQN][NV];  // predictor: conserved own-cell values awaiting their update
+  double dq[QN][NV];  // x/y divergence awaiting the z faces
   double fzp[NV];
   bool bad = false;
   double smax = 0.0;
   const int mask = bi.finer_mask;
 
 #pragma unroll
-  for (int s = 0; s < WN; ++s)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) w[s][v] = 0.0;
+  for (int s = 0; s < WN; ++s) w[s] = FState{1.0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0, 1.0};
 #pragma unroll
   for (int s = 0; s < QN; ++s)
 #pragma unroll
     for (int v = 0; v < NV; ++v) dq[s][v] = 0.0;
 #pragma unroll
+  for (int s = 0; s < UQN; ++s)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uq[s][v] = 0.0;
+#pragma unroll
   for (int v = 0; v < NV; ++v) fzp[v] = 0.0;
 
+  // stage one cell's inputs into LDS slot c; returns its state
+  auto stage_cell = [&](const double u[NV], int c) {
+    FState q;
+    double wp[NV];
+    bad |= !to_prim(u, gam, wp);
+    q.r = wp[0];
+    q.v0 = wp[1];
+    q.v1 = wp[2];
+    q.v2 = wp[3];
+    q.p = wp[4];
+    sQ[0][c] = q.r;
+    sQ[1][c] = q.v0;
+    sQ[2][c] = q.v1;
+    sQ[3][c] = q.v2;
+    sQ[4][c] = q.p;
+    if constexpr (!RECON) {
+      complete_state(q, gam, igm1);
+      sQ[5][c] = q.sr;
+      sQ[6][c] = q.c;
+      sQ[7][c] = q.h;
+    }
+    return q;
+  };
+  // face states of the face between LDS cells cm (lower) and c0 (upper),
+  // stride st between neighbours along the face normal
+  auto face_states = [&](int c0, int st, FState& L, FState& R) {
+    if constexpr (RECON) {
+      double wl[NV], wr[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double qm2 = sQ[v][c0 - 2 * st], qm1 = sQ[v][c0 - st], q0 = sQ[v][c0],
+                     qp1 = sQ[v][c0 + st];
+        wl[v] = qm1 + 0.5 * mc_slope(qm1 - qm2, q0 - qm1);
+        wr[v] = q0 - 0.5 * mc_slope(q0 - qm1, qp1 - q0);
+      }
+      L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+      R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+      complete_state(L, gam, igm1);
+      complete_state(R, gam, igm1);
+    } else {
+      const int cm = c0 - st;
+      L = FState{sQ[0][cm], sQ[1][cm], sQ[2][cm], sQ[3][cm], sQ[4][cm], sQ[5][cm], sQ[6][cm], sQ[7][cm]};
+      R = FState{sQ[0][c0], sQ[1][c0], sQ[2][c0], sQ[3][c0], sQ[4][c0], sQ[5][c0], sQ[6][c0], sQ[7][c0]};
+    }
+  };
+
   for (int p = -1 - LAG; p < n3 + 1 + LAG; ++p) {
-    // --- stage plane p (rows j0-2 .. j0+TJ+1) as primitives in LDS
-    const int64_t pofs = ((int64_t)(p + NG) * g.p2 + j0) * P1;
-    for (int c = tid; c < PLANE; c += NT) {
-      double u[NV], wp[NV];
+    // --- stage plane p (rows j0-2 .. j0+TJ+1): own cell first, then halo
+    const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
+    {
+      double u[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) u[v] = in[v * vs + pofs + c];
-      bad |= !to_prim(u, gam, wp);
+      for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + own];
+      const FState q = stage_cell(u, own);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sW[v][c] = wp[v];
+      for (int s = 0; s < WN - 1; ++s) w[s] = w[s + 1];
+      w[WN - 1] = q;
+      if constexpr (!RECON) {
+#pragma unroll
+        for (int s = 0; s < UQN - 1; ++s)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) uq[s][v] = uq[s + 1][v];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uq[UQN - 1][v] = u[v];
+      }
+    }
+    for (int h = tid; h < NHALO; h += NT) {
+      int c;
+      if (h < 2 * P1) {
+        c = h;
+      } else if (h < 4 * P1) {
+        c = (TJ + NG) * P1 + (h - 2 * P1);
+      } else {
+        const int hh = h - 4 * P1, r = hh >> 2, s4 = hh & 3;
+        c = (r + NG) * P1 + (s4 < 2 ? s4 : P1 - 4 + s4);
+      }
+      double u[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + c];
+      stage_cell(u, c);
     }
     __syncthreads();
-
-    // --- z window
-#pragma unroll
-    for (int s = 0; s < WN - 1; ++s)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) w[s][v] = w[s + 1][v];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) w[WN - 1][v] = sW[v][(tj + NG) * P1 + ti + NG];
 
     // --- z face m between cells m-1 and m, then finish cell m-1
     const int m = p - LAG;
     if (m >= 0 && m <= n3) {
-      double wl[NV], wr[NV], fz[NV];
+      FState L, R;
+      double fz[NV];
+      if constexpr (RECON) {
+        const double c0[NV] = {w[0].r, w[0].v0, w[0].v1, w[0].v2, w[0].p};
+        const double c1[NV] = {w[1].r, w[1].v0, w[1].v1, w[1].v2, w[1].p};
+        const double c2[NV] = {w[2].r, w[2].v0, w[2].v1, w[2].v2, w[2].p};
+        const double c3[NV] = {w[3].r, w[3].v0, w[3].v1, w[3].v2, w[3].p};
+        double wl[NV], wr[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if constexpr (RECON) {
-          wl[v] = w[1][v] + 0.5 * mc_slope(w[1][v] - w[0][v], w[2][v] - w[1][v]);
-          wr[v] = w[2][v] - 0.5 * mc_slope(w[2][v] - w[1][v], w[3][v] - w[2][v]);
-        } else {
-          wl[v] = w[0][v];
-          wr[v] = w[1][v];
+        for (int v = 0; v < NV; ++v) {
+          wl[v] = c1[v] + 0.5 * mc_slope(c1[v] - c0[v], c2[v] - c1[v]);
+          wr[v] = c2[v] - 0.5 * mc_slope(c2[v] - c1[v], c3[v] - c2[v]);
         }
+        L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+        R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+        complete_state(L, gam, igm1);
+        complete_state(R, gam, igm1);
+      } else {
+        L = w[0];
+        R = w[1];
       }
-      hlle<2>(wl, wr, gam, fz);
+      hlle<2>(L, R, gm1, fz);
       if (m == 0 && bi.fslot[ZLO] >= 0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -215,9 +267,11 @@ __global__ void __launch_bounds__(N1 * TJ) stage_kernel(StageLaunch a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const double du = dq[0][v] + (fz[v] - fzp[v]) * bi.idx[2];
-          un[v] = base[v * vs + o] - coef * du;
+          const double ub = RECON ? base[v * vs + o] : uq[0][v];
+          un[v] = ub - coef * du;
           out[v * vs + o] = un[v];
         }
+        if (nb27) push_ghosts(a.uout, nb27, g, ti, j, k, un);
         if (a.do_dt) {
           const bool skip = ((mask >> XLO) & 1 && ti == 0) || ((mask >> XHI) & 1 && ti == N1 - 1) ||
                             ((mask >> YLO) & 1 && j == 0) || ((mask >> YHI) & 1 && j == n2 - 1) ||
@@ -225,70 +279,62 @@ __global__ void __launch_bounds__(N1 * TJ) stage_kernel(StageLaunch a) {
           if (!skip) {
             double wn[NV];
             bad |= !to_prim(un, gam, wn);
-            const double cs = sqrt(gam * wn[4] / wn[0]);
-            const double s = fmax(fmax((fabs(wn[1]) + cs) * bi.idx[0], (fabs(wn[2]) + cs) * bi.idx[1]),
-                                  (fabs(wn[3]) + cs) * bi.idx[2]);
-            smax = fmax(smax, s);
+            const double cs = fsqrt(gam * wn[4] * frcp(wn[0]));
+            const double sv = fmax(fmax((fabs(wn[1]) + cs) * bi.idx[0], (fabs(wn[2]) + cs) * bi.idx[1]),
+                                   (fabs(wn[3]) + cs) * bi.idx[2]);
+            smax = fmax(smax, sv);
           }
         }
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) fzp[v] = fz[v];
     }
-
-    // --- x and y faces of plane p, divergence into the queue
+    // --- x and y faces of plane p, divergence into the queue. Each thread
+    // solves the lower x and y faces of its cell; the tile's upper x faces
+    // (one per row) and upper y faces (one per column) are spread over the
+    // first lanes of every wave so that all waves do the same number of
+    // solves between barriers.
     if (p >= 0 && p < n3) {
-      for (int f = tid; f < NX + NY; f += NT) {
-        double wl[NV], wr[NV], fl[NV];
-        if (f < NX) {
-          const int r = f / (N1 + 1), i = f - r * (N1 + 1);
-          const int c0 = (r + NG) * P1 + i;  // cell i-2 of row r
+      // remainder jobs (the tile's upper x and y faces) go to consecutive
+      // threads starting at one wave, rotated with the plane and the
+      // workgroup so that no SIMD always gets the extra work
+      const int wr = (wg + p + 2) % NWAVE;
+      const int q = (tid - wr * 64 + NT) % NT;
+#pragma unroll 1
+      for (int slot = 0; slot < 3; ++slot) {
+        // slot 0: lower x face of the own cell; 1: lower y face; 2: upper x
+        // face of row q (q < TJ) or upper y face of column q - TJ
+        if (slot == 2 && q >= TJ + N1) break;
+        const int dir = slot == 0 ? 0 : (slot == 1 ? 1 : (q < TJ ? 0 : 1));
+        const int iy = q - TJ;
+        const int c0 = slot < 2 ? own : (dir == 0 ? (q + NG) * P1 + N1 + NG : (TJ + NG) * P1 + iy + NG);
+        FState L, R;
+        double fl[NV];
+        face_states(c0, dir == 0 ? 1 : P1, L, R);
+        hlle<-1>(L, R, gm1, fl, dir);
+        const int fo = slot < 2 ? (dir == 0 ? tj * (N1 + 1) + ti : tj * N1 + ti)
+                                : (dir == 0 ? q * (N1 + 1) + N1 : TJ * N1 + iy);
+        double* dstf = dir == 0 ? &sFx[0][fo] : &sFy[0][fo];
+        const int vstr = dir == 0 ? NX : NY;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const double qm2 = sW[v][c0], qm1 = sW[v][c0 + 1], q0 = sW[v][c0 + 2], qp1 = sW[v][c0 + 3];
-            if constexpr (RECON) {
-              wl[v] = qm1 + 0.5 * mc_slope(qm1 - qm2, q0 - qm1);
-              wr[v] = q0 - 0.5 * mc_slope(q0 - qm1, qp1 - q0);
-            } else {
-              wl[v] = qm1;
-              wr[v] = q0;
-            }
-          }
-          hlle<0>(wl, wr, gam, fl);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) sFx[v][f] = fl[v];
-          const int slot = (i == 0) ? bi.fslot[XLO] : ((i == N1) ? bi.fslot[XHI] : -1);
-          if (slot >= 0) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-              fbuf[(int64_t)slot * fsz + ((int64_t)v * n3 + p) * n2 + j0 + r] = fl[v];
-          }
+        for (int v = 0; v < NV; ++v) dstf[v * vstr] = fl[v];
+        // fine-coarse faces: keep this leaf's flux for the correction
+        int fsl = -1;
+        int64_t o = 0, vst = 0;
+        if (dir == 0) {
+          const bool lo = slot == 0 && ti == 0, hi = slot == 2;
+          fsl = lo ? bi.fslot[XLO] : (hi ? bi.fslot[XHI] : -1);
+          o = (int64_t)p * n2 + (slot == 0 ? j : j0 + q);
+          vst = (int64_t)n3 * n2;
         } else {
-          const int f2 = f - NX;
-          const int r = f2 / N1, i = f2 - r * N1;
-          const int c0 = r * P1 + i + NG;  // row r-2 of the tile, column i
+          const bool lo = slot == 1 && j == 0, hi = slot == 2 && j0 + TJ == n2;
+          fsl = lo ? bi.fslot[YLO] : (hi ? bi.fslot[YHI] : -1);
+          o = (int64_t)p * N1 + (slot == 1 ? ti : iy);
+          vst = (int64_t)n3 * N1;
+        }
+        if (fsl >= 0) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const double qm2 = sW[v][c0], qm1 = sW[v][c0 + P1], q0 = sW[v][c0 + 2 * P1],
-                         qp1 = sW[v][c0 + 3 * P1];
-            if constexpr (RECON) {
-              wl[v] = qm1 + 0.5 * mc_slope(qm1 - qm2, q0 - qm1);
-              wr[v] = q0 - 0.5 * mc_slope(q0 - qm1, qp1 - q0);
-            } else {
-              wl[v] = qm1;
-              wr[v] = q0;
-            }
-          }
-          hlle<1>(wl, wr, gam, fl);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) sFy[v][f2] = fl[v];
-          const int jf = j0 + r;
-          const int slot = (jf == 0) ? bi.fslot[YLO] : ((jf == n2) ? bi.fslot[YHI] : -1);
-          if (slot >= 0) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-              fbuf[(int64_t)slot * fsz + ((int64_t)v * n3 + p) * N1 + i] = fl[v];
-          }
+          for (int v = 0; v < NV; ++v) fbuf[(int64_t)fsl * fsz + v * vst + o] = fl[v];
         }
       }
       __syncthreads();
@@ -307,6 +353,7 @@ __global__ void __launch_bounds__(N1 * TJ) stage_kernel(StageLaunch a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
     }
+
     __syncthreads();
   }
 
@@ -338,16 +385,38 @@ static hipError_t launch_stage_n(const StageLaunch& a, hipStream_t s) {
   return a.recon ? launch_stage_t<1, N1, TJ>(a, s) : launch_stage_t<0, N1, TJ>(a, s);
 }
 
+int stage_tile_rows(int n1, int n2, int tj) {
+  // compiled (N1, TJ) variants; the first is the default
+  static const int opts[4][3] = {{8, 8, 0}, {8, 16, 4}, {8, 4, 16}, {4, 2, 0}};
+  const int row = n1 == 8 ? 0 : n1 == 16 ? 1 : n1 == 32 ? 2 : n1 == 64 ? 3 : -1;
+  if (row < 0) return -1;
+  if (tj == 0) tj = opts[row][0];
+  for (int q = 0; q < 3; ++q)
+    if (opts[row][q] == tj && tj > 0 && n2 % tj == 0) return tj;
+  return -1;
+}
+
 hipError_t launch_stage(const StageLaunch& a, hipStream_t s) {
-  switch (a.g.n1) {
-    case 8:
+  const int tj = stage_tile_rows(a.g.n1, a.g.n2, a.tj);
+  switch (a.g.n1 * 100 + tj) {
+    case 808:
       return launch_stage_n<8, 8>(a, s);
-    case 16:
+    case 1608:
       return launch_stage_n<16, 8>(a, s);
-    case 32:
+    case 1616:
+      return launch_stage_n<16, 16>(a, s);
+    case 1604:
+      return launch_stage_n<16, 4>(a, s);
+    case 3208:
       return launch_stage_n<32, 8>(a, s);
-    case 64:
+    case 3204:
+      return launch_stage_n<32, 4>(a, s);
+    case 3216:
+      return launch_stage_n<32, 16>(a, s);
+    case 6404:
       return launch_stage_n<64, 4>(a, s);
+    case 6402:
+      return launch_stage_n<64, 2>(a, s);
     default:
       return hipErrorInvalidValue;
   }
@@ -467,7 +536,7 @@ __device__ __forceinline__ void ghost_coord(int q, const Geom& g, int& i, int& j
 }
 
 __global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* blocks, int nblocks,
-                                                   Geom g, LevelMaps M, DevTime* tm) {
+                                                   Geom g, LevelMaps M, DevTime* tm, int skip_same) {
   const int ngc = 4 * g.p1 * g.p2 + 4 * g.n3 * g.p1 + 4 * g.n3 * g.n2;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
@@ -486,6 +555,7 @@ __global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* b
   double* dst = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
   const int32_t id = leaf_at(M, L, bl[0], bl[1], bl[2]);
   if (id >= 0) {  // same level: copy
+    if (skip_same) return;
     const double* src = u + (int64_t)id * g.bstride +
                         pad_index(g, J[0] - bl[0] * n[0], J[1] - bl[1] * n[1], J[2] - bl[2] * n[2]);
 #pragma unroll
@@ -504,10 +574,11 @@ __global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* b
 }
 
 hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
-                       const LevelMaps& maps, DevTime* tm, hipStream_t s) {
+                       const LevelMaps& maps, DevTime* tm, int32_t skip_same, hipStream_t s) {
   const int ngc = 4 * g.p1 * g.p2 + 4 * g.n3 * g.p1 + 4 * g.n3 * g.n2;
   dim3 grid((ngc + 255) / 256, nblocks);
-  hipLaunchKernelGGL(fill_kernel, grid, dim3(256), 0, s, u, blocks, nblocks, g, maps, tm);
+  hipLaunchKernelGGL(fill_kernel, grid, dim3(256), 0, s, u, blocks, nblocks, g, maps, tm,
+                     (int)skip_same);
   return hipGetLastError();
 }
 
@@ -525,7 +596,7 @@ __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const Bloc
                                                            const int32_t* ff_first,
                                                            const int32_t* cblocks, Geom g,
                                                            DevTime* tm, double beta, int do_dt,
-                                                           const double* fbuf) {
+                                                           const double* fbuf, const int32_t* nbr) {
   __shared__ double sRed[4];
   const int c = blockIdx.y;
   const int b = cblocks[c];
@@ -567,6 +638,7 @@ __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const Bloc
     if (touched) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) cell[v * g.vstride] = uc[v];
+      push_ghosts(u, nbr + (int64_t)b * 27, g, i, j, k, uc);
       if (do_dt) {
         double wn[NV];
         bad = !to_prim(uc, g.gamma, wn);
@@ -592,12 +664,12 @@ __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const Bloc
 hipError_t launch_flux_correct(double* u, const BlockInfo* blocks, const FineFace* ff,
                                const int32_t* ff_first, const int32_t* cblocks, int32_t ncblocks,
                                const Geom& g, DevTime* tm, double beta, int32_t do_dt,
-                               const double* fbuf, hipStream_t s) {
+                               const double* fbuf, const int32_t* nbr, hipStream_t s) {
   if (ncblocks == 0) return hipSuccess;
   const int ncell = g.n1 * g.n2 * g.n3;
   dim3 grid((ncell + 255) / 256, ncblocks);
   hipLaunchKernelGGL(flux_correct_kernel, grid, dim3(256), 0, s, u, blocks, ff, ff_first, cblocks,
-                     g, tm, beta, do_dt, fbuf);
+                     g, tm, beta, do_dt, fbuf, nbr);
   return hipGetLastError();
 }
 
@@ -817,6 +889,248 @@ hipError_t launch_regrid_data(double* unew, const BlockInfo* bnew, const int32_t
   dim3 grid((ncell + 255) / 256, nnew);
   hipLaunchKernelGGL(regrid_kernel, grid, dim3(256), 0, s, unew, bnew, kind, src, uold, bold,
                      old_maps, g, tm);
+  return hipGetLastError();
+}
+
+}  // namespace pkh
+
+// ===========================================================================
+// Reverse mode of one stage, U_out = U_base - c * D(U_in), w.r.t. U_in
+// (the identity through U_base is added by the caller): with
+// lam = dL/dU_out, the face adjoint of face f along d is
+// mu_f = c/dx_d * (lam(f) - lam(f-1)) (only the block's own active cells),
+// propagated back through HLLE, the face reconstruction and the primitive
+// recovery to the cells of the face stencil, including ghost cells; the
+// ghost contributions are then returned to the leaves they were copied
+// from (the transpose of the same-level ghost exchange).
+// ===========================================================================
+
+namespace pkh {
+
+// One thread per pencil (active transverse position) of a block along D;
+// it walks the pencil's padded cells with a window of states and a ring of
+// four cell accumulators, so each cell's primitive adjoint is complete when
+// emitted: direction 0 writes, directions 1 and 2 add on active cells and
+// write on their own ghost cells (no other pass touches those).
+template <int RECON, int D>
+__global__ void __launch_bounds__(256) adj_pencil_kernel(const double* __restrict__ U,
+                                                         const double* __restrict__ lam,
+                                                         double* __restrict__ wbar,
+                                                         const BlockInfo* blocks, int nblocks,
+                                                         Geom g, const double* dtp, double beta) {
+  const int n[3] = {g.n1, g.n2, g.n3};
+  constexpr int T1 = D == 0 ? 1 : 0, T2 = D == 2 ? 1 : 2;
+  const int nt1 = n[T1], nt2 = n[T2], nd = n[D];
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)nt1 * nt2;
+  const int b = (int)(gid / per);
+  if (b >= nblocks) return;
+  const int rem = (int)(gid - (int64_t)b * per);
+  const int a1 = rem % nt1, a2 = rem / nt1;
+  const BlockInfo bi = blocks[b];
+  const double gam = g.gamma, gm1 = gam - 1.0, igm1 = 1.0 / gm1;
+  const double coef = beta * (*dtp) * bi.idx[D];
+  const int pst[3] = {1, g.p1, g.p1 * g.p2};  // padded strides
+  const int ast[3] = {1, g.n1, g.n1 * g.n2};  // active strides
+  int c3[3];
+  c3[T1] = a1;
+  c3[T2] = a2;
+  c3[D] = 0;
+  const int64_t pbase = (int64_t)b * g.bstride + ((int64_t)(c3[2] + NG) * g.p2 + (c3[1] + NG)) * g.p1 +
+                        (c3[0] + NG);  // padded index of the pencil's cell 0
+  const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
+  const int64_t abase = (int64_t)b * NV * ncell + (int64_t)c3[2] * ast[2] + (int64_t)c3[1] * ast[1] + c3[0];
+  const int ps = pst[D], as = ast[D];
+
+  auto loadw = [&](int s, double w[NV]) {
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[pbase + (int64_t)v * g.vstride + (int64_t)s * ps];
+    to_prim(u, gam, w);
+  };
+  auto loadl = [&](int s, double l[NV]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) l[v] = (s >= 0 && s < nd) ? lam[abase + (int64_t)v * ncell + (int64_t)s * as] : 0.0;
+  };
+  auto emit = [&](int s, const double acc[NV]) {
+    const bool active = s >= 0 && s < nd;
+    double* o = wbar + pbase + (int64_t)s * ps;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (D != 0 && active)
+        o[(int64_t)v * g.vstride] += acc[v];
+      else
+        o[(int64_t)v * g.vstride] = acc[v];
+    }
+  };
+
+  double W[4][NV];   // states of cells f-2 .. f+1
+  double acc[4][NV]; // adjoints of cells f-2 .. f+1
+  double lm1[NV], l0[NV];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[k][v] = W[k][v] = 0.0;
+  loadw(-2, W[1]);
+  loadw(-1, W[2]);
+  loadw(0, W[3]);
+  loadl(-1, l0);
+  for (int f = 0; f <= nd; ++f) {
+    // shift the state window to cells f-2 .. f+1
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) W[k][v] = W[k + 1][v];
+    loadw(f + 1, W[3]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lm1[v] = l0[v];
+    loadl(f, l0);
+    double mu[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mu[v] = coef * (l0[v] - lm1[v]);
+    double gl[NV] = {0, 0, 0, 0, 0}, gr[NV] = {0, 0, 0, 0, 0};
+    FState L, R;
+    double wl[NV], wr[NV];
+    if constexpr (RECON) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        wl[v] = W[1][v] + 0.5 * mc_slope(W[1][v] - W[0][v], W[2][v] - W[1][v]);
+        wr[v] = W[2][v] - 0.5 * mc_slope(W[2][v] - W[1][v], W[3][v] - W[2][v]);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        wl[v] = W[1][v];
+        wr[v] = W[2][v];
+      }
+    }
+    L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+    R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+    complete_state(L, gam, igm1);
+    complete_state(R, gam, igm1);
+    double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    hlle_rev<D>(L, R, gm1, mu, gL, gR);
+    complete_state_rev(L, gam, igm1, gL, gl);
+    complete_state_rev(R, gam, igm1, gR, gr);
+    if constexpr (RECON) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double ga, gb;
+        mc_branch(W[1][v] - W[0][v], W[2][v] - W[1][v], ga, gb);
+        acc[1][v] += gl[v] * (1.0 + 0.5 * ga - 0.5 * gb);
+        acc[0][v] -= gl[v] * 0.5 * ga;
+        acc[2][v] += gl[v] * 0.5 * gb;
+        mc_branch(W[2][v] - W[1][v], W[3][v] - W[2][v], ga, gb);
+        acc[2][v] += gr[v] * (1.0 - 0.5 * ga + 0.5 * gb);
+        acc[1][v] += gr[v] * 0.5 * ga;
+        acc[3][v] -= gr[v] * 0.5 * gb;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        acc[1][v] += gl[v];
+        acc[2][v] += gr[v];
+      }
+    }
+    emit(f - 2, acc[0]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[k][v] = acc[k + 1][v];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[3][v] = 0.0;
+  }
+  emit(nd - 1, acc[0]);
+  emit(nd, acc[1]);
+  emit(nd + 1, acc[2]);
+}
+
+// Transposed ghost exchange and primitive-to-conserved adjoint, one thread
+// per active cell: the cell's own primitive adjoint plus those of its ghost
+// copies in the face neighbours, mapped through the primitive recovery at
+// the cell's state, plus optional addends.
+__global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restrict__ wbar,
+                                                           const double* __restrict__ U,
+                                                           const int32_t* __restrict__ nbr, Geom g,
+                                                           int64_t total, double* out,
+                                                           const double* add0, const double* add1) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= total) return;
+  const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
+  const int b = (int)(q / ncell);
+  const int c = (int)(q - (int64_t)b * ncell);
+  const int i = c % g.n1, j = (c / g.n1) % g.n2, k = c / (g.n1 * g.n2);
+  const int32_t* nb27 = nbr + (int64_t)b * 27;
+  double gw[NV];
+  const int64_t own = (int64_t)b * g.bstride + pad_index(g, i, j, k);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) gw[v] = wbar[own + (int64_t)v * g.vstride];
+  auto add_copy = [&](int dx, int dy, int dz) {
+    const int32_t nb = nb27[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
+    if (nb < 0) return;
+    const int64_t o = (int64_t)nb * g.bstride + pad_index(g, i - dx * g.n1, j - dy * g.n2, k - dz * g.n3);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gw[v] += wbar[o + (int64_t)v * g.vstride];
+  };
+  if (i < NG) add_copy(-1, 0, 0);
+  if (i >= g.n1 - NG) add_copy(1, 0, 0);
+  if (j < NG) add_copy(0, -1, 0);
+  if (j >= g.n2 - NG) add_copy(0, 1, 0);
+  if (k < NG) add_copy(0, 0, -1);
+  if (k >= g.n3 - NG) add_copy(0, 0, 1);
+  double u[NV], gu[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = U[own + (int64_t)v * g.vstride];
+  prim_rev(u, g.gamma, gw, gu);
+  const int64_t ao = (int64_t)b * NV * ncell + c;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double r = gu[v];
+    if (add0) r += add0[ao + v * ncell];
+    if (add1) r += add1[ao + v * ncell];
+    out[ao + v * ncell] = r;
+  }
+}
+
+template <int RECON>
+static hipError_t launch_adj_pencils(const double* U, const double* lam, double* wbar,
+                                     const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                                     const double* dtp, double beta, hipStream_t s) {
+  const int64_t npen[3] = {(int64_t)g.n2 * g.n3, (int64_t)g.n1 * g.n3, (int64_t)g.n1 * g.n2};
+  dim3 blk(256);
+  hipLaunchKernelGGL((adj_pencil_kernel<RECON, 0>), dim3((unsigned)((npen[0] * nblocks + 255) / 256)), blk,
+                     0, s, U, lam, wbar, blocks, nblocks, g, dtp, beta);
+  hipLaunchKernelGGL((adj_pencil_kernel<RECON, 1>), dim3((unsigned)((npen[1] * nblocks + 255) / 256)), blk,
+                     0, s, U, lam, wbar, blocks, nblocks, g, dtp, beta);
+  hipLaunchKernelGGL((adj_pencil_kernel<RECON, 2>), dim3((unsigned)((npen[2] * nblocks + 255) / 256)), blk,
+                     0, s, U, lam, wbar, blocks, nblocks, g, dtp, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar,
+                            const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                            const int32_t* nbr, const double* dtp, double beta, double* out,
+                            const double* add0, const double* add1, hipStream_t s) {
+  hipError_t e = recon ? launch_adj_pencils<1>(U, lam, wbar, blocks, nblocks, g, dtp, beta, s)
+                       : launch_adj_pencils<0>(U, lam, wbar, blocks, nblocks, g, dtp, beta, s);
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)nblocks * g.n1 * g.n2 * g.n3;
+  hipLaunchKernelGGL(adj_exchange_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, wbar,
+                     U, nbr, g, total, out, add0, add1);
+  return hipGetLastError();
+}
+
+// Device clock for recomputation: dt of the current cycle from a record.
+__global__ void tape_dt_kernel(DevTime* tm, const double* dts, int c, int record) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (record)
+    const_cast<double*>(dts)[c] = tm->dt;
+  else
+    tm->dt = dts[c];
+}
+
+hipError_t launch_tape_dt(DevTime* tm, double* dts, int32_t c, int32_t record, hipStream_t s) {
+  hipLaunchKernelGGL(tape_dt_kernel, dim3(1), dim3(64), 0, s, tm, (const double*)dts, (int)c, (int)record);
   return hipGetLastError();
 }
 

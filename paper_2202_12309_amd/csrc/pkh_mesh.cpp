@@ -186,6 +186,8 @@ struct pkh_mesh {
   int32_t* d_ff_first = nullptr;
   int32_t* d_cblocks = nullptr;
   int32_t ncblocks = 0;
+  int32_t* d_nbr = nullptr;   // [leaf][27] same-level neighbours (-1: other level)
+  bool need_fill = false;     // some ghost region has a neighbour at another level
   double* d_partial = nullptr;
   double* d_tot = nullptr;
   size_t partial_cap = 0;
@@ -193,6 +195,11 @@ struct pkh_mesh {
   std::vector<int8_t> flags;
   bool ghosts_valid = false;
   int32_t tj = 0;
+  // kernel timing: event pairs around launches of the selected kinds
+  uint32_t kt_mask = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::array<int64_t, 3>> kt_rec;  // kind, start event, end event
   // captured cycles
   hipGraphExec_t gexec = nullptr;
   int32_t g_cycles = 0;
@@ -233,6 +240,8 @@ void free_tables(pkh_mesh* m) {
   m->dfree(m->d_ff);
   m->dfree(m->d_ff_first);
   m->dfree(m->d_cblocks);
+  m->dfree(m->d_nbr);
+  m->d_nbr = nullptr;
   m->d_blocks = nullptr;
   m->d_map = nullptr;
   m->d_fbuf = nullptr;
@@ -321,6 +330,20 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
   ff_first.push_back((int32_t)ff.size());
   for (int64_t b = 0; b < nb; ++b)
     for (int f = 0; f < 6; ++f) hb[b].fslot[f] = slot_of[b][f];
+  // same-level neighbour table
+  std::vector<int32_t> nbr(nb * 27, -1);
+  bool need_fill = false;
+  for (int64_t b = 0; b < nb; ++b) {
+    const pkh_loc& l = t.leaves[b];
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (!dx && !dy && !dz) continue;
+          const int32_t id = t.at(l.level, l.lx1 + dx, l.lx2 + dy, l.lx3 + dz);
+          nbr[b * 27 + (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] = id;
+          if (id < 0) need_fill = true;
+        }
+  }
   // level maps
   std::vector<int32_t> flat;
   for (int L = 0; L <= t.maxl; ++L) {
@@ -343,6 +366,8 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
     if ((rc = upload_vec(m, &m->d_ff_first, ff_first))) return rc;
     if ((rc = upload_vec(m, &m->d_cblocks, cblocks))) return rc;
     m->ncblocks = (int32_t)cblocks.size();
+    if ((rc = upload_vec(m, &m->d_nbr, nbr))) return rc;
+    m->need_fill = need_fill;
   }
   // the host vectors above are sources of asynchronous copies
   HIPCHK(hipStreamSynchronize(m->stream));
@@ -369,7 +394,7 @@ int check_err(pkh_mesh* m) {
 }
 
 int do_exchange(pkh_mesh* m) {
-  HIPCHK(launch_fill(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->maps, m->d_time, m->stream));
+  HIPCHK(launch_fill(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->maps, m->d_time, 0, m->stream));
   HIPCHK(hipMemsetAsync(&m->d_time->smax_bits, 0, sizeof(unsigned long long), m->stream));
   HIPCHK(launch_dt(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->d_time, m->stream));
   HIPCHK(launch_clock(m->d_time, CLOCK_FROM_SMAX, NAN, m->stream));
@@ -377,8 +402,40 @@ int do_exchange(pkh_mesh* m) {
   return PKH_OK;
 }
 
+hipEvent_t next_event(pkh_mesh* m) {
+  if (m->ev_used == m->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    m->ev_pool.push_back(e);
+  }
+  return m->ev_pool[m->ev_used++];
+}
+
+// Bracket a launch of kind index k with events when timing is on and the
+// stream is not being captured.
+struct KTimer {
+  pkh_mesh* m;
+  int k;
+  int64_t s = -1;
+  bool on;
+  KTimer(pkh_mesh* mm, int kind, bool capturing) : m(mm), k(kind) {
+    on = !capturing && ((m->kt_mask >> k) & 1u);
+    if (on) {
+      hipEvent_t e = next_event(m);
+      if (e && hipEventRecord(e, m->stream) == hipSuccess) s = (int64_t)(m->ev_used - 1);
+    }
+  }
+  ~KTimer() {
+    if (on && s >= 0) {
+      hipEvent_t e = next_event(m);
+      if (e && hipEventRecord(e, m->stream) == hipSuccess)
+        m->kt_rec.push_back({k, s, (int64_t)(m->ev_used - 1)});
+    }
+  }
+};
+
 // One cycle's kernels (the clock BEGIN of the cycle has been enqueued).
-int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end) {
+int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = false) {
   const int32_t nb = (int32_t)m->nb();
   StageLaunch s{};
   s.blocks = m->d_blocks;
@@ -386,6 +443,7 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end) {
   s.g = m->g;
   s.tm = m->d_time;
   s.fbuf = m->d_fbuf;
+  s.nbr = m->d_nbr;
   s.tj = m->tj;
   // predictor: U* = U^n - dt/2 D(U^n)
   s.uin = m->A;
@@ -394,10 +452,20 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end) {
   s.beta = 0.5;
   s.recon = m->cfg.stage1_recon;
   s.do_dt = 0;
-  HIPCHK(launch_stage(s, m->stream));
-  HIPCHK(launch_flux_correct(m->B, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks, m->ncblocks,
-                             m->g, m->d_time, 0.5, 0, m->d_fbuf, m->stream));
-  HIPCHK(launch_fill(m->B, m->d_blocks, nb, m->g, m->maps, m->d_time, m->stream));
+  {
+    KTimer kt(m, 0, capturing);
+    HIPCHK(launch_stage(s, m->stream));
+  }
+  if (m->ncblocks) {
+    KTimer kt(m, 3, capturing);
+    HIPCHK(launch_flux_correct(m->B, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks,
+                               m->ncblocks, m->g, m->d_time, 0.5, 0, m->d_fbuf, m->d_nbr,
+                               m->stream));
+  }
+  if (m->need_fill) {  // same-level ghosts were written by the stage kernel
+    KTimer kt(m, 2, capturing);
+    HIPCHK(launch_fill(m->B, m->d_blocks, nb, m->g, m->maps, m->d_time, 1, m->stream));
+  }
   // corrector: U^{n+1} = U^n - dt D_PLM(U*), in place; CFL reduction fused
   s.uin = m->B;
   s.ubase = m->A;
@@ -405,10 +473,20 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end) {
   s.beta = 1.0;
   s.recon = PKH_RECON_PLM;
   s.do_dt = 1;
-  HIPCHK(launch_stage(s, m->stream));
-  HIPCHK(launch_flux_correct(m->A, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks, m->ncblocks,
-                             m->g, m->d_time, 1.0, 1, m->d_fbuf, m->stream));
-  HIPCHK(launch_fill(m->A, m->d_blocks, nb, m->g, m->maps, m->d_time, m->stream));
+  {
+    KTimer kt(m, 1, capturing);
+    HIPCHK(launch_stage(s, m->stream));
+  }
+  if (m->ncblocks) {
+    KTimer kt(m, 3, capturing);
+    HIPCHK(launch_flux_correct(m->A, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks,
+                               m->ncblocks, m->g, m->d_time, 1.0, 1, m->d_fbuf, m->d_nbr,
+                               m->stream));
+  }
+  if (m->need_fill) {
+    KTimer kt(m, 2, capturing);
+    HIPCHK(launch_fill(m->A, m->d_blocks, nb, m->g, m->maps, m->d_time, 1, m->stream));
+  }
   HIPCHK(launch_clock(m->d_time, mode_after, t_end, m->stream));
   return PKH_OK;
 }
@@ -521,6 +599,7 @@ int pkh_mesh_destroy(pkh_mesh* m) {
   if (!m) return PKH_OK;
   (void)hipStreamSynchronize(m->stream);
   drop_graph(m);
+  for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   free_tables(m);
   m->dfree(m->A);
   m->dfree(m->B);
@@ -602,7 +681,7 @@ int pkh_step(pkh_mesh* m, int32_t n_cycles, double t_end) {
     drop_graph(m);
     hipGraph_t graph_h = nullptr;
     HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_cycle(m, CLOCK_END | CLOCK_BEGIN, t_end);
+    rc = enqueue_cycle(m, CLOCK_END | CLOCK_BEGIN, t_end, true);
     hipError_t e = hipStreamEndCapture(m->stream, &graph_h);
     if (rc) return rc;
     if (e != hipSuccess) return fail(PKH_EHIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -764,10 +843,12 @@ int pkh_regrid(pkh_mesh* m) {
   m->dfree(m->d_ff);
   m->dfree(m->d_ff_first);
   m->dfree(m->d_cblocks);
+  m->dfree(m->d_nbr);
   m->d_fbuf = nullptr;
   m->d_ff = nullptr;
   m->d_ff_first = nullptr;
   m->d_cblocks = nullptr;
+  m->d_nbr = nullptr;
   m->tree = std::move(nt);
   int32_t *d_kind = nullptr, *d_src = nullptr;
   if ((rc = build_tables(m, m->h_blocks, &m->d_map, m->maps)) || (rc = alloc_state(m)) ||
@@ -792,6 +873,248 @@ int pkh_conserved_totals(pkh_mesh* m, double out[5]) {
   HIPCHK(launch_totals(m->d_partial, m->d_tot, m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->stream));
   HIPCHK(hipMemcpyAsync(out, m->d_tot, NV * sizeof(double), hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
+  return check_err(m);
+}
+
+int pkh_set_tuning(pkh_mesh* m, const pkh_tuning* t) {
+  if (!m || !t) return fail(PKH_EINVAL, "null argument");
+  if (stage_tile_rows(m->g.n1, m->g.n2, t->tile_rows) < 0)
+    return fail(PKH_EINVAL, "tile_rows %d not available for blocks of %d x %d", t->tile_rows, m->g.n1,
+                m->g.n2);
+  if (t->tile_rows != m->tj) drop_graph(m);
+  m->tj = t->tile_rows;
+  return PKH_OK;
+}
+
+int pkh_get_tuning(const pkh_mesh* m, pkh_tuning* t) {
+  if (!m || !t) return fail(PKH_EINVAL, "null argument");
+  *t = pkh_tuning{};
+  t->tile_rows = stage_tile_rows(m->g.n1, m->g.n2, m->tj);
+  return PKH_OK;
+}
+
+int pkh_kernel_timing(pkh_mesh* m, uint32_t kinds) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  HIPCHK(hipStreamSynchronize(m->stream));
+  m->kt_mask = kinds & 31u;
+  m->kt_rec.clear();
+  m->ev_used = 0;
+  return PKH_OK;
+}
+
+int pkh_kernel_times(pkh_mesh* m, double* ms, int64_t* count) {
+  if (!m || !ms || !count) return fail(PKH_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(m->stream));
+  for (int k = 0; k < 5; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  for (const auto& r : m->kt_rec) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, m->ev_pool[r[1]], m->ev_pool[r[2]]));
+    ms[r[0]] += t;
+    count[r[0]] += 1;
+  }
+  return PKH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct pkh_tape {
+  pkh_mesh* m = nullptr;
+  int32_t K = 1;                 // checkpoint interval
+  int32_t ncycles = 0;           // recorded cycles
+  std::vector<double*> ckpt;     // active-layout states at cycles 0, K, 2K, ...
+  double* d_dts = nullptr;       // dt of every recorded cycle
+  int32_t dts_cap = 0;
+  std::vector<double*> S;        // recomputed ghost-filled U^n, K + 1 of them
+  std::vector<double*> Us;       // recomputed ghost-filled U*, K of them
+  double* wbar = nullptr;        // padded primitive-adjoint scratch
+  double* lam[3] = {nullptr, nullptr, nullptr};  // active-layout adjoints
+  DevTime* d_time = nullptr;     // clock for recomputation (dt from the record)
+};
+
+namespace {
+size_t active_bytes(const pkh_mesh* m) {
+  return (size_t)m->nb() * NV * m->g.n1 * m->g.n2 * m->g.n3 * sizeof(double);
+}
+
+void tape_free(pkh_tape* t) {
+  pkh_mesh* m = t->m;
+  for (double* p : t->ckpt) m->dfree(p);
+  for (double* p : t->S) m->dfree(p);
+  for (double* p : t->Us) m->dfree(p);
+  t->ckpt.clear();
+  t->S.clear();
+  t->Us.clear();
+  m->dfree(t->d_dts);
+  m->dfree(t->wbar);
+  for (auto& l : t->lam) m->dfree(l);
+  m->dfree(t->d_time);
+  t->d_dts = nullptr;
+  t->wbar = nullptr;
+  t->d_time = nullptr;
+  for (auto& l : t->lam) l = nullptr;
+}
+
+// Ghost-filled recomputation of cycle inputs S[0..len] and U*[0..len-1]
+// from the checkpoint of a segment starting at cycle c0.
+int tape_recompute(pkh_tape* t, int c0, int len) {
+  pkh_mesh* m = t->m;
+  const int32_t nb = (int32_t)m->nb();
+  HIPCHK(launch_scatter(t->S[0], t->ckpt[c0 / t->K], nb, m->g, m->stream));
+  HIPCHK(launch_fill(t->S[0], m->d_blocks, nb, m->g, m->maps, t->d_time, 0, m->stream));
+  StageLaunch s{};
+  s.blocks = m->d_blocks;
+  s.nblocks = nb;
+  s.g = m->g;
+  s.tm = t->d_time;
+  s.fbuf = m->d_fbuf;
+  s.nbr = m->d_nbr;
+  s.tj = m->tj;
+  s.do_dt = 0;
+  for (int q = 0; q < len; ++q) {
+    HIPCHK(launch_tape_dt(t->d_time, t->d_dts, c0 + q, 0, m->stream));
+    s.uin = t->S[q];
+    s.ubase = t->S[q];
+    s.uout = t->Us[q];
+    s.beta = 0.5;
+    s.recon = m->cfg.stage1_recon;
+    HIPCHK(launch_stage(s, m->stream));
+    s.uin = t->Us[q];
+    s.ubase = t->S[q];
+    s.uout = t->S[q + 1];
+    s.beta = 1.0;
+    s.recon = PKH_RECON_PLM;
+    HIPCHK(launch_stage(s, m->stream));
+  }
+  return PKH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
+  if (!m || !out || ckpt_every < 1) return fail(PKH_EINVAL, "bad argument");
+  *out = nullptr;
+  if (m->need_fill || m->ncblocks)
+    return fail(PKH_EINVAL, "the reverse mode supports single-level meshes only");
+  pkh_tape* t = new pkh_tape();
+  t->m = m;
+  t->K = ckpt_every;
+  const size_t pb = m->state_bytes();
+  bool ok = true;
+  for (int q = 0; q <= ckpt_every && ok; ++q) {
+    t->S.push_back((double*)m->dalloc(pb));
+    ok = t->S.back() != nullptr;
+  }
+  for (int q = 0; q < ckpt_every && ok; ++q) {
+    t->Us.push_back((double*)m->dalloc(pb));
+    ok = t->Us.back() != nullptr;
+  }
+  if (ok) {
+    t->wbar = (double*)m->dalloc(pb);
+    for (auto& l : t->lam) l = (double*)m->dalloc(active_bytes(m));
+    t->d_time = (DevTime*)m->dalloc(sizeof(DevTime));
+    ok = t->wbar && t->lam[0] && t->lam[1] && t->lam[2] && t->d_time;
+  }
+  if (!ok) {
+    tape_free(t);
+    delete t;
+    return fail(PKH_ENOMEM, "tape allocation failed");
+  }
+  // ghost zones of the recomputation buffers start defined
+  for (double* p : t->S) HIPCHK(hipMemsetAsync(p, 0, pb, m->stream));
+  for (double* p : t->Us) HIPCHK(hipMemsetAsync(p, 0, pb, m->stream));
+  HIPCHK(hipMemcpyAsync(t->d_time, m->d_time, sizeof(DevTime), hipMemcpyDeviceToDevice, m->stream));
+  *out = t;
+  return PKH_OK;
+}
+
+int pkh_tape_destroy(pkh_tape* t) {
+  if (!t) return PKH_OK;
+  (void)hipStreamSynchronize(t->m->stream);
+  tape_free(t);
+  delete t;
+  return PKH_OK;
+}
+
+int pkh_forward_taped(pkh_mesh* m, pkh_tape* t, int32_t n) {
+  if (!m || !t || t->m != m || n < 1) return fail(PKH_EINVAL, "bad argument");
+  int rc;
+  if (!m->ghosts_valid && (rc = do_exchange(m))) return rc;
+  const int nck = (n + t->K - 1) / t->K;
+  HIPCHK(hipStreamSynchronize(m->stream));
+  for (double* p : t->ckpt) m->dfree(p);
+  t->ckpt.clear();
+  for (int q = 0; q < nck; ++q) {
+    t->ckpt.push_back((double*)m->dalloc(active_bytes(m)));
+    if (!t->ckpt.back()) return fail(PKH_ENOMEM, "checkpoint allocation failed");
+  }
+  if (t->dts_cap < n) {
+    m->dfree(t->d_dts);
+    t->d_dts = (double*)m->dalloc((size_t)n * sizeof(double));
+    if (!t->d_dts) return fail(PKH_ENOMEM, "allocation failed");
+    t->dts_cap = n;
+  }
+  t->ncycles = n;
+  HIPCHK(launch_clock(m->d_time, CLOCK_BEGIN, INFINITY, m->stream));
+  for (int c = 0; c < n; ++c) {
+    if (c % t->K == 0) HIPCHK(launch_gather(t->ckpt[c / t->K], m->A, (int32_t)m->nb(), m->g, m->stream));
+    HIPCHK(launch_tape_dt(m->d_time, t->d_dts, c, 1, m->stream));
+    if ((rc = enqueue_cycle(m, c + 1 < n ? (CLOCK_END | CLOCK_BEGIN) : CLOCK_END, INFINITY))) return rc;
+  }
+  return PKH_OK;
+}
+
+int pkh_tape_replay(pkh_mesh* m, pkh_tape* t) {
+  if (!m || !t || t->m != m) return fail(PKH_EINVAL, "bad argument");
+  if (t->ncycles < 1) return fail(PKH_ESTATE, "nothing recorded on the tape");
+  int rc;
+  if (!m->ghosts_valid && (rc = do_exchange(m))) return rc;
+  for (int c = 0; c < t->ncycles; ++c) {
+    HIPCHK(launch_tape_dt(m->d_time, t->d_dts, c, 0, m->stream));
+    if ((rc = enqueue_cycle(m, CLOCK_END, INFINITY))) return rc;
+  }
+  return PKH_OK;
+}
+
+int pkh_adjoint(pkh_mesh* m, pkh_tape* t, const double* lam_final, double* grad_init) {
+  if (!m || !t || t->m != m || !lam_final || !grad_init) return fail(PKH_EINVAL, "bad argument");
+  if (t->ncycles < 1) return fail(PKH_ESTATE, "nothing recorded on the tape");
+  const int32_t nb = (int32_t)m->nb();
+  int rc;
+  double* lam = t->lam[0];
+  double* lam_star = t->lam[1];
+  double* lam_new = t->lam[2];
+  HIPCHK(hipMemcpyAsync(lam, lam_final, active_bytes(m), hipMemcpyDeviceToDevice, m->stream));
+  const int nseg = (t->ncycles + t->K - 1) / t->K;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int c0 = seg * t->K;
+    const int len = std::min(t->K, t->ncycles - c0);
+    if ((rc = tape_recompute(t, c0, len))) return rc;
+    for (int q = len - 1; q >= 0; --q) {
+      const double* dtp = t->d_dts + c0 + q;
+      {  // corrector: lam* = (dU^{n+1}/dU*)^T lam
+        KTimer kt(m, 4, false);
+        HIPCHK(launch_adj_stage(PKH_RECON_PLM, t->Us[q], lam, t->wbar, m->d_blocks, nb, m->g, m->d_nbr,
+                                dtp, 1.0, lam_star, nullptr, nullptr, m->stream));
+      }
+      {  // predictor and the identities: lam^n = lam + lam* + (dU*/dU^n)^T-term of lam*
+        KTimer kt(m, 4, false);
+        HIPCHK(launch_adj_stage(m->cfg.stage1_recon, t->S[q], lam_star, t->wbar, m->d_blocks, nb, m->g,
+                                m->d_nbr, dtp, 0.5, lam_new, lam, lam_star, m->stream));
+      }
+      std::swap(lam, lam_new);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(grad_init, lam, active_bytes(m), hipMemcpyDeviceToDevice, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  t->lam[0] = lam;
+  t->lam[2] = lam_new;
   return check_err(m);
 }
 
