@@ -116,6 +116,46 @@ def adjoint_ratio(cycles=50, ckpt=10):
             "gradient_over_forward": round(t_adj / t_fwd, 3)}
 
 
+def batch_leg(cycles=50):
+    """64 independent FP64 periodic instances (edges 32..128, blocks 16^3 or
+    32^3, sound-wave or blast initial conditions; seed 4): aggregate
+    zone-cycles/s of the plain per-instance launches, the grouped launches,
+    the captured-graph replays, and the graph after autotuning."""
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Batch, Mesh
+    specs = inputs.batch_mix(n=64, seed=4)
+    stream = torch.cuda.Stream()
+    meshes = []
+    cells = 0
+    for sp in specs:
+        n = (sp["blk"],) * 3
+        nrb = (sp["N"] // sp["blk"],) * 3
+        m = Mesh((sp["N"],) * 3, n, inputs.uniform_leaves(nrb), stream=stream)
+        m.upload(inputs.batch_state(sp, m.leaves()))
+        meshes.append(m)
+        cells += sp["N"] ** 3
+    b = Batch(meshes)
+    out = {"workload": "64 instances, edges 32..128, blocks 16^3/32^3, wave or blast, seed 4",
+           "cells": cells, "cycles_timed": cycles}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for label, mode, tune in (("plain", "plain", False), ("fused", "fused", False),
+                              ("graph", "graph", False), ("graph_autotuned", "graph", True)):
+        if tune:
+            out["autotuned_tile_rows"] = sorted(set(b.autotune(3)))
+        b.step(cycles, mode)  # warm-up (and graph capture)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        b.step(cycles, mode)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        out[label] = cells * cycles / (ms / 1e3)
+    out["speedup_graph_vs_plain"] = out["graph_autotuned"] / out["plain"]
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +166,7 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0, help="stage-kernel tile rows (0: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (the HBM-counter calibration kernel)")
     args = ap.parse_args()
@@ -212,14 +253,19 @@ def main():
         "sim_time": t,
         "adjoint_forward_ratio": None,
         "adjoint": None,
+        "batch": None,
         "roofline": roof,
     }
     if not args.no_adjoint:
         adj = adjoint_ratio()
         out["adjoint"] = adj
         out["adjoint_forward_ratio"] = adj["reverse_sweep_over_forward"]
-    if not args.no_cpu_baseline:
+    if not args.no_batch:
         del mesh
+        torch.cuda.empty_cache()
+        out["batch"] = batch_leg()
+    if not args.no_cpu_baseline:
+        mesh = None
         out["cpu_baseline"] = cpu_baseline(blk)
     print(json.dumps(out))
 

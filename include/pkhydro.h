@@ -209,6 +209,27 @@ int pkh_tape_replay(pkh_mesh *mesh, pkh_tape *tape);
    Enqueued on the mesh's stream; synchronises at the end. */
 int pkh_adjoint(pkh_mesh *mesh, pkh_tape *tape, const double *lam_final, double *grad_init);
 
+/* ---- Batches: many independent single-level meshes advanced together
+   (each keeps its own t and dt). The meshes must share one HIP stream. ---- */
+typedef struct pkh_batch pkh_batch;
+enum {
+  PKH_PLAIN = 0, /* per mesh and cycle: the mesh's own launches (pkh_step) */
+  PKH_FUSED = 1, /* per cycle: one grouped launch per stage and tile shape over
+                    every mesh's tiles, one clock launch for all meshes */
+  PKH_GRAPH = 2  /* PKH_FUSED with segments of up to 50 cycles replayed from a
+                    captured hipGraph */
+};
+/* The results of the three modes are bitwise identical. */
+int pkh_batch_create(pkh_mesh *const *meshes, int32_t n, pkh_batch **out);
+int pkh_batch_destroy(pkh_batch *batch);
+int pkh_batch_step(pkh_batch *batch, int32_t n_cycles, uint32_t mode);
+/* Autotune: for each group of meshes with the same block width, time every
+   compiled tile-rows choice over `trial_cycles` fused cycles (the meshes'
+   states and clocks are saved and restored around the trials) and keep the
+   fastest; writes the chosen tile rows per mesh into tile_rows[n] if not
+   NULL. Synchronises. */
+int pkh_batch_autotune(pkh_batch *batch, int32_t trial_cycles, int32_t *tile_rows);
+
 /* Launch tuning of the stage kernels (set by the caller or an autotuner).
    tile_rows: rows of cells per workgroup tile (0 = default). Compiled
    choices: n1 = 8: 8; n1 = 16: 8, 16, 4; n1 = 32: 8, 4, 16; n1 = 64: 4, 2.
@@ -220,6 +241,10 @@ typedef struct {
 } pkh_tuning;
 int pkh_set_tuning(pkh_mesh *mesh, const pkh_tuning *tuning);
 int pkh_get_tuning(const pkh_mesh *mesh, pkh_tuning *tuning);
+
+/* Autotune one mesh the same way (states saved and restored); writes the
+   chosen tuning to *out if not NULL. */
+int pkh_autotune(pkh_mesh *mesh, int32_t trial_cycles, pkh_tuning *out);
 
 /* Kernel timing with HIP events on the handle's stream (a measurement aid
    for the roofline report). `kinds` is a mask of PKH_KT_* bits; while it is

@@ -75,6 +75,11 @@ _SIGS = {
     "pkh_forward_taped": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
     "pkh_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pkh_tape_replay": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pkh_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "pkh_batch_destroy": (C.c_int, [C.c_void_p]),
+    "pkh_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32]),
+    "pkh_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "pkh_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
 }
 
 
@@ -271,6 +276,13 @@ class Mesh:
         t.tile_rows = int(tile_rows)
         _check(lib().pkh_set_tuning(self._h, C.byref(t)))
 
+    def autotune(self, trial_cycles=3):
+        """Time every compiled tile-rows choice and keep the fastest (state
+        and clock restored afterwards)."""
+        t = Tuning()
+        _check(lib().pkh_autotune(self._h, int(trial_cycles), C.byref(t)))
+        return {"tile_rows": t.tile_rows}
+
     def tuning(self):
         t = Tuning()
         _check(lib().pkh_get_tuning(self._h, C.byref(t)))
@@ -378,3 +390,39 @@ def euler_vl2(U0, mesh, n_cycles, ckpt_every=10):
     if _EULER_FN is None:
         _EULER_FN = _euler_vl2_function()
     return _EULER_FN.apply(U0, mesh, int(n_cycles), int(ckpt_every))
+
+
+BATCH_MODES = {"plain": 0, "fused": 1, "graph": 2}
+
+
+class Batch:
+    """Independent single-level meshes advanced together (they must share a
+    stream). Modes: 'plain' (each mesh's own launches), 'fused' (grouped
+    launches over every mesh's tiles), 'graph' (fused, replayed from captured
+    50-cycle hipGraphs); bitwise identical results."""
+
+    def __init__(self, meshes):
+        self.meshes = list(meshes)
+        arr = (C.c_void_p * len(self.meshes))(*[m._h.value for m in self.meshes])
+        h = C.c_void_p()
+        _check(lib().pkh_batch_create(arr, len(self.meshes), C.byref(h)))
+        self._h = h
+
+    def step(self, n_cycles, mode="fused"):
+        _check(lib().pkh_batch_step(self._h, int(n_cycles), BATCH_MODES[mode]))
+
+    def autotune(self, trial_cycles=3):
+        out = (C.c_int32 * len(self.meshes))()
+        _check(lib().pkh_batch_autotune(self._h, int(trial_cycles), out))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pkh_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

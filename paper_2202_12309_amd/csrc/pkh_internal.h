@@ -86,6 +86,14 @@ struct StageLaunch {
 };
 
 hipError_t launch_stage(const StageLaunch& a, hipStream_t s);
+// One work item of a grouped stage launch over many meshes.
+struct GroupItem {
+  int32_t inst, blk, j0, pad;
+};
+// Grouped launch of the stage over the items of meshes that share block
+// width n1 and tile rows tj; insts/items are device arrays.
+hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
+                              const GroupItem* items, int nitems, hipStream_t s);
 // Rows per workgroup tile actually used for a block of n1 x n2 cells and a
 // requested value (0: default); -1 if no compiled variant fits.
 int stage_tile_rows(int n1, int n2, int tj);
@@ -123,6 +131,10 @@ hipError_t launch_adj_stage(int recon, const double* U, const double* lam, doubl
                             const double* add0, const double* add1, hipStream_t s);
 // record: dts[c] = tm->dt; else tm->dt = dts[c].
 hipError_t launch_tape_dt(DevTime* tm, double* dts, int32_t c, int32_t record, hipStream_t s);
+
+// Clocks of many meshes in one launch; tms is a device array of n pointers.
+hipError_t launch_clock_group(DevTime* const* tms, int32_t n, int32_t mode, double t_end,
+                              hipStream_t s);
 
 // Clock modes
 enum : int { CLOCK_END = 1, CLOCK_BEGIN = 2, CLOCK_FROM_SMAX = 4 };

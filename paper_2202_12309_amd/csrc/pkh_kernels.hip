@@ -69,9 +69,10 @@ __device__ __forceinline__ void push_ghosts(double* u, const int32_t* nb27, cons
 // ghosts are written into that neighbour's ghost zone here.
 // ---------------------------------------------------------------------------
 
+// One tile (TJ rows of block blk starting at row j0) of a stage; rot
+// rotates which wave takes the tile's remainder faces.
 template <int RECON, int N1, int TJ>
-// At most 168 VGPRs so that three waves fit per SIMD (no spills).
-__global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
+__device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0, int rot) {
   constexpr int NT = N1 * TJ;
   constexpr int P1 = N1 + 2 * NG;
   constexpr int RW = TJ + 2 * NG;
@@ -85,6 +86,7 @@ __global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
   constexpr int UQN = RECON ? 1 : 2;  // predictor: conserved own-cell queue length
   constexpr int NQ = RECON ? 5 : 8;   // staged values per cell
   constexpr int NWAVE = (NT + 63) / 64;
+  static_assert(NT % 64 == 0, "whole waves");
 
   __shared__ double sQ[NQ][PLANE];
   __shared__ double sFx[NV][NX];
@@ -92,16 +94,6 @@ __global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
   __shared__ double sRed[NWAVE];
 
   const Geom& g = a.g;
-  const int ntj = g.n2 / TJ;
-  const int nwg = gridDim.x;
-  int wg = blockIdx.x;
-  // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; map
-  // consecutive tiles of a block (which share halo rows) to one XCD's L2.
-  if ((nwg & 7) == 0) wg = (wg & 7) * (nwg >> 3) + (wg >> 3);
-  static_assert(NT % 64 == 0, "whole waves");
-  const int blk = wg / ntj;
-  if (blk >= a.nblocks) return;
-  const int j0 = (wg - blk * ntj) * TJ;
   const int tid = threadIdx.x;
   const int ti = tid % N1, tj = tid / N1;
 
@@ -298,7 +290,7 @@ __global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
       // remainder jobs (the tile's upper x and y faces) go to consecutive
       // threads starting at one wave, rotated with the plane and the
       // workgroup so that no SIMD always gets the extra work
-      const int wr = (wg + p + 2) % NWAVE;
+      const int wr = (rot + p + 2) % NWAVE;
       const int q = (tid - wr * 64 + NT) % NT;
 #pragma unroll 1
       for (int slot = 0; slot < 3; ++slot) {
@@ -371,6 +363,42 @@ __global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
   if (bad) atomicOr(&a.tm->err, 1);
 }
 
+// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; map
+// consecutive items (tiles of a block, which share halo rows) to one XCD's L2.
+__device__ __forceinline__ int xcd_order(int wg, int nwg) {
+  return (nwg & 7) == 0 ? (wg & 7) * (nwg >> 3) + (wg >> 3) : wg;
+}
+
+// At most 168 VGPRs so that three waves fit per SIMD (no spills).
+template <int RECON, int N1, int TJ>
+__global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
+  const int ntj = a.g.n2 / TJ;
+  const int wg = xcd_order(blockIdx.x, gridDim.x);
+  const int blk = wg / ntj;
+  if (blk >= a.nblocks) return;
+  stage_tile<RECON, N1, TJ>(a, blk, (wg - blk * ntj) * TJ, wg);
+}
+
+// Grouped launch: the tiles of many independent meshes (same block width
+// and tile) in one grid; items[w] names the mesh, block and first row.
+template <int RECON, int N1, int TJ>
+__global__ void __launch_bounds__(N1 * TJ, 3) stage_group_kernel(const StageLaunch* insts,
+                                                                 const GroupItem* items, int nitems) {
+  const int wg = xcd_order(blockIdx.x, gridDim.x);
+  if (wg >= nitems) return;
+  const GroupItem it = items[wg];
+  stage_tile<RECON, N1, TJ>(insts[it.inst], it.blk, it.j0, wg);
+}
+
+template <int RECON, int N1, int TJ>
+static hipError_t launch_group_t(const StageLaunch* insts, const GroupItem* items, int nitems,
+                                 hipStream_t s) {
+  const int nwg = (nitems + 7) / 8 * 8;
+  hipLaunchKernelGGL((stage_group_kernel<RECON, N1, TJ>), dim3((unsigned)nwg), dim3(N1 * TJ), 0, s, insts,
+                     items, nitems);
+  return hipGetLastError();
+}
+
 template <int RECON, int N1, int TJ>
 static hipError_t launch_stage_t(const StageLaunch& a, hipStream_t s) {
   const int ntj = a.g.n2 / TJ;
@@ -394,6 +422,29 @@ int stage_tile_rows(int n1, int n2, int tj) {
   for (int q = 0; q < 3; ++q)
     if (opts[row][q] == tj && tj > 0 && n2 % tj == 0) return tj;
   return -1;
+}
+
+hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
+                              const GroupItem* items, int nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+#define PKH_G(N1_, TJ_)                                                                 \
+  case N1_ * 100 + TJ_:                                                                 \
+    return recon ? launch_group_t<1, N1_, TJ_>(insts, items, nitems, s)                 \
+                 : launch_group_t<0, N1_, TJ_>(insts, items, nitems, s);
+  switch (n1 * 100 + tj) {
+    PKH_G(8, 8)
+    PKH_G(16, 8)
+    PKH_G(16, 16)
+    PKH_G(16, 4)
+    PKH_G(32, 8)
+    PKH_G(32, 4)
+    PKH_G(32, 16)
+    PKH_G(64, 4)
+    PKH_G(64, 2)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PKH_G
 }
 
 hipError_t launch_stage(const StageLaunch& a, hipStream_t s) {
@@ -1131,6 +1182,37 @@ __global__ void tape_dt_kernel(DevTime* tm, const double* dts, int c, int record
 
 hipError_t launch_tape_dt(DevTime* tm, double* dts, int32_t c, int32_t record, hipStream_t s) {
   hipLaunchKernelGGL(tape_dt_kernel, dim3(1), dim3(64), 0, s, tm, (const double*)dts, (int)c, (int)record);
+  return hipGetLastError();
+}
+
+}  // namespace pkh
+
+namespace pkh {
+
+// Device clocks of many meshes in one launch (thread per mesh); modes as
+// for clock_kernel.
+__global__ void clock_group_kernel(DevTime* const* tms, int n, int mode, double t_end) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  DevTime* tm = tms[q];
+  if (mode & (CLOCK_END | CLOCK_FROM_SMAX)) {
+    const double smax = __longlong_as_double((long long)tm->smax_bits);
+    tm->dt_next = tm->cfl / smax;
+  }
+  if (mode & CLOCK_END) {
+    tm->t += tm->dt;
+    tm->cycle += 1;
+  }
+  if (mode & CLOCK_BEGIN) {
+    double dt = tm->dt_next;
+    if (isfinite(t_end) && dt > t_end - tm->t) dt = fmax(t_end - tm->t, 0.0);
+    tm->dt = dt;
+    tm->smax_bits = 0ull;
+  }
+}
+
+hipError_t launch_clock_group(DevTime* const* tms, int32_t n, int32_t mode, double t_end, hipStream_t s) {
+  hipLaunchKernelGGL(clock_group_kernel, dim3((n + 63) / 64), dim3(64), 0, s, tms, (int)n, (int)mode, t_end);
   return hipGetLastError();
 }
 

@@ -1118,6 +1118,328 @@ int pkh_adjoint(pkh_mesh* m, pkh_tape* t, const double* lam_final, double* grad_
   return check_err(m);
 }
 
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct pkh_batch {
+  std::vector<pkh_mesh*> meshes;
+  hipStream_t stream = nullptr;
+  struct Group {
+    int n1 = 0, tj = 0;
+    std::vector<int32_t> members;   // mesh indices
+    std::vector<GroupItem> items;
+    GroupItem* d_items = nullptr;
+  };
+  std::vector<Group> groups;
+  StageLaunch* d_pred = nullptr;    // per mesh: predictor launch parameters
+  StageLaunch* d_corr = nullptr;    // per mesh: corrector launch parameters
+  DevTime** d_tms = nullptr;        // per mesh clock
+  hipGraphExec_t gexec = nullptr;
+  int32_t g_cycles = 0;
+};
+
+namespace {
+void batch_drop_graph(pkh_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  b->g_cycles = 0;
+}
+
+void batch_free_items(pkh_batch* b) {
+  pkh_mesh* m0 = b->meshes[0];
+  for (auto& gr : b->groups) {
+    m0->dfree(gr.d_items);
+    gr.d_items = nullptr;
+  }
+}
+
+// Work items of each group for its current tile rows (block-major, tiles of
+// a block consecutive).
+int batch_build_items(pkh_batch* b) {
+  pkh_mesh* m0 = b->meshes[0];
+  batch_free_items(b);
+  batch_drop_graph(b);
+  for (auto& gr : b->groups) {
+    gr.items.clear();
+    for (int32_t mi : gr.members) {
+      pkh_mesh* m = b->meshes[mi];
+      m->tj = gr.tj;
+      for (int32_t blk = 0; blk < (int32_t)m->nb(); ++blk)
+        for (int32_t j0 = 0; j0 < m->g.n2; j0 += gr.tj) gr.items.push_back(GroupItem{mi, blk, j0, 0});
+    }
+    int rc = upload_vec(m0, &gr.d_items, gr.items);
+    if (rc) return rc;
+  }
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return PKH_OK;
+}
+
+int batch_enqueue_cycle(pkh_batch* b, int mode_after) {
+  for (const auto& gr : b->groups)
+    HIPCHK(launch_stage_group(b->meshes[gr.members[0]]->cfg.stage1_recon, gr.n1, gr.tj, b->d_pred, gr.d_items,
+                              (int)gr.items.size(), b->stream));
+  for (const auto& gr : b->groups)
+    HIPCHK(launch_stage_group(PKH_RECON_PLM, gr.n1, gr.tj, b->d_corr, gr.d_items, (int)gr.items.size(),
+                              b->stream));
+  HIPCHK(launch_clock_group(b->d_tms, (int32_t)b->meshes.size(), mode_after, INFINITY, b->stream));
+  return PKH_OK;
+}
+
+int batch_prepare(pkh_batch* b) {
+  int rc;
+  for (pkh_mesh* m : b->meshes)
+    if (!m->ghosts_valid && (rc = do_exchange(m))) return rc;
+  return PKH_OK;
+}
+
+int batch_fused(pkh_batch* b, int32_t n, bool graph) {
+  int rc;
+  if ((rc = batch_prepare(b))) return rc;
+  HIPCHK(launch_clock_group(b->d_tms, (int32_t)b->meshes.size(), CLOCK_BEGIN, INFINITY, b->stream));
+  int c = 0;
+  if (graph) {
+    const int K = std::min(n, 50);
+    if (!b->gexec || b->g_cycles != K) {
+      batch_drop_graph(b);
+      hipGraph_t gh = nullptr;
+      HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      for (int q = 0; q < K && !rc; ++q) rc = batch_enqueue_cycle(b, CLOCK_END | CLOCK_BEGIN);
+      hipError_t e = hipStreamEndCapture(b->stream, &gh);
+      if (rc) return rc;
+      if (e != hipSuccess) return fail(PKH_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&b->gexec, gh, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gh);
+      if (e != hipSuccess) return fail(PKH_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+      b->g_cycles = K;
+    }
+    for (; c + K <= n; c += K) HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+  }
+  for (; c < n; ++c)
+    if ((rc = batch_enqueue_cycle(b, CLOCK_END | CLOCK_BEGIN))) return rc;
+  return PKH_OK;
+}
+
+// Save / restore of the active state and clock of every mesh (autotuning).
+struct Saved {
+  std::vector<double*> A;
+  std::vector<DevTime*> tm;
+};
+
+int save_states(const std::vector<pkh_mesh*>& ms, Saved& sv) {
+  for (pkh_mesh* m : ms) {
+    double* a = (double*)m->dalloc(m->state_bytes());
+    DevTime* t = (DevTime*)m->dalloc(sizeof(DevTime));
+    if (!a || !t) return fail(PKH_ENOMEM, "autotune scratch allocation failed");
+    HIPCHK(hipMemcpyAsync(a, m->A, m->state_bytes(), hipMemcpyDeviceToDevice, m->stream));
+    HIPCHK(hipMemcpyAsync(t, m->d_time, sizeof(DevTime), hipMemcpyDeviceToDevice, m->stream));
+    sv.A.push_back(a);
+    sv.tm.push_back(t);
+  }
+  return PKH_OK;
+}
+
+int restore_states(const std::vector<pkh_mesh*>& ms, Saved& sv) {
+  for (size_t q = 0; q < ms.size(); ++q) {
+    pkh_mesh* m = ms[q];
+    HIPCHK(hipMemcpyAsync(m->A, sv.A[q], m->state_bytes(), hipMemcpyDeviceToDevice, m->stream));
+    HIPCHK(hipMemcpyAsync(m->d_time, sv.tm[q], sizeof(DevTime), hipMemcpyDeviceToDevice, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    m->dfree(sv.A[q]);
+    m->dfree(sv.tm[q]);
+  }
+  return PKH_OK;
+}
+
+const int kTileChoices[] = {4, 8, 16, 2};
+}  // namespace
+
+extern "C" {
+
+int pkh_batch_create(pkh_mesh* const* meshes, int32_t n, pkh_batch** out) {
+  if (!meshes || n < 1 || !out) return fail(PKH_EINVAL, "bad argument");
+  *out = nullptr;
+  pkh_batch* b = new pkh_batch();
+  b->meshes.assign(meshes, meshes + n);
+  b->stream = meshes[0]->stream;
+  for (pkh_mesh* m : b->meshes) {
+    if (!m || m->stream != b->stream) {
+      delete b;
+      return fail(PKH_EINVAL, "batched meshes must share one stream");
+    }
+    if (m->need_fill || m->ncblocks) {
+      delete b;
+      return fail(PKH_EINVAL, "batches hold single-level meshes");
+    }
+  }
+  std::vector<StageLaunch> pred(n), corr(n);
+  std::vector<DevTime*> tms(n);
+  for (int32_t q = 0; q < n; ++q) {
+    pkh_mesh* m = b->meshes[q];
+    StageLaunch s{};
+    s.blocks = m->d_blocks;
+    s.nblocks = (int32_t)m->nb();
+    s.g = m->g;
+    s.tm = m->d_time;
+    s.fbuf = m->d_fbuf;
+    s.nbr = m->d_nbr;
+    s.uin = m->A;
+    s.ubase = m->A;
+    s.uout = m->B;
+    s.beta = 0.5;
+    s.recon = m->cfg.stage1_recon;
+    s.do_dt = 0;
+    pred[q] = s;
+    s.uin = m->B;
+    s.uout = m->A;
+    s.beta = 1.0;
+    s.recon = PKH_RECON_PLM;
+    s.do_dt = 1;
+    corr[q] = s;
+    tms[q] = m->d_time;
+    // group by block width and stage-1 reconstruction
+    const int tj = stage_tile_rows(m->g.n1, m->g.n2, m->tj);
+    bool placed = false;
+    for (auto& gr : b->groups) {
+      pkh_mesh* r = b->meshes[gr.members[0]];
+      if (gr.n1 == m->g.n1 && r->cfg.stage1_recon == m->cfg.stage1_recon &&
+          stage_tile_rows(m->g.n1, m->g.n2, gr.tj) == gr.tj) {
+        gr.members.push_back(q);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) {
+      pkh_batch::Group gr;
+      gr.n1 = m->g.n1;
+      gr.tj = tj;
+      gr.members.push_back(q);
+      b->groups.push_back(gr);
+    }
+  }
+  pkh_mesh* m0 = b->meshes[0];
+  int rc;
+  if ((rc = upload_vec(m0, &b->d_pred, pred)) || (rc = upload_vec(m0, &b->d_corr, corr)) ||
+      (rc = upload_vec(m0, &b->d_tms, tms)) || (rc = batch_build_items(b))) {
+    pkh_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return PKH_OK;
+}
+
+int pkh_batch_destroy(pkh_batch* b) {
+  if (!b) return PKH_OK;
+  (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  batch_free_items(b);
+  pkh_mesh* m0 = b->meshes[0];
+  m0->dfree(b->d_pred);
+  m0->dfree(b->d_corr);
+  m0->dfree(b->d_tms);
+  delete b;
+  return PKH_OK;
+}
+
+int pkh_batch_step(pkh_batch* b, int32_t n, uint32_t mode) {
+  if (!b || n < 0 || mode > PKH_GRAPH) return fail(PKH_EINVAL, "bad argument");
+  if (n == 0) return PKH_OK;
+  if (mode == PKH_PLAIN) {
+    int rc;
+    for (int c = 0; c < n; ++c)
+      for (pkh_mesh* m : b->meshes)
+        if ((rc = pkh_step(m, 1, INFINITY))) return rc;
+    return PKH_OK;
+  }
+  return batch_fused(b, n, mode == PKH_GRAPH);
+}
+
+int pkh_batch_autotune(pkh_batch* b, int32_t trial_cycles, int32_t* tile_rows) {
+  if (!b || trial_cycles < 1) return fail(PKH_EINVAL, "bad argument");
+  int rc;
+  if ((rc = batch_prepare(b))) return rc;
+  Saved sv;
+  if ((rc = save_states(b->meshes, sv))) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (auto& gr : b->groups) {
+    int best = gr.tj;
+    float best_ms = 1e30f;
+    for (int tj : kTileChoices) {
+      if (stage_tile_rows(gr.n1, b->meshes[gr.members[0]]->g.n2, tj) != tj) continue;
+      bool all = true;
+      for (int32_t mi : gr.members) all &= stage_tile_rows(gr.n1, b->meshes[mi]->g.n2, tj) == tj;
+      if (!all) continue;
+      gr.tj = tj;
+      if ((rc = batch_build_items(b))) return rc;
+      if ((rc = batch_fused(b, 1, false))) return rc;  // warm-up
+      HIPCHK(hipEventRecord(e0, b->stream));
+      if ((rc = batch_fused(b, trial_cycles, false))) return rc;
+      HIPCHK(hipEventRecord(e1, b->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = tj;
+      }
+    }
+    gr.tj = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if ((rc = batch_build_items(b)) || (rc = restore_states(b->meshes, sv))) return rc;
+  if (tile_rows)
+    for (size_t q = 0; q < b->meshes.size(); ++q) tile_rows[q] = stage_tile_rows(b->meshes[q]->g.n1, b->meshes[q]->g.n2, b->meshes[q]->tj);
+  return PKH_OK;
+}
+
+int pkh_autotune(pkh_mesh* m, int32_t trial_cycles, pkh_tuning* out) {
+  if (!m || trial_cycles < 1) return fail(PKH_EINVAL, "bad argument");
+  int rc;
+  if (!m->ghosts_valid && (rc = do_exchange(m))) return rc;
+  std::vector<pkh_mesh*> ms{m};
+  Saved sv;
+  if ((rc = save_states(ms, sv))) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const uint32_t flags = m->cfg.flags;
+  m->cfg.flags &= ~PKH_FLAG_GRAPH;
+  int best = stage_tile_rows(m->g.n1, m->g.n2, m->tj);
+  float best_ms = 1e30f;
+  for (int tj : kTileChoices) {
+    if (stage_tile_rows(m->g.n1, m->g.n2, tj) != tj) continue;
+    m->tj = tj;
+    if ((rc = pkh_step(m, 1, INFINITY))) break;
+    HIPCHK(hipEventRecord(e0, m->stream));
+    if ((rc = pkh_step(m, trial_cycles, INFINITY))) break;
+    HIPCHK(hipEventRecord(e1, m->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = tj;
+    }
+  }
+  m->cfg.flags = flags;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  m->tj = best;
+  drop_graph(m);
+  int rc2 = restore_states(ms, sv);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (out) {
+    *out = pkh_tuning{};
+    out->tile_rows = best;
+  }
+  return PKH_OK;
+}
+
 int pkh_sync(pkh_mesh* m) {
   if (!m) return fail(PKH_EINVAL, "null mesh");
   return check_err(m);

@@ -225,3 +225,27 @@ def smooth_density(leaves, n, nrb, seed=5, amp=1e-3, kmax=4, rho0=1.0, p0=0.6,
         rho = rho0 + amp * dl / mx
         U[b] = _to_conserved(rho, 0 * rho, 0 * rho, 0 * rho, p0 + 0 * rho, gamma)
     return U
+
+
+def batch_mix(n=64, seed=4, sizes=(32, 48, 64, 80, 96, 112, 128)):
+    """Seeded mix of independent periodic unit-cube instances: edge N drawn
+    uniformly from `sizes`, block edge 32 when 32 divides N and a coin flip
+    says so (else 16), initial condition a sound wave or a spherical blast
+    (coin flip). Returns a list of dicts (N, blk, kind)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        N = int(rng.choice(sizes))
+        blk = 32 if (N % 32 == 0 and rng.random() < 0.5) else 16
+        kind = "blast" if rng.random() < 0.5 else "wave"
+        out.append({"N": N, "blk": blk, "kind": kind})
+    return out
+
+
+def batch_state(spec, leaves):
+    """Initial state of one batch instance (see batch_mix)."""
+    n = (spec["blk"],) * 3
+    nrb = (spec["N"] // spec["blk"],) * 3
+    if spec["kind"] == "blast":
+        return blast(leaves, n, nrb)
+    return sound_wave(leaves, n, nrb, amp=1e-3, noise=0.0)
