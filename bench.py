@@ -26,14 +26,14 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2202_12309_amd", "csrc", "pkh_kernels.hip
 
 def algorithmic_bytes(n):
     """Bytes per zone for the corrector kernel and for the whole cycle, FP64,
-    5 variables, ghost width 2, ghosts materialised in memory.
+    5 variables, ghost width 2, r_g = (n+4)^3 / n^3.
 
     Corrector: read U* with ghosts (r_g * 40 B), read U^n (40 B), write
-    U^{n+1} (40 B), r_g = (n+4)^3 / n^3. Cycle: predictor (r_g*40 + 40),
-    corrector (r_g*40 + 80), two ghost fills ((r_g - 1)*40 read + write each)
-    = 240 r_g - 40."""
+    U^{n+1} (40 B) and the ghost copies a same-level neighbour needs
+    ((r_g - 1) * 40 B). Predictor: r_g*40 + 40 + (r_g-1)*40. Cycle: both
+    stages = 160 r_g + 40 (268 B at n = 32)."""
     rg = (n + 4) ** 3 / n ** 3
-    return rg * 40.0 + 80.0, 240.0 * rg - 40.0
+    return rg * 40.0 + 80.0 + (rg - 1.0) * 40.0, 160.0 * rg + 40.0
 
 
 def traffic_from_profile(kernel_sha):
