@@ -86,6 +86,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   constexpr int UQN = RECON ? 1 : 2;  // predictor: conserved own-cell queue length
   constexpr int NQ = RECON ? 5 : 8;   // staged values per cell
   constexpr int NWAVE = (NT + 63) / 64;
+  constexpr bool PF = !RECON;         // prefetch the next plane into registers
   static_assert(NT % 64 == 0, "whole waves");
 
   __shared__ double sQ[NQ][PLANE];
@@ -180,13 +181,42 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     }
   };
 
+  // halo cell h of the plane (rows -2,-1 and TJ,TJ+1 of the tile, then the
+  // two cells at each end of the interior rows) -> its LDS slot
+  auto hcell = [&](int h) {
+    if (h < 2 * P1) return h;
+    if (h < 4 * P1) return (TJ + NG) * P1 + (h - 2 * P1);
+    const int hh = h - 4 * P1, r = hh >> 2, s4 = hh & 3;
+    return (r + NG) * P1 + (s4 < 2 ? s4 : P1 - 4 + s4);
+  };
+  constexpr int HMAX = PF ? (NHALO + NT - 1) / NT : 1;
+  double pu[NV], ph[HMAX][NV];  // prefetched own and halo cells of the next plane
+  if constexpr (PF) {
+    const double* pl = in + ((int64_t)(-1 - LAG + NG) * g.p2 + j0) * P1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) pu[v] = pl[v * vs + own];
+#pragma unroll
+    for (int hh = 0; hh < HMAX; ++hh) {
+      const int h = tid + hh * NT;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ph[hh][v] = h < NHALO ? pl[v * vs + hcell(h)] : 1.0;
+    }
+  }
+
   for (int p = -1 - LAG; p < n3 + 1 + LAG; ++p) {
-    // --- stage plane p (rows j0-2 .. j0+TJ+1): own cell first, then halo
-    const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
+    // --- stage plane p (rows j0-2 .. j0+TJ+1): own cell first, then halo.
+    // The predictor takes plane p from registers loaded while plane p-1 was
+    // being computed and starts the loads of plane p+1 right away.
     {
       double u[NV];
+      if constexpr (PF) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + own];
+        for (int v = 0; v < NV; ++v) u[v] = pu[v];
+      } else {
+        const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + own];
+      }
       const FState q = stage_cell(u, own);
 #pragma unroll
       for (int s = 0; s < WN - 1; ++s) w[s] = w[s + 1];
@@ -200,20 +230,35 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
         for (int v = 0; v < NV; ++v) uq[UQN - 1][v] = u[v];
       }
     }
-    for (int h = tid; h < NHALO; h += NT) {
-      int c;
-      if (h < 2 * P1) {
-        c = h;
-      } else if (h < 4 * P1) {
-        c = (TJ + NG) * P1 + (h - 2 * P1);
-      } else {
-        const int hh = h - 4 * P1, r = hh >> 2, s4 = hh & 3;
-        c = (r + NG) * P1 + (s4 < 2 ? s4 : P1 - 4 + s4);
-      }
-      double u[NV];
+    if constexpr (PF) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + c];
-      stage_cell(u, c);
+      for (int hh = 0; hh < HMAX; ++hh) {
+        const int h = tid + hh * NT;
+        if (h < NHALO) stage_cell(ph[hh], hcell(h));
+      }
+      if (p + 1 < n3 + 1 + LAG) {
+        const double* pn = in + ((int64_t)(p + 1 + NG) * g.p2 + j0) * P1;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pu[v] = pn[v * vs + own];
+#pragma unroll
+        for (int hh = 0; hh < HMAX; ++hh) {
+          const int h = tid + hh * NT;
+          if (h < NHALO) {
+            const int c = hcell(h);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ph[hh][v] = pn[v * vs + c];
+          }
+        }
+      }
+    } else {
+      const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
+      for (int h = tid; h < NHALO; h += NT) {
+        double u[NV];
+        const int c = hcell(h);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + c];
+        stage_cell(u, c);
+      }
     }
     __syncthreads();
 
@@ -369,9 +414,11 @@ __device__ __forceinline__ int xcd_order(int wg, int nwg) {
   return (nwg & 7) == 0 ? (wg & 7) * (nwg >> 3) + (wg >> 3) : wg;
 }
 
-// At most 168 VGPRs so that three waves fit per SIMD (no spills).
+// Occupancy: the corrector is held to 168 VGPRs (three waves per SIMD); the
+// predictor keeps the next plane's loads in flight in registers and runs
+// at two waves per SIMD.
 template <int RECON, int N1, int TJ>
-__global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
+__global__ void __launch_bounds__(N1 * TJ, RECON ? 3 : 2) stage_kernel(StageLaunch a) {
   const int ntj = a.g.n2 / TJ;
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   const int blk = wg / ntj;
@@ -382,7 +429,7 @@ __global__ void __launch_bounds__(N1 * TJ, 3) stage_kernel(StageLaunch a) {
 // Grouped launch: the tiles of many independent meshes (same block width
 // and tile) in one grid; items[w] names the mesh, block and first row.
 template <int RECON, int N1, int TJ>
-__global__ void __launch_bounds__(N1 * TJ, 3) stage_group_kernel(const StageLaunch* insts,
+__global__ void __launch_bounds__(N1 * TJ, RECON ? 3 : 2) stage_group_kernel(const StageLaunch* insts,
                                                                  const GroupItem* items, int nitems) {
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   if (wg >= nitems) return;

@@ -17,7 +17,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pkhydro.h"
+#include "pkhydro.h"
 #include "pkh_internal.h"
 
 using namespace pkh;
