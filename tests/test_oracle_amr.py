@@ -253,3 +253,63 @@ def test_regrid_conserves_totals():
     m.regrid(flags)
     T1, _ = m.totals()
     assert np.all(np.abs(T1 - T0) <= 1e-14 * A0)
+
+
+# ---------------------------------------------------------------------------
+# Pressure-jump refinement indicator (the harness's criterion)
+# ---------------------------------------------------------------------------
+
+def _pressure_state(m, pfun):
+    """rho = 1 at rest with pressure pfun(x, y, z) at the cell centres."""
+    U = np.zeros(m.shape())
+    g1 = m.gamma - 1.0
+    for b in range(m.nleaves):
+        x, y, z = m.cell_centers(b)
+        U[b, 0] = 1.0
+        U[b, 4] = pfun(x, y, z) / g1
+    return U
+
+
+def test_pressure_jump_uniform_is_zero():
+    m = _amr_mesh()
+    m.set_state(_pressure_state(m, lambda x, y, z: 0.7 + 0 * x))
+    assert np.all(m.pressure_jump() == 0.0)
+
+
+def test_pressure_jump_linear_field_closed_form():
+    # P = a + s x: |P(x+dx) - P(x-dx)| / (P(x+dx) + P(x-dx)) = s dx / (a + s x),
+    # largest at the lowest cell centre of the leaf; exact ghosts of a linear
+    # field (copy, restriction, prolongation) make this hold on both levels
+    # away from the periodic seam in x
+    a, s = 2.0, 0.75
+    m = _amr_mesh()
+    m.set_state(_pressure_state(m, lambda x, y, z: a + s * x))
+    eta = m.pressure_jump()
+    lv = m.leaves()
+    checked = 0
+    for b, (lev, lx, ly, lz) in enumerate(lv):
+        nx = NRB4[0] << lev
+        if lx == 0 or lx == nx - 1:
+            continue
+        dx = 1.0 / (NRB4[0] * N8[0] * (1 << lev))
+        xlo = (lx * N8[0] + 0.5) * dx
+        want = s * dx / (a + s * xlo)
+        assert abs(eta[b] - want) <= 1e-13 * want, (b, eta[b], want)
+        checked += 1
+    assert checked > 40
+
+
+def test_pressure_jump_step_and_flags():
+    # a pressure step across x = 1/2 (a level-0 face): the leaves on both
+    # sides of it see exactly |P2 - P1| / (P2 + P1)
+    p1, p2 = 0.1, 100.0
+    nrb = (4, 2, 2)
+    m = OracleMesh(N8, nrb, inputs.uniform_leaves(nrb), xmax=(2.0, 1.0, 1.0))
+    m.set_state(_pressure_state(m, lambda x, y, z: np.where(x < 1.0, p1, p2)))
+    eta = m.pressure_jump()
+    want = (p2 - p1) / (p2 + p1)
+    lv = m.leaves()
+    for b, (lev, lx, ly, lz) in enumerate(lv):
+        assert eta[b] == want  # every leaf touches x = 1 or the periodic seam
+    flags = np.where(eta > 0.1, 1, np.where(eta < 0.02, -1, 0))
+    assert np.all(flags == 1)
