@@ -156,6 +156,46 @@ def batch_leg(cycles=50):
     return out
 
 
+def amr_leg(cycles=200, regrid_every=10):
+    """Two-level blast: 128^3 root in blocks of 16^3, the root blocks meeting
+    the open ball r < 0.25 refined once (960 leaves), P = 100 inside r < 0.1
+    and 0.1 outside, rho = 1 at rest. Every 10 cycles the device
+    pressure-jump indicator sets the flags (refine above 0.1, derefine below
+    0.02) and the mesh is regridded. Zone-cycles count the leaf cells of
+    every cycle; the time includes the indicator and the regrids."""
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+    blk, nrb = 16, (8, 8, 8)
+    n = (blk,) * 3
+    mesh = Mesh((128,) * 3, n, inputs.sphere_refined_leaves(nrb, radius=0.25), max_level=1)
+    mesh.upload(inputs.blast(mesh.leaves(), n, nrb))
+    mesh.sync()
+    leaves0 = mesh.nleaves
+    counts = []
+    zc = 0
+    t_regrid = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(cycles // regrid_every):
+        zc += mesh.nleaves * blk ** 3 * regrid_every
+        mesh.step(regrid_every)
+        t1 = time.perf_counter()
+        mesh.flag_pressure_jump(0.1, 0.02)  # waits for the cycles
+        t2 = time.perf_counter()
+        mesh.regrid()
+        t_regrid += time.perf_counter() - t2
+        counts.append(mesh.nleaves)
+    mesh.sync()
+    el = time.perf_counter() - t0
+    t, dt, cyc = mesh.time()
+    return {"workload": "two-level blast, 128^3 root in 16^3 blocks, sphere r=0.25 refined once, "
+                        "regrid every 10 cycles (pressure-jump flags 0.1 / 0.02)",
+            "cycles": cyc, "zone_cycles": zc, "seconds": round(el, 4),
+            "zone_cycles_per_s": zc / el, "regrid_seconds": round(t_regrid, 4),
+            "leaves_start": leaves0, "leaves_after_each_regrid": counts, "sim_time": t}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +207,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (the HBM-counter calibration kernel)")
     args = ap.parse_args()
@@ -254,12 +295,15 @@ def main():
         "adjoint_forward_ratio": None,
         "adjoint": None,
         "batch": None,
+        "amr": None,
         "roofline": roof,
     }
     if not args.no_adjoint:
         adj = adjoint_ratio()
         out["adjoint"] = adj
         out["adjoint_forward_ratio"] = adj["reverse_sweep_over_forward"]
+    if not args.no_amr:
+        out["amr"] = amr_leg()
     if not args.no_batch:
         del mesh
         torch.cuda.empty_cache()

@@ -163,6 +163,18 @@ int pkh_set_time(pkh_mesh *mesh, double t, int64_t cycle);
    +1 refine (Sec. 2.1, Sec. 3.8). Applied by pkh_regrid. */
 int pkh_set_refinement_flags(pkh_mesh *mesh, const int8_t *flags, int64_t n);
 
+/* Device refinement indicator (the paper leaves the criterion to the
+   application; Sec. 2.1, Sec. 3.8). Per leaf, eta = the largest
+   |P(i+e_d) - P(i-e_d)| / (P(i+e_d) + P(i-e_d)) over active cells i and
+   directions d, from the current state with ghosts filled; evaluated without
+   FMA contraction and with correctly rounded division. Sets the mesh's flags
+   to +1 where eta > refine_above, -1 where eta < derefine_below, else 0 (as
+   pkh_set_refinement_flags would) and, when non-NULL, copies them to
+   flags_out[n leaves] and eta to eta_out[n leaves] (host arrays, caller
+   owned). PKH_EINVAL if derefine_below > refine_above. Synchronises. */
+int pkh_flag_pressure_jump(pkh_mesh *mesh, double refine_above, double derefine_below,
+                           int8_t *flags_out, double *eta_out);
+
 /* Apply the flags: +1 splits a leaf below max_level into 8 children; a
    refinement that would break 2:1 also refines the touching coarser
    leaves, to a fixed point; 8 siblings all flagged -1 (none refining) merge
@@ -188,8 +200,9 @@ int pkh_conserved_totals(pkh_mesh *mesh, double out[5]);
 typedef struct pkh_tape pkh_tape;
 
 /* Tape for the mesh; ckpt_every >= 1. Device memory: one active-state copy
-   per checkpoint (allocated as cycles are recorded) plus 2*ckpt_every + 2
-   ghost-filled states for recomputation. PKH_EINVAL on multilevel meshes. */
+   per checkpoint (allocated as cycles are recorded) plus 2*ckpt_every + 1
+   ghost-filled states for recomputation and 3 for the reverse sweep.
+   PKH_EINVAL on multilevel meshes. */
 int pkh_tape_create(pkh_mesh *mesh, int32_t ckpt_every, pkh_tape **out);
 int pkh_tape_destroy(pkh_tape *tape);
 

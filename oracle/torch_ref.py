@@ -28,14 +28,22 @@ def to_prim(U, gamma):
     return torch.stack([rho, vx, vy, vz, p])
 
 
-def mc_slope(dl, dr):
-    mag = torch.minimum(torch.minimum(2.0 * dl.abs(), 2.0 * dr.abs()), 0.5 * (dl + dr).abs())
-    return torch.where(dl * dr > 0.0, torch.sign(dl) * mag, torch.zeros_like(dl))
+def mc_slope(dl, dr, log=None):
+    a, b, c = 2.0 * dl.abs(), 2.0 * dr.abs(), 0.5 * (dl + dr).abs()
+    mag = torch.minimum(torch.minimum(a, b), c)
+    pos = dl * dr > 0.0
+    if log is not None:
+        # branch taken: 0 no slope, else 1 + which bound is the smallest
+        # (first in the order 2|dl|, 2|dr|, |dl+dr|/2 on ties)
+        which = torch.where(a <= torch.minimum(b, c), 1, torch.where(b <= c, 2, 3))
+        log.append(torch.where(pos, which, 0).to(torch.int8))
+    return torch.where(pos, torch.sign(dl) * mag, torch.zeros_like(dl))
 
 
-def hlle_flux(wl, wr, d, gamma):
+def hlle_flux(wl, wr, d, gamma, log=None):
     """Conserved flux through faces normal to d from primitive states
-    wl, wr shaped [5][...]."""
+    wl, wr shaped [5][...]. With ``log`` a list, appends the branches the
+    wave-speed bounds take (which argument attains the max / min)."""
     g1 = gamma - 1.0
     rl, pl, rr, pr = wl[0], wl[4], wr[0], wr[4]
     vl, vr = wl[1:4], wr[1:4]
@@ -52,6 +60,11 @@ def hlle_flux(wl, wr, d, gamma):
     zero = torch.zeros_like(ul)
     bp = torch.maximum(torch.maximum(vbar[d] + abar, ur + cr), zero)
     bm = torch.minimum(torch.minimum(vbar[d] - abar, ul - cl), zero)
+    if log is not None:
+        p1, p2 = vbar[d] + abar, ur + cr
+        m1, m2 = vbar[d] - abar, ul - cl
+        log.append(torch.where(p1 >= torch.maximum(p2, zero), 0, torch.where(p2 >= zero, 1, 2)).to(torch.int8))
+        log.append(torch.where(m1 <= torch.minimum(m2, zero), 0, torch.where(m2 <= zero, 1, 2)).to(torch.int8))
 
     def phys(r, v, p, e):
         u = v[d]
@@ -66,25 +79,25 @@ def hlle_flux(wl, wr, d, gamma):
     return (bp * fl - bm * fr + bp * bm * (ur_c - ul_c)) / (bp - bm)
 
 
-def face_flux(W, d, recon, gamma):
+def face_flux(W, d, recon, gamma, log=None):
     """Flux at the lower face (i - 1/2 along d) of every cell."""
     ax = _DIM[d]
     q0 = W
     qm1 = torch.roll(W, 1, ax)
     if recon == 0:
-        return hlle_flux(qm1, q0, d, gamma)
+        return hlle_flux(qm1, q0, d, gamma, log)
     qm2 = torch.roll(W, 2, ax)
     qp1 = torch.roll(W, -1, ax)
-    wl = qm1 + 0.5 * mc_slope(qm1 - qm2, q0 - qm1)
-    wr = q0 - 0.5 * mc_slope(q0 - qm1, qp1 - q0)
-    return hlle_flux(wl, wr, d, gamma)
+    wl = qm1 + 0.5 * mc_slope(qm1 - qm2, q0 - qm1, log)
+    wr = q0 - 0.5 * mc_slope(q0 - qm1, qp1 - q0, log)
+    return hlle_flux(wl, wr, d, gamma, log)
 
 
-def divergence(U, recon, gamma, dx):
+def divergence(U, recon, gamma, dx, log=None):
     W = to_prim(U, gamma)
     D = None
     for d in range(3):
-        F = face_flux(W, d, recon, gamma)
+        F = face_flux(W, d, recon, gamma, log)
         term = (torch.roll(F, -1, _DIM[d]) - F) / dx[d]
         D = term if D is None else D + term
     return D
@@ -100,21 +113,24 @@ def cfl_dt(U, gamma, cfl, dx):
     return cfl * best
 
 
-def cycle(U, dt, gamma, dx, stage1_recon=0):
-    Us = U - 0.5 * dt * divergence(U, stage1_recon, gamma, dx)
-    return U - dt * divergence(Us, 1, gamma, dx)
+def cycle(U, dt, gamma, dx, stage1_recon=0, log=None):
+    Us = U - 0.5 * dt * divergence(U, stage1_recon, gamma, dx, log)
+    return U - dt * divergence(Us, 1, gamma, dx, log)
 
 
-def run(U, ncycles, gamma=5.0 / 3.0, cfl=0.3, dx=None, stage1_recon=0, dts=None):
+def run(U, ncycles, gamma=5.0 / 3.0, cfl=0.3, dx=None, stage1_recon=0, dts=None, log=None):
     """Advance ncycles; the timestep is evaluated from the detached state
-    (or taken from ``dts``). Returns (U, list of dt)."""
+    (or taken from ``dts``). Returns (U, list of dt). With ``log`` a list,
+    every limiter and wave-speed branch taken is appended to it (int8
+    tensors), so two runs are on the same smooth piece of the map exactly
+    when their logs are equal."""
     if dx is None:
         dx = tuple(1.0 / U.shape[3 - d] for d in range(3))
     used = []
     for c in range(ncycles):
         dt = cfl_dt(U.detach(), gamma, cfl, dx) if dts is None else torch.as_tensor(dts[c], dtype=U.dtype)
         used.append(float(dt))
-        U = cycle(U, dt, gamma, dx, stage1_recon)
+        U = cycle(U, dt, gamma, dx, stage1_recon, log)
     return U, used
 
 

@@ -63,6 +63,8 @@ _SIGS = {
     "pkh_set_time": (C.c_int, [C.c_void_p, C.c_double, C.c_int64]),
     "pkh_set_refinement_flags": (C.c_int, [C.c_void_p, C.POINTER(C.c_int8), C.c_int64]),
     "pkh_regrid": (C.c_int, [C.c_void_p]),
+    "pkh_flag_pressure_jump": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(C.c_int8),
+                                         C.POINTER(C.c_double)]),
     "pkh_conserved_totals": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pkh_sync": (C.c_int, [C.c_void_p]),
     "pkh_kernel_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
@@ -309,6 +311,17 @@ class Mesh:
     def set_flags(self, flags):
         f = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
         _check(lib().pkh_set_refinement_flags(self._h, f.ctypes.data_as(C.POINTER(C.c_int8)), len(f)))
+
+    def flag_pressure_jump(self, refine_above, derefine_below):
+        """Set the flags from the device pressure-jump indicator; returns
+        (flags int8[nleaves], eta float64[nleaves]) in storage order."""
+        n = self.nleaves
+        f = np.zeros(n, dtype=np.int8)
+        eta = np.zeros(n, dtype=np.float64)
+        _check(lib().pkh_flag_pressure_jump(self._h, float(refine_above), float(derefine_below),
+                                            f.ctypes.data_as(C.POINTER(C.c_int8)),
+                                            eta.ctypes.data_as(C.POINTER(C.c_double))))
+        return f, eta
 
     def regrid(self, flags=None):
         if flags is not None:

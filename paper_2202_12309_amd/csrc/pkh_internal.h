@@ -114,6 +114,8 @@ hipError_t launch_gather(double* dst, const double* u, int32_t nblocks, const Ge
                          hipStream_t s);
 hipError_t launch_totals(double* partial, double* out, const double* u, const BlockInfo* blocks,
                          int32_t nblocks, const Geom& g, hipStream_t s);
+// Pressure-jump indicator per leaf into eta[nblocks] (ghost-filled u).
+hipError_t launch_eta(double* eta, const double* u, int32_t nblocks, const Geom& g, hipStream_t s);
 // Regrid: new leaf r takes kind[r] (0 copy, 1 child of a refined leaf,
 // 2 merged parent) from old leaf src[r].
 hipError_t launch_regrid_data(double* unew, const BlockInfo* bnew, const int32_t* kind,
@@ -123,8 +125,8 @@ hipError_t launch_regrid_data(double* unew, const BlockInfo* bnew, const int32_t
 
 // Reverse mode of one stage U_out = U_base - beta*dt*D(U_in) w.r.t. U_in
 // (same-level meshes): out = add0 + add1 + (dD/dU_in)^T-term of lam;
-// U is the padded, ghost-filled U_in; wbar a padded scratch array; dt is
-// read from dtp on the device.
+// U is the padded, ghost-filled U_in; wbar scratch for three padded
+// states (one per direction); dt is read from dtp on the device.
 hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar,
                             const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                             const int32_t* nbr, const double* dtp, double beta, double* out,

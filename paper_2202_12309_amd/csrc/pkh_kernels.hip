@@ -14,6 +14,8 @@
 // each side, i (x) contiguous. One launch covers every block of the mesh.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pkh_internal.h"
 #include "pkh_physics.h"
 
@@ -946,6 +948,51 @@ hipError_t launch_totals(double* partial, double* out, const double* u, const Bl
 }
 
 // ---------------------------------------------------------------------------
+// Pressure-jump refinement indicator: per leaf, the largest relative jump
+// |P(i+e_d) - P(i-e_d)| / (P(i+e_d) + P(i-e_d)) over active cells and
+// directions, on the ghost-filled state. Evaluated without contraction and
+// with correctly rounded division, so a threshold test on it decides the
+// same way as the plain expression evaluated on a CPU.
+// ---------------------------------------------------------------------------
+
+__device__ double pressure_nc(const double* c, int64_t vs, double gm1) {
+#pragma clang fp contract(off)
+  const double rho = c[0], m1 = c[vs], m2 = c[2 * vs], m3 = c[3 * vs], e = c[4 * vs];
+  const double ke = 0.5 * ((m1 * m1 + m2 * m2) + m3 * m3) / rho;
+  return gm1 * (e - ke);
+}
+
+__global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, Geom g) {
+#pragma clang fp contract(off)
+  __shared__ double sRed[4];
+  const int b = blockIdx.x;
+  const int ncell = g.n1 * g.n2 * g.n3;
+  const double gm1 = g.gamma - 1.0;
+  const int64_t st[3] = {1, g.p1, (int64_t)g.p1 * g.p2};
+  double mx = 0.0;
+  for (int q = threadIdx.x; q < ncell; q += 256) {
+    const int i = q % g.n1, j = (q / g.n1) % g.n2, k = q / (g.n1 * g.n2);
+    const double* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double pp = pressure_nc(cell + st[d], g.vstride, gm1);
+      const double pm = pressure_nc(cell - st[d], g.vstride, gm1);
+      mx = fmax(mx, fabs(pp - pm) / (pp + pm));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) eta[b] = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
+}
+
+hipError_t launch_eta(double* eta, const double* u, int32_t nblocks, const Geom& g, hipStream_t s) {
+  hipLaunchKernelGGL(eta_kernel, dim3(nblocks), dim3(256), 0, s, eta, u, g);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Regrid data: each new leaf is a copy, a child (prolongation of the
 // composite field at the parent's level on the old mesh) or a merged parent
 // (restriction of its children).
@@ -1008,18 +1055,16 @@ namespace pkh {
 // One thread per pencil (active transverse position) of a block along D;
 // it walks the pencil's padded cells with a window of states and a ring of
 // four cell accumulators, so each cell's primitive adjoint is complete when
-// emitted: direction 0 writes, directions 1 and 2 add on active cells and
-// write on their own ghost cells (no other pass touches those).
+// emitted. Each direction writes its own array (every padded cell of its
+// pencils), so the three directions run in one launch.
 template <int RECON, int D>
-__global__ void __launch_bounds__(256) adj_pencil_kernel(const double* __restrict__ U,
-                                                         const double* __restrict__ lam,
-                                                         double* __restrict__ wbar,
-                                                         const BlockInfo* blocks, int nblocks,
-                                                         Geom g, const double* dtp, double beta) {
+__device__ __forceinline__ void adj_pencil(const double* __restrict__ U, const double* __restrict__ lam,
+                                           double* __restrict__ wbar, const BlockInfo* blocks,
+                                           int nblocks, const Geom& g, const double* dtp, double beta,
+                                           int64_t gid) {
   const int n[3] = {g.n1, g.n2, g.n3};
   constexpr int T1 = D == 0 ? 1 : 0, T2 = D == 2 ? 1 : 2;
   const int nt1 = n[T1], nt2 = n[T2], nd = n[D];
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)nt1 * nt2;
   const int b = (int)(gid / per);
   if (b >= nblocks) return;
@@ -1051,15 +1096,9 @@ __global__ void __launch_bounds__(256) adj_pencil_kernel(const double* __restric
     for (int v = 0; v < NV; ++v) l[v] = (s >= 0 && s < nd) ? lam[abase + (int64_t)v * ncell + (int64_t)s * as] : 0.0;
   };
   auto emit = [&](int s, const double acc[NV]) {
-    const bool active = s >= 0 && s < nd;
     double* o = wbar + pbase + (int64_t)s * ps;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if (D != 0 && active)
-        o[(int64_t)v * g.vstride] += acc[v];
-      else
-        o[(int64_t)v * g.vstride] = acc[v];
-    }
+    for (int v = 0; v < NV; ++v) o[(int64_t)v * g.vstride] = acc[v];
   };
 
   double W[4][NV];   // states of cells f-2 .. f+1
@@ -1143,11 +1182,31 @@ __global__ void __launch_bounds__(256) adj_pencil_kernel(const double* __restric
   emit(nd + 1, acc[2]);
 }
 
+template <int RECON>
+__global__ void __launch_bounds__(256) adj_pencils_kernel(const double* __restrict__ U,
+                                                          const double* __restrict__ lam,
+                                                          double* __restrict__ wbar3, int64_t wstride,
+                                                          const BlockInfo* blocks, int nblocks, Geom g,
+                                                          const double* dtp, double beta) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  switch (blockIdx.y) {
+    case 0:
+      adj_pencil<RECON, 0>(U, lam, wbar3, blocks, nblocks, g, dtp, beta, gid);
+      break;
+    case 1:
+      adj_pencil<RECON, 1>(U, lam, wbar3 + wstride, blocks, nblocks, g, dtp, beta, gid);
+      break;
+    default:
+      adj_pencil<RECON, 2>(U, lam, wbar3 + 2 * wstride, blocks, nblocks, g, dtp, beta, gid);
+  }
+}
+
 // Transposed ghost exchange and primitive-to-conserved adjoint, one thread
 // per active cell: the cell's own primitive adjoint plus those of its ghost
 // copies in the face neighbours, mapped through the primitive recovery at
 // the cell's state, plus optional addends.
 __global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restrict__ wbar,
+                                                           int64_t wstride,
                                                            const double* __restrict__ U,
                                                            const int32_t* __restrict__ nbr, Geom g,
                                                            int64_t total, double* out,
@@ -1162,13 +1221,16 @@ __global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restr
   double gw[NV];
   const int64_t own = (int64_t)b * g.bstride + pad_index(g, i, j, k);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) gw[v] = wbar[own + (int64_t)v * g.vstride];
+  for (int v = 0; v < NV; ++v)
+    gw[v] = (wbar[own + (int64_t)v * g.vstride] + wbar[wstride + own + (int64_t)v * g.vstride]) +
+            wbar[2 * wstride + own + (int64_t)v * g.vstride];
   auto add_copy = [&](int dx, int dy, int dz) {
     const int32_t nb = nb27[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
     if (nb < 0) return;
+    const double* wd = wbar + (dx ? 0 : (dy ? wstride : 2 * wstride));
     const int64_t o = (int64_t)nb * g.bstride + pad_index(g, i - dx * g.n1, j - dy * g.n2, k - dz * g.n3);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) gw[v] += wbar[o + (int64_t)v * g.vstride];
+    for (int v = 0; v < NV; ++v) gw[v] += wd[o + (int64_t)v * g.vstride];
   };
   if (i < NG) add_copy(-1, 0, 0);
   if (i >= g.n1 - NG) add_copy(1, 0, 0);
@@ -1190,30 +1252,25 @@ __global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restr
   }
 }
 
-template <int RECON>
-static hipError_t launch_adj_pencils(const double* U, const double* lam, double* wbar,
-                                     const BlockInfo* blocks, int32_t nblocks, const Geom& g,
-                                     const double* dtp, double beta, hipStream_t s) {
-  const int64_t npen[3] = {(int64_t)g.n2 * g.n3, (int64_t)g.n1 * g.n3, (int64_t)g.n1 * g.n2};
-  dim3 blk(256);
-  hipLaunchKernelGGL((adj_pencil_kernel<RECON, 0>), dim3((unsigned)((npen[0] * nblocks + 255) / 256)), blk,
-                     0, s, U, lam, wbar, blocks, nblocks, g, dtp, beta);
-  hipLaunchKernelGGL((adj_pencil_kernel<RECON, 1>), dim3((unsigned)((npen[1] * nblocks + 255) / 256)), blk,
-                     0, s, U, lam, wbar, blocks, nblocks, g, dtp, beta);
-  hipLaunchKernelGGL((adj_pencil_kernel<RECON, 2>), dim3((unsigned)((npen[2] * nblocks + 255) / 256)), blk,
-                     0, s, U, lam, wbar, blocks, nblocks, g, dtp, beta);
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar,
+hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar3,
                             const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                             const int32_t* nbr, const double* dtp, double beta, double* out,
                             const double* add0, const double* add1, hipStream_t s) {
-  hipError_t e = recon ? launch_adj_pencils<1>(U, lam, wbar, blocks, nblocks, g, dtp, beta, s)
-                       : launch_adj_pencils<0>(U, lam, wbar, blocks, nblocks, g, dtp, beta, s);
+  // one launch for the three directions: x pencils, y pencils, z pencils
+  const int64_t npen = (int64_t)nblocks * std::max(std::max((int64_t)g.n2 * g.n3, (int64_t)g.n1 * g.n3),
+                                                   (int64_t)g.n1 * g.n2);
+  const int64_t wstride = (int64_t)nblocks * g.bstride;
+  dim3 grid((unsigned)((npen + 255) / 256), 3);
+  if (recon)
+    hipLaunchKernelGGL(adj_pencils_kernel<1>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nblocks, g,
+                       dtp, beta);
+  else
+    hipLaunchKernelGGL(adj_pencils_kernel<0>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nblocks, g,
+                       dtp, beta);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)nblocks * g.n1 * g.n2 * g.n3;
-  hipLaunchKernelGGL(adj_exchange_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, wbar,
+  hipLaunchKernelGGL(adj_exchange_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, wbar3, wstride,
                      U, nbr, g, total, out, add0, add1);
   return hipGetLastError();
 }

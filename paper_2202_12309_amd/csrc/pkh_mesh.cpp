@@ -732,6 +732,29 @@ int pkh_set_refinement_flags(pkh_mesh* m, const int8_t* flags, int64_t n) {
   return PKH_OK;
 }
 
+int pkh_flag_pressure_jump(pkh_mesh* m, double refine_above, double derefine_below, int8_t* flags_out,
+                           double* eta_out) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  if (!(derefine_below <= refine_above)) return fail(PKH_EINVAL, "derefine threshold above refine threshold");
+  int rc;
+  if (!m->ghosts_valid && (rc = do_exchange(m))) return rc;
+  if ((rc = ensure_partials(m))) return rc;
+  const int64_t nb = m->nb();
+  std::vector<double> eta(nb);
+  HIPCHK(launch_eta(m->d_partial, m->A, (int32_t)nb, m->g, m->stream));
+  HIPCHK(hipMemcpyAsync(eta.data(), m->d_partial, nb * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if ((rc = check_err(m))) return rc;
+  m->flags.assign(nb, 0);
+  for (int64_t b = 0; b < nb; ++b) {
+    if (!(eta[b] == eta[b])) return fail(PKH_EPHYS, "non-finite pressure jump in leaf %lld", (long long)b);
+    m->flags[b] = eta[b] > refine_above ? 1 : (eta[b] < derefine_below ? -1 : 0);
+  }
+  if (flags_out) std::copy(m->flags.begin(), m->flags.end(), flags_out);
+  if (eta_out) std::copy(eta.begin(), eta.end(), eta_out);
+  return PKH_OK;
+}
+
 int pkh_regrid(pkh_mesh* m) {
   if (!m) return fail(PKH_EINVAL, "null mesh");
   const Tree& t = m->tree;
@@ -932,7 +955,7 @@ struct pkh_tape {
   int32_t dts_cap = 0;
   std::vector<double*> S;        // recomputed ghost-filled U^n, K + 1 of them
   std::vector<double*> Us;       // recomputed ghost-filled U*, K of them
-  double* wbar = nullptr;        // padded primitive-adjoint scratch
+  double* wbar = nullptr;        // padded primitive-adjoint scratch, one per direction
   double* lam[3] = {nullptr, nullptr, nullptr};  // active-layout adjoints
   DevTime* d_time = nullptr;     // clock for recomputation (dt from the record)
 };
@@ -1016,7 +1039,7 @@ int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
     ok = t->Us.back() != nullptr;
   }
   if (ok) {
-    t->wbar = (double*)m->dalloc(pb);
+    t->wbar = (double*)m->dalloc(3 * pb);
     for (auto& l : t->lam) l = (double*)m->dalloc(active_bytes(m));
     t->d_time = (DevTime*)m->dalloc(sizeof(DevTime));
     ok = t->wbar && t->lam[0] && t->lam[1] && t->lam[2] && t->d_time;

@@ -39,3 +39,26 @@ def rel_err(a, b, gamma):
 
 def print_case(msg):
     print(f"[case] {msg}", flush=True)
+
+
+def bump_directions(N, count, seed):
+    """Seeded perturbation directions on an N^3 periodic grid, [5][N][N][N]:
+    a Gaussian bump (unit variance in cells, cut at radius 3) with an N(0,1)
+    weight per conserved variable. The first is centred on the corner shared
+    by the eight blocks of a 2x2x2 decomposition; the others at random cells."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    out = []
+    for t in range(count):
+        c = np.full(3, N / 2 - 0.5) if t == 0 else rng.integers(0, N, 3).astype(float)
+        d = [np.minimum(np.abs(a - ca), N - np.abs(a - ca)) for a, ca in zip((x, y, z), c)]
+        r2 = d[0] ** 2 + d[1] ** 2 + d[2] ** 2
+        bump = np.exp(-0.5 * r2) * (r2 <= 9.0)
+        out.append(np.stack([bump * rng.normal() for _ in range(5)]))
+    return out
+
+
+def same_branches(log_a, log_b):
+    """True when two branch logs of the reference formulation agree entry by
+    entry (the two runs sit on the same smooth piece of the map)."""
+    return len(log_a) == len(log_b) and all(bool((a == b).all()) for a, b in zip(log_a, log_b))

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from _helpers import print_case
+from _helpers import bump_directions, print_case, same_branches
 from oracle import torch_ref
 from paper_2202_12309_amd import inputs
 
@@ -85,10 +85,13 @@ def _fd_check(mesh, U0, tgt, cycles, ckpt, dV, dirs, h, rtol):
 def test_gradient_matches_finite_differences_smooth_density():
     """The adjoint workload's state (gas at rest, uniform pressure, smooth
     density perturbation of 1e-3) on 16^3 as 8 blocks of 8^3, 50 cycles,
-    density-only directions. At density extrema the HLLE bound
-    max(u_roe + a_roe, u_R + c_R) and the limiter switch branch, so the loss
-    has kinks there; exact autograd of the reference shows the same
-    finite-difference scatter (~1e-4 relative), hence the tolerance."""
+    density-only directions. The velocities of this flow are of rounding
+    size, so limiter and wave-speed branches sit at ties: the reference
+    formulation switches about a fifth of its branches between the +h and
+    -h runs at every h from 1e-6 to 1e-8, and the map has kinks at the ulp
+    scale. Difference quotients scatter by ~1e-4 relative about the exact
+    derivative (autograd of the reference shows the same scatter), hence
+    the tolerance; the strict check is the next test."""
     print_case("adjoint vs FD 16^3 50 cycles, density directions")
     N, blk, cycles = 16, 8, 50
     mesh, lv, n, nrb, U0, tgt = _setup(N, blk)
@@ -100,17 +103,47 @@ def test_gradient_matches_finite_differences_smooth_density():
     assert _fd_check(mesh, U0, tgt, cycles, 10, 1.0 / N ** 3, dirs, 1e-8, 3e-3) == 3
 
 
-def test_gradient_matches_finite_differences_general_flow():
-    """A flow with velocity and pressure structure, smooth directions in
-    every conserved variable, 10 cycles, h = 1e-8 (the reference gradient
-    meets central differences there to 1e-6 or better)."""
-    print_case("adjoint vs FD 16^3 10 cycles, general flow")
-    N, blk, cycles = 16, 8, 10
+def test_gradient_matches_finite_differences_branch_consistent():
+    """A flow with velocity and pressure structure on 16^3 as 8 blocks of
+    8^3, 2 cycles, checkpoint every cycle; localized directions in all five
+    conserved variables (the first straddles the corner of all 8 blocks, so
+    the transposed ghost exchange is in the path). For each direction the
+    step h is the largest of a sweep for which the reference formulation
+    takes the same branches at +h and -h (no kink inside the segment); the
+    GPU's central difference then meets the GPU gradient to 1e-8."""
+    print_case("adjoint vs FD 16^3 2 cycles, branch-consistent localized directions")
+    N, blk, cycles = 16, 8, 2
     mesh, lv, n, nrb, U0, tgt = _setup(N, blk, amp=3e-2)
     U0 = U0 + 0.05 * inputs.turbulent_box(lv, n, nrb, seed=9) - 0.05 * inputs.uniform_state(lv, n)
-    rng = np.random.default_rng(4)
-    dirs = []
-    for trial in range(3):
-        base = inputs.smooth_density(lv, n, nrb, seed=50 + trial, amp=1.0)[:, 0] - 1.0
-        dirs.append(np.stack([base * rng.normal() for _ in range(5)], axis=1))
-    assert _fd_check(mesh, U0, tgt, cycles, 5, 1.0 / N ** 3, dirs, 1e-8, 1e-5) >= 2
+    dV = 1.0 / N ** 3
+    _, g, _ = _gpu_grad(mesh, U0, tgt, cycles, 1, dV)
+    tape = mesh.tape(1)
+    mesh.upload(U0)
+    tape.forward(cycles)
+    G0 = torch.tensor(torch_ref.blocks_to_global(U0, lv, n, nrb))
+    _, dts = torch_ref.run(G0, cycles)
+
+    def rho_of(U):
+        mesh.upload(U)
+        tape.replay()
+        return mesh.download()[:, 0] - tgt
+
+    accepted = []
+    for V in bump_directions(N, 8, seed=3):
+        v = torch_ref.global_to_blocks(V, lv, n)
+        dirder = float((g * v).sum())
+        Vt = torch.tensor(V)
+        for h in (1e-5, 3e-6, 1e-6, 3e-7):
+            lp, lm = [], []
+            with torch.no_grad():
+                torch_ref.run(G0 + h * Vt, cycles, dts=dts, log=lp)
+                torch_ref.run(G0 - h * Vt, cycles, dts=dts, log=lm)
+            if not same_branches(lp, lm):
+                continue
+            ap, am = rho_of(U0 + h * v), rho_of(U0 - h * v)
+            fd = float((0.5 * (ap - am) * (ap + am)).sum() * dV / (2 * h))
+            print("h", h, "dirder", dirder, "fd", fd, "rel", (fd - dirder) / dirder, flush=True)
+            accepted.append(abs(fd - dirder) / abs(dirder))
+            break
+    assert len(accepted) >= 3, accepted
+    assert max(accepted) <= 1e-8, accepted

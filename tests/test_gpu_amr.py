@@ -1,0 +1,76 @@
+"""Two-level blast with regridding: the device pressure-jump indicator
+against the oracle's, and the cycle-plus-regrid loop against the oracle with
+the flags the oracle computes shared by both sides (so the meshes stay
+identical). Runs on an MI355X."""
+import numpy as np
+import pytest
+
+from _helpers import print_case, rel_err
+from oracle.oracle import OracleMesh
+from paper_2202_12309_amd import inputs
+
+pytestmark = pytest.mark.gpu
+G = 5.0 / 3.0
+REFINE, DEREFINE = 0.1, 0.02
+
+
+def _blast_pair(nrb, blk=16, radius=0.25):
+    from paper_2202_12309_amd.binding import Mesh
+    n = (blk,) * 3
+    leaves = inputs.sphere_refined_leaves(nrb, radius=radius)
+    gm = Mesh(tuple(nrb[d] * blk for d in range(3)), n, leaves, max_level=1)
+    om = OracleMesh(n, nrb, leaves, max_level=1)
+    assert np.array_equal(gm.leaves(), om.leaves())
+    U0 = inputs.blast(gm.leaves(), n, nrb)
+    gm.upload(U0)
+    om.set_state(U0)
+    return gm, om
+
+
+def _flags(eta):
+    return np.where(eta > REFINE, 1, np.where(eta < DEREFINE, -1, 0)).astype(np.int8)
+
+
+def test_pressure_jump_indicator_matches_oracle():
+    print_case("pressure-jump indicator, 128^3 root in 16^3 blocks, two levels, 10 cycles")
+    gm, om = _blast_pair((8, 8, 8))
+    gm.step(10)
+    om.step(10)
+    fg, eg = gm.flag_pressure_jump(REFINE, DEREFINE)
+    eo = om.pressure_jump()
+    assert np.all(np.abs(eg - eo) <= 1e-10 * np.maximum(eo, 1e-3)), np.abs(eg - eo).max()
+    fo = _flags(eo)
+    # the decision is the same except where eta sits within rounding of a threshold
+    near = (np.abs(eo - REFINE) <= 1e-9) | (np.abs(eo - DEREFINE) <= 1e-9)
+    assert np.array_equal(fg[~near], fo[~near])
+    assert (fg == 1).sum() > 0 and (fg == -1).sum() > 0
+
+
+def _regrid_loop(gm, om, segments, every):
+    for s in range(segments):
+        gm.step(every)
+        om.step(every)
+        c = (s + 1) * every
+        err = rel_err(gm.download(), om.state(), G)
+        print(f"cycle {c}: leaves {gm.nleaves}, rel err {err}", flush=True)
+        assert np.all(err <= 1e-11 * c), (c, err)
+        To, Ao = om.totals()
+        assert np.all(np.abs(gm.totals() - To) <= 1e-13 * np.maximum(Ao, 1.0))
+        flags = _flags(om.pressure_jump())
+        gm.regrid(flags)
+        om.regrid(flags)
+        assert np.array_equal(gm.leaves(), om.leaves())
+        assert np.all(rel_err(gm.download(), om.state(), G) <= 1e-11 * c)
+
+
+def test_two_level_blast_regrid_parity_full_size():
+    print_case("two-level blast, 128^3 root, 960 leaves, 30 cycles, regrid every 10")
+    gm, om = _blast_pair((8, 8, 8))
+    assert gm.nleaves == 960
+    _regrid_loop(gm, om, 3, 10)
+
+
+def test_two_level_blast_regrid_parity_100_cycles():
+    print_case("two-level blast, 64^3 root, 100 cycles, regrid every 10")
+    gm, om = _blast_pair((4, 4, 4), radius=0.3)
+    _regrid_loop(gm, om, 10, 10)
