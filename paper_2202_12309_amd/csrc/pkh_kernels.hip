@@ -1085,11 +1085,9 @@ __device__ __forceinline__ void adj_pencil(const double* __restrict__ U, const d
   const int64_t abase = (int64_t)b * NV * ncell + (int64_t)c3[2] * ast[2] + (int64_t)c3[1] * ast[1] + c3[0];
   const int ps = pst[D], as = ast[D];
 
-  auto loadw = [&](int s, double w[NV]) {
-    double u[NV];
+  auto loadu = [&](int s, double u[NV]) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = U[pbase + (int64_t)v * g.vstride + (int64_t)s * ps];
-    to_prim(u, gam, w);
   };
   auto loadl = [&](int s, double l[NV]) {
 #pragma unroll
@@ -1100,86 +1098,419 @@ __device__ __forceinline__ void adj_pencil(const double* __restrict__ U, const d
 #pragma unroll
     for (int v = 0; v < NV; ++v) o[(int64_t)v * g.vstride] = acc[v];
   };
+  // face f lies between cells f-1 and f; its flux enters cell f-1 with +coef
+  // and cell f with -coef, so its adjoint is coef * (lam(f) - lam(f-1))
+  double un[NV], lp[NV], ln[NV];
+  const double zero5[NV] = {0, 0, 0, 0, 0};
 
-  double W[4][NV];   // states of cells f-2 .. f+1
-  double acc[4][NV]; // adjoints of cells f-2 .. f+1
-  double lm1[NV], l0[NV];
+  if constexpr (!RECON) {
+    // donor cell: the face states are the cell states, so each cell's
+    // derived state is formed once and its adjoint reversed once, after both
+    // of its faces have been swept
+    FState Qa, Qb;
+    double gQa[8], gQb[8];
+    auto state_of = [&](const double u[NV], FState& q) {
+      double w[NV];
+      to_prim(u, gam, w);
+      q = FState{w[0], w[1], w[2], w[3], w[4], 0, 0, 0};
+      complete_state(q, gam, igm1);
+    };
+    loadu(-1, un);
+    state_of(un, Qa);
+    loadu(0, un);
+    state_of(un, Qb);
+    loadu(1, un);  // next cell, one iteration ahead
+    loadl(-1, lp);
+    loadl(0, ln);
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 8; ++k) gQa[k] = gQb[k] = 0.0;
+    emit(-2, zero5);
+    for (int f = 0; f <= nd; ++f) {
+      double mu[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[k][v] = W[k][v] = 0.0;
-  loadw(-2, W[1]);
-  loadw(-1, W[2]);
-  loadw(0, W[3]);
-  loadl(-1, l0);
-  for (int f = 0; f <= nd; ++f) {
-    // shift the state window to cells f-2 .. f+1
+      for (int v = 0; v < NV; ++v) mu[v] = coef * (ln[v] - lp[v]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+      for (int v = 0; v < NV; ++v) lp[v] = ln[v];
+      loadl(f + 1, ln);
+      hlle_rev<D>(Qa, Qb, gm1, mu, gQa, gQb);
+      double gw[NV] = {0, 0, 0, 0, 0};
+      complete_state_rev(Qa, gam, igm1, gQa, gw);
+      emit(f - 1, gw);
+      if (f < nd) {
+        Qa = Qb;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) W[k][v] = W[k + 1][v];
-    loadw(f + 1, W[3]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) lm1[v] = l0[v];
-    loadl(f, l0);
-    double mu[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) mu[v] = coef * (l0[v] - lm1[v]);
-    double gl[NV] = {0, 0, 0, 0, 0}, gr[NV] = {0, 0, 0, 0, 0};
-    FState L, R;
-    double wl[NV], wr[NV];
-    if constexpr (RECON) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        wl[v] = W[1][v] + 0.5 * mc_slope(W[1][v] - W[0][v], W[2][v] - W[1][v]);
-        wr[v] = W[2][v] - 0.5 * mc_slope(W[2][v] - W[1][v], W[3][v] - W[2][v]);
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        wl[v] = W[1][v];
-        wr[v] = W[2][v];
+        for (int k = 0; k < 8; ++k) {
+          gQa[k] = gQb[k];
+          gQb[k] = 0.0;
+        }
+        state_of(un, Qb);
+        if (f + 2 <= nd) loadu(f + 2, un);
       }
     }
-    L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
-    R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+    double gw[NV] = {0, 0, 0, 0, 0};
+    complete_state_rev(Qb, gam, igm1, gQb, gw);
+    emit(nd, gw);
+    emit(nd + 1, zero5);
+  } else {
+    // PLM: window of primitives of cells f-1, f, f+1; the limited slope of
+    // each cell and its branch derivatives are formed once, when the cell's
+    // right neighbour arrives, and used by both faces of the cell
+    double W0[NV], W1[NV], W2[NV];  // cells f-1, f, f+1
+    double Sp[NV], Gap[NV], Gbp[NV];  // slope of cell f-1 and d slope / d (dl, dr)
+    double acc0[NV], acc1[NV], acc2[NV], acc3[NV];  // cells f-2 .. f+1
+    {
+      double Wm[NV];
+      loadu(-2, un);
+      to_prim(un, gam, Wm);
+      loadu(-1, un);
+      to_prim(un, gam, W1);
+      loadu(0, un);
+      to_prim(un, gam, W2);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double dl = W1[v] - Wm[v], dr = W2[v] - W1[v];
+        Sp[v] = mc_slope(dl, dr);
+        mc_branch(dl, dr, Gap[v], Gbp[v]);
+      }
+    }
+    loadu(1, un);
+    loadl(-1, lp);
+    loadl(0, ln);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc0[v] = acc1[v] = acc2[v] = acc3[v] = 0.0;
+    for (int f = 0; f <= nd; ++f) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        W0[v] = W1[v];
+        W1[v] = W2[v];
+      }
+      to_prim(un, gam, W2);
+      if (f + 2 <= nd + 1) loadu(f + 2, un);
+      double mu[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) mu[v] = coef * (ln[v] - lp[v]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lp[v] = ln[v];
+      loadl(f + 1, ln);
+      double Sc[NV], Gac[NV], Gbc[NV];
+      double wl[NV], wr[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double dl = W1[v] - W0[v], dr = W2[v] - W1[v];
+        Sc[v] = mc_slope(dl, dr);
+        mc_branch(dl, dr, Gac[v], Gbc[v]);
+        wl[v] = W0[v] + 0.5 * Sp[v];
+        wr[v] = W1[v] - 0.5 * Sc[v];
+      }
+      FState L{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+      FState R{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+      complete_state(L, gam, igm1);
+      complete_state(R, gam, igm1);
+      double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      hlle_rev<D>(L, R, gm1, mu, gL, gR);
+      double gl[NV] = {0, 0, 0, 0, 0}, gr[NV] = {0, 0, 0, 0, 0};
+      complete_state_rev(L, gam, igm1, gL, gl);
+      complete_state_rev(R, gam, igm1, gR, gr);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        // wl = W(f-1) + s(f-1)/2, s(f-1) = MC(W(f-1) - W(f-2), W(f) - W(f-1))
+        acc0[v] -= gl[v] * 0.5 * Gap[v];
+        acc1[v] += gl[v] * (1.0 + 0.5 * Gap[v] - 0.5 * Gbp[v]);
+        acc2[v] += gl[v] * 0.5 * Gbp[v];
+        // wr = W(f) - s(f)/2, s(f) = MC(W(f) - W(f-1), W(f+1) - W(f))
+        acc1[v] += gr[v] * 0.5 * Gac[v];
+        acc2[v] += gr[v] * (1.0 - 0.5 * Gac[v] + 0.5 * Gbc[v]);
+        acc3[v] -= gr[v] * 0.5 * Gbc[v];
+        Sp[v] = Sc[v];
+        Gap[v] = Gac[v];
+        Gbp[v] = Gbc[v];
+      }
+      emit(f - 2, acc0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        acc0[v] = acc1[v];
+        acc1[v] = acc2[v];
+        acc2[v] = acc3[v];
+        acc3[v] = 0.0;
+      }
+    }
+    emit(nd - 1, acc0);
+    emit(nd, acc1);
+    emit(nd + 1, acc2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x direction of the reverse sweep, face-parallel along rows. A pencil walk
+// along x would put every lane of a wave on a different row of the
+// contiguous dimension; here lane i of an n1-wide lane segment owns cell i
+// of one row and the face below it (face i, between cells i-1 and i), so
+// loads and stores are coalesced. Neighbour states and the contributions a
+// face makes to cells i-2 .. i+1 move between lanes by shuffles within the
+// segment. The face above the last cell (face n1) has no lane; a separate
+// pass computes it for every row first and leaves its contributions in a
+// side buffer (20 doubles per row) that the row pass merges.
+// ---------------------------------------------------------------------------
+
+// Side-buffer slot q of row `row` (slot-major, rows fastest).
+__device__ __forceinline__ int64_t xlast_at(int64_t nrows, int q, int64_t row) {
+  return (int64_t)q * nrows + row;
+}
+
+template <int RECON>
+__global__ void __launch_bounds__(256) adj_xlast_kernel(const double* __restrict__ U,
+                                                        const double* __restrict__ lam,
+                                                        double* __restrict__ xl, const BlockInfo* blocks,
+                                                        int nblocks, Geom g, const double* dtp, double beta) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rpb = (int64_t)g.n2 * g.n3;
+  const int64_t nrows = rpb * nblocks;
+  if (row >= nrows) return;
+  const int b = (int)(row / rpb);
+  const int r = (int)(row - (int64_t)b * rpb);
+  const int j = r % g.n2, k = r / g.n2;
+  const int nd = g.n1;
+  const double gam = g.gamma, gm1 = gam - 1.0, igm1 = 1.0 / gm1;
+  const double coef = beta * (*dtp) * blocks[b].idx[0];
+  const int64_t pbase = (int64_t)b * g.bstride + ((int64_t)(k + NG) * g.p2 + (j + NG)) * g.p1 + NG;
+  const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
+  const int64_t abase = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
+  auto loadw = [&](int s, double w[NV]) {
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[pbase + (int64_t)v * g.vstride + s];
+    to_prim(u, gam, w);
+  };
+  double mu[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) mu[v] = -coef * lam[abase + (int64_t)v * ncell + (nd - 1)];
+  if constexpr (RECON) {
+    double W0[NV], W1[NV], W2[NV], W3[NV];  // cells nd-2 .. nd+1
+    loadw(nd - 2, W0);
+    loadw(nd - 1, W1);
+    loadw(nd, W2);
+    loadw(nd + 1, W3);
+    double ga0[NV], gb0[NV], ga1[NV], gb1[NV], wl[NV], wr[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double s0 = mc_slope(W1[v] - W0[v], W2[v] - W1[v]);
+      mc_branch(W1[v] - W0[v], W2[v] - W1[v], ga0[v], gb0[v]);
+      const double s1 = mc_slope(W2[v] - W1[v], W3[v] - W2[v]);
+      mc_branch(W2[v] - W1[v], W3[v] - W2[v], ga1[v], gb1[v]);
+      wl[v] = W1[v] + 0.5 * s0;
+      wr[v] = W2[v] - 0.5 * s1;
+    }
+    FState L{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+    FState R{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
     complete_state(L, gam, igm1);
     complete_state(R, gam, igm1);
     double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    hlle_rev<D>(L, R, gm1, mu, gL, gR);
+    hlle_rev<0>(L, R, gm1, mu, gL, gR);
+    double gl[NV] = {0, 0, 0, 0, 0}, gr[NV] = {0, 0, 0, 0, 0};
     complete_state_rev(L, gam, igm1, gL, gl);
     complete_state_rev(R, gam, igm1, gR, gr);
-    if constexpr (RECON) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double ga, gb;
-        mc_branch(W[1][v] - W[0][v], W[2][v] - W[1][v], ga, gb);
-        acc[1][v] += gl[v] * (1.0 + 0.5 * ga - 0.5 * gb);
-        acc[0][v] -= gl[v] * 0.5 * ga;
-        acc[2][v] += gl[v] * 0.5 * gb;
-        mc_branch(W[2][v] - W[1][v], W[3][v] - W[2][v], ga, gb);
-        acc[2][v] += gr[v] * (1.0 - 0.5 * ga + 0.5 * gb);
-        acc[1][v] += gr[v] * 0.5 * ga;
-        acc[3][v] -= gr[v] * 0.5 * gb;
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        acc[1][v] += gl[v];
-        acc[2][v] += gr[v];
-      }
+    for (int v = 0; v < NV; ++v) {
+      xl[xlast_at(nrows, 0 * NV + v, row)] = -gl[v] * 0.5 * ga0[v];
+      xl[xlast_at(nrows, 1 * NV + v, row)] = gl[v] * (1.0 + 0.5 * ga0[v] - 0.5 * gb0[v]) + gr[v] * 0.5 * ga1[v];
+      xl[xlast_at(nrows, 2 * NV + v, row)] = gl[v] * 0.5 * gb0[v] + gr[v] * (1.0 - 0.5 * ga1[v] + 0.5 * gb1[v]);
+      xl[xlast_at(nrows, 3 * NV + v, row)] = -gr[v] * 0.5 * gb1[v];
     }
-    emit(f - 2, acc[0]);
+  } else {
+    double wa[NV], wb[NV];
+    loadw(nd - 1, wa);
+    loadw(nd, wb);
+    FState Qa{wa[0], wa[1], wa[2], wa[3], wa[4], 0, 0, 0};
+    FState Qb{wb[0], wb[1], wb[2], wb[3], wb[4], 0, 0, 0};
+    complete_state(Qa, gam, igm1);
+    complete_state(Qb, gam, igm1);
+    double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    hlle_rev<0>(Qa, Qb, gm1, mu, gL, gR);
+    double gw[NV] = {0, 0, 0, 0, 0};
+    complete_state_rev(Qb, gam, igm1, gR, gw);
+    // slots 0..7: derived-state adjoint of cell nd-1; 8..12: cell nd
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int q = 0; q < 8; ++q) xl[xlast_at(nrows, q, row)] = gL[q];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[k][v] = acc[k + 1][v];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[3][v] = 0.0;
+    for (int v = 0; v < NV; ++v) xl[xlast_at(nrows, 8 + v, row)] = gw[v];
   }
-  emit(nd - 1, acc[0]);
-  emit(nd, acc[1]);
-  emit(nd + 1, acc[2]);
+}
+
+// Lane shuffles within segments of W lanes (one row each); a lane whose
+// source falls outside its segment gets its own value back.
+template <int W>
+__device__ __forceinline__ double shup(double x, int d) {
+  return __shfl_up(x, d, W);
+}
+template <int W>
+__device__ __forceinline__ double shdn(double x, int d) {
+  return __shfl_down(x, d, W);
+}
+
+template <int RECON, int N1>
+__global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict__ U,
+                                                       const double* __restrict__ lam,
+                                                       double* __restrict__ wbar,
+                                                       const double* __restrict__ xl,
+                                                       const BlockInfo* blocks, int nblocks, Geom g,
+                                                       const double* dtp, double beta) {
+  static_assert(N1 == 8 || N1 == 16 || N1 == 32 || N1 == 64, "row width");
+  const int i = (int)(threadIdx.x % N1);
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / N1;
+  const int64_t rpb = (int64_t)g.n2 * g.n3;
+  const int64_t nrows = rpb * nblocks;
+  // every lane of a segment shares the row, so whole segments leave together
+  if (row >= nrows) return;
+  const int b = (int)(row / rpb);
+  const int r = (int)(row - (int64_t)b * rpb);
+  const int j = r % g.n2, k = r / g.n2;
+  const double gam = g.gamma, gm1 = gam - 1.0, igm1 = 1.0 / gm1;
+  const double coef = beta * (*dtp) * blocks[b].idx[0];
+  const int64_t pbase = (int64_t)b * g.bstride + ((int64_t)(k + NG) * g.p2 + (j + NG)) * g.p1 + NG;
+  const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
+  const int64_t abase = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
+  auto loadw = [&](int s, double w[NV]) {
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[pbase + (int64_t)v * g.vstride + s];
+    to_prim(u, gam, w);
+  };
+  auto emit = [&](int s, const double a[NV]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wbar[pbase + (int64_t)v * g.vstride + s] = a[v];
+  };
+  // face i adjoint: coef * (lam(i) - lam(i-1)), lam(-1) = 0
+  double mu[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double l0 = lam[abase + (int64_t)v * ncell + i];
+    const double lm = shup<N1>(l0, 1);
+    mu[v] = coef * (l0 - (i > 0 ? lm : 0.0));
+  }
+  const bool first = i == 0, last = i == N1 - 1;
+
+  if constexpr (RECON) {
+    // own cell, and the ghost cell a segment-edge lane needs: lane 0 cell -2,
+    // lane 1 cell -1, last lane cell n1
+    double W[NV], Wx[NV];
+    loadw(i, W);
+    const int sx = i == 0 ? -2 : (i == 1 ? -1 : N1);
+    loadw(sx, Wx);
+    double Wm1[NV], Wm2[NV], Wp1[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double a1 = shup<N1>(W[v], 1), a2 = shup<N1>(W[v], 2), p1 = shdn<N1>(W[v], 1);
+      const double gm = shdn<N1>(Wx[v], 1);  // lane 0 <- lane 1's ghost (cell -1)
+      Wm1[v] = first ? gm : a1;
+      Wm2[v] = first ? Wx[v] : (i == 1 ? Wx[v] : a2);
+      Wp1[v] = last ? Wx[v] : p1;
+    }
+    double ga0[NV], gb0[NV], ga1[NV], gb1[NV], wl[NV], wr[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      // slope of cell i-1 (left state of the face) and of cell i (right state)
+      const double s0 = mc_slope(Wm1[v] - Wm2[v], W[v] - Wm1[v]);
+      mc_branch(Wm1[v] - Wm2[v], W[v] - Wm1[v], ga0[v], gb0[v]);
+      const double s1 = mc_slope(W[v] - Wm1[v], Wp1[v] - W[v]);
+      mc_branch(W[v] - Wm1[v], Wp1[v] - W[v], ga1[v], gb1[v]);
+      wl[v] = Wm1[v] + 0.5 * s0;
+      wr[v] = W[v] - 0.5 * s1;
+    }
+    FState L{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+    FState R{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+    complete_state(L, gam, igm1);
+    complete_state(R, gam, igm1);
+    double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    hlle_rev<0>(L, R, gm1, mu, gL, gR);
+    double gl[NV] = {0, 0, 0, 0, 0}, gr[NV] = {0, 0, 0, 0, 0};
+    complete_state_rev(L, gam, igm1, gL, gl);
+    complete_state_rev(R, gam, igm1, gR, gr);
+    // contributions of face i to cells i-2 .. i+1, summed per cell across lanes
+    double own[NV], gm2[NV], gm1c[NV], gp3[NV], gp4[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double c0 = -gl[v] * 0.5 * ga0[v];
+      const double c1 = gl[v] * (1.0 + 0.5 * ga0[v] - 0.5 * gb0[v]) + gr[v] * 0.5 * ga1[v];
+      const double c2 = gl[v] * 0.5 * gb0[v] + gr[v] * (1.0 - 0.5 * ga1[v] + 0.5 * gb1[v]);
+      const double c3 = -gr[v] * 0.5 * gb1[v];
+      const double f1 = shdn<N1>(c1, 1), f0 = shdn<N1>(c0, 2), b3 = shup<N1>(c3, 1);
+      const double f0n = shdn<N1>(c0, 1);
+      // face n1 (side buffer): k0 -> cell n1-2, k1 -> n1-1, k2 -> n1, k3 -> n1+1
+      double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+      if (i == N1 - 2) x0 = xl[xlast_at(nrows, 0 * NV + v, row)];
+      if (last) {
+        x1 = xl[xlast_at(nrows, 1 * NV + v, row)];
+        x2 = xl[xlast_at(nrows, 2 * NV + v, row)];
+        x3 = xl[xlast_at(nrows, 3 * NV + v, row)];
+      }
+      double a = c2 + (first ? 0.0 : b3);
+      a += last ? x1 : f1;
+      a += (i >= N1 - 2) ? x0 : f0;
+      own[v] = a;
+      gm2[v] = c0;         // lane 0: cell -2
+      gm1c[v] = c1 + f0n;  // lane 0: cell -1
+      gp3[v] = c3 + x2;    // last lane: cell n1
+      gp4[v] = x3;         // last lane: cell n1+1
+    }
+    emit(i, own);
+    if (first) {
+      emit(-2, gm2);
+      emit(-1, gm1c);
+    }
+    if (last) {
+      emit(N1, gp3);
+      emit(N1 + 1, gp4);
+    }
+  } else {
+    // donor cell: face i joins cells i-1 and i; each lane forms its cell's
+    // derived state, lane 0 also that of cell -1
+    double W[NV];
+    loadw(i, W);
+    FState Q{W[0], W[1], W[2], W[3], W[4], 0, 0, 0};
+    complete_state(Q, gam, igm1);
+    FState Qm;
+    {
+      const double m[8] = {shup<N1>(Q.r, 1),  shup<N1>(Q.v0, 1), shup<N1>(Q.v1, 1), shup<N1>(Q.v2, 1),
+                           shup<N1>(Q.p, 1),  shup<N1>(Q.sr, 1), shup<N1>(Q.c, 1),  shup<N1>(Q.h, 1)};
+      Qm = FState{m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7]};
+    }
+    FState Qg = Q;
+    if (first) {
+      double Wg[NV];
+      loadw(-1, Wg);
+      Qg = FState{Wg[0], Wg[1], Wg[2], Wg[3], Wg[4], 0, 0, 0};
+      complete_state(Qg, gam, igm1);
+      Qm = Qg;
+    }
+    double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    hlle_rev<0>(Qm, Q, gm1, mu, gL, gR);
+    // cell i: right-state part of face i plus left-state part of face i+1
+    double gQ[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double nb = shdn<N1>(gL[q], 1);
+      double x = 0.0;
+      if (last) x = xl[xlast_at(nrows, q, row)];
+      gQ[q] = gR[q] + (last ? x : nb);
+    }
+    double gw[NV] = {0, 0, 0, 0, 0};
+    complete_state_rev(Q, gam, igm1, gQ, gw);
+    emit(i, gw);
+    const double zero5[NV] = {0, 0, 0, 0, 0};
+    if (first) {
+      double gg[NV] = {0, 0, 0, 0, 0};
+      complete_state_rev(Qg, gam, igm1, gL, gg);
+      emit(-1, gg);
+      emit(-2, zero5);
+    }
+    if (last) {
+      double gn[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) gn[v] = xl[xlast_at(nrows, 8 + v, row)];
+      emit(N1, gn);
+      emit(N1 + 1, zero5);
+    }
+  }
 }
 
 template <int RECON>
@@ -1187,9 +1518,9 @@ __global__ void __launch_bounds__(256) adj_pencils_kernel(const double* __restri
                                                           const double* __restrict__ lam,
                                                           double* __restrict__ wbar3, int64_t wstride,
                                                           const BlockInfo* blocks, int nblocks, Geom g,
-                                                          const double* dtp, double beta) {
+                                                          const double* dtp, double beta, int dir0) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  switch (blockIdx.y) {
+  switch (blockIdx.y + dir0) {
     case 0:
       adj_pencil<RECON, 0>(U, lam, wbar3, blocks, nblocks, g, dtp, beta, gid);
       break;
@@ -1252,21 +1583,59 @@ __global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restr
   }
 }
 
-hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar3,
+template <int RECON>
+static void launch_xrow(int n1, dim3 grid, hipStream_t s, const double* U, const double* lam, double* wx,
+                        const double* xl, const BlockInfo* blocks, int nblocks, const Geom& g,
+                        const double* dtp, double beta) {
+  switch (n1) {
+    case 8:
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 8>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nblocks, g, dtp,
+                         beta);
+      break;
+    case 16:
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 16>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nblocks, g, dtp,
+                         beta);
+      break;
+    case 32:
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 32>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nblocks, g, dtp,
+                         beta);
+      break;
+    default:
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 64>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nblocks, g, dtp,
+                         beta);
+  }
+}
+
+bool adj_xrow_supported(int n1) { return n1 == 8 || n1 == 16 || n1 == 32 || n1 == 64; }
+
+hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar3, double* xlast,
                             const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                             const int32_t* nbr, const double* dtp, double beta, double* out,
                             const double* add0, const double* add1, hipStream_t s) {
-  // one launch for the three directions: x pencils, y pencils, z pencils
   const int64_t npen = (int64_t)nblocks * std::max(std::max((int64_t)g.n2 * g.n3, (int64_t)g.n1 * g.n3),
                                                    (int64_t)g.n1 * g.n2);
   const int64_t wstride = (int64_t)nblocks * g.bstride;
-  dim3 grid((unsigned)((npen + 255) / 256), 3);
+  // x: last face of every row, then the rows face-parallel; y and z: pencils
+  const bool rows = adj_xrow_supported(g.n1) && xlast != nullptr;
+  if (rows) {
+    const int64_t nrows = (int64_t)nblocks * g.n2 * g.n3;
+    const dim3 gl((unsigned)((nrows + 255) / 256)), gr((unsigned)((nrows * g.n1 + 255) / 256));
+    if (recon) {
+      hipLaunchKernelGGL(adj_xlast_kernel<1>, gl, dim3(256), 0, s, U, lam, xlast, blocks, nblocks, g, dtp, beta);
+      launch_xrow<1>(g.n1, gr, s, U, lam, wbar3, xlast, blocks, nblocks, g, dtp, beta);
+    } else {
+      hipLaunchKernelGGL(adj_xlast_kernel<0>, gl, dim3(256), 0, s, U, lam, xlast, blocks, nblocks, g, dtp, beta);
+      launch_xrow<0>(g.n1, gr, s, U, lam, wbar3, xlast, blocks, nblocks, g, dtp, beta);
+    }
+  }
+  const int dir0 = rows ? 1 : 0;
+  dim3 grid((unsigned)((npen + 255) / 256), 3 - dir0);
   if (recon)
     hipLaunchKernelGGL(adj_pencils_kernel<1>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nblocks, g,
-                       dtp, beta);
+                       dtp, beta, dir0);
   else
     hipLaunchKernelGGL(adj_pencils_kernel<0>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nblocks, g,
-                       dtp, beta);
+                       dtp, beta, dir0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)nblocks * g.n1 * g.n2 * g.n3;

@@ -956,6 +956,7 @@ struct pkh_tape {
   std::vector<double*> S;        // recomputed ghost-filled U^n, K + 1 of them
   std::vector<double*> Us;       // recomputed ghost-filled U*, K of them
   double* wbar = nullptr;        // padded primitive-adjoint scratch, one per direction
+  double* xlast = nullptr;       // last x-face of every row, 20 doubles per row
   double* lam[3] = {nullptr, nullptr, nullptr};  // active-layout adjoints
   DevTime* d_time = nullptr;     // clock for recomputation (dt from the record)
 };
@@ -975,10 +976,12 @@ void tape_free(pkh_tape* t) {
   t->Us.clear();
   m->dfree(t->d_dts);
   m->dfree(t->wbar);
+  m->dfree(t->xlast);
   for (auto& l : t->lam) m->dfree(l);
   m->dfree(t->d_time);
   t->d_dts = nullptr;
   t->wbar = nullptr;
+  t->xlast = nullptr;
   t->d_time = nullptr;
   for (auto& l : t->lam) l = nullptr;
 }
@@ -1040,9 +1043,10 @@ int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
   }
   if (ok) {
     t->wbar = (double*)m->dalloc(3 * pb);
+    t->xlast = (double*)m->dalloc((size_t)m->nb() * m->g.n2 * m->g.n3 * 20 * sizeof(double));
     for (auto& l : t->lam) l = (double*)m->dalloc(active_bytes(m));
     t->d_time = (DevTime*)m->dalloc(sizeof(DevTime));
-    ok = t->wbar && t->lam[0] && t->lam[1] && t->lam[2] && t->d_time;
+    ok = t->wbar && t->xlast && t->lam[0] && t->lam[1] && t->lam[2] && t->d_time;
   }
   if (!ok) {
     tape_free(t);
@@ -1123,12 +1127,12 @@ int pkh_adjoint(pkh_mesh* m, pkh_tape* t, const double* lam_final, double* grad_
       const double* dtp = t->d_dts + c0 + q;
       {  // corrector: lam* = (dU^{n+1}/dU*)^T lam
         KTimer kt(m, 4, false);
-        HIPCHK(launch_adj_stage(PKH_RECON_PLM, t->Us[q], lam, t->wbar, m->d_blocks, nb, m->g, m->d_nbr,
+        HIPCHK(launch_adj_stage(PKH_RECON_PLM, t->Us[q], lam, t->wbar, t->xlast, m->d_blocks, nb, m->g, m->d_nbr,
                                 dtp, 1.0, lam_star, nullptr, nullptr, m->stream));
       }
       {  // predictor and the identities: lam^n = lam + lam* + (dU*/dU^n)^T-term of lam*
         KTimer kt(m, 4, false);
-        HIPCHK(launch_adj_stage(m->cfg.stage1_recon, t->S[q], lam_star, t->wbar, m->d_blocks, nb, m->g,
+        HIPCHK(launch_adj_stage(m->cfg.stage1_recon, t->S[q], lam_star, t->wbar, t->xlast, m->d_blocks, nb, m->g,
                                 m->d_nbr, dtp, 0.5, lam_new, lam, lam_star, m->stream));
       }
       std::swap(lam, lam_new);

@@ -161,7 +161,7 @@ PKH_HD void mc_branch(double dl, double dr, double& ga, double& gb) {
 // accumulates the primitive adjoint into gw.
 PKH_HD void complete_state_rev(const FState& q, double gam, double igm1, const double g[8],
                                double gw[NVAR]) {
-  const double ir = 1.0 / q.r;
+  const double ir = frcp(q.r);
   const double v2 = q.v0 * q.v0 + q.v1 * q.v1 + q.v2 * q.v2;
   const double e = q.p * igm1 + 0.5 * q.r * v2;
   double gr = g[0], gp = g[4], gir = 0.0;
@@ -171,7 +171,7 @@ PKH_HD void complete_state_rev(const FState& q, double gam, double igm1, const d
   gp += g[7] * ir;
   gir += g[7] * (e + q.p);
   // c = sqrt(gam p / r)
-  const double hc = 0.5 / q.c;
+  const double hc = 0.5 * frcp(q.c);
   gp += g[6] * gam * ir * hc;
   gir += g[6] * gam * q.p * hc;
   // e = p/(gam-1) + r |v|^2 / 2
@@ -181,7 +181,7 @@ PKH_HD void complete_state_rev(const FState& q, double gam, double igm1, const d
   gv[1] += ge * q.r * q.v1;
   gv[2] += ge * q.r * q.v2;
   // sr = sqrt(r), ir = 1/r
-  gr += g[5] * 0.5 / q.sr;
+  gr += g[5] * 0.5 * frcp(q.sr);
   gr -= gir * ir * ir;
   gw[0] += gr;
   gw[1] += gv[0];
@@ -197,14 +197,14 @@ PKH_HD void hlle_rev(const FState& L, const FState& R, double gm1, const double 
                      double gL[8], double gR[8], int drt = 0) {
   const int d = D >= 0 ? D : drt;
   // forward recomputation
-  const double isum = 1.0 / (L.sr + R.sr);
+  const double isum = frcp(L.sr + R.sr);
   const double r = L.sr * isum, r1 = 1.0 - r;
   const double vl[3] = {L.v0, L.v1, L.v2}, vr[3] = {R.v0, R.v1, R.v2};
   double vb[3];
   for (int c = 0; c < 3; ++c) vb[c] = r * vl[c] + r1 * vr[c];
   const double hb = r * L.h + r1 * R.h;
   const double q = hb - 0.5 * (vb[0] * vb[0] + vb[1] * vb[1] + vb[2] * vb[2]);
-  const double ab = sqrt(gm1 * q);
+  const double ab = fsqrt(gm1 * q);
   const double vbn = vb[d], ul = vl[d], ur = vr[d];
   const double a1 = vbn + ab, a2 = ur + R.c;
   const int kp = (a1 >= a2 && a1 >= 0.0) ? 0 : (a2 >= 0.0 ? 1 : 2);
@@ -212,7 +212,7 @@ PKH_HD void hlle_rev(const FState& L, const FState& R, double gm1, const double 
   const double b1 = vbn - ab, b2 = ul - L.c;
   const int km = (b1 <= b2 && b1 <= 0.0) ? 0 : (b2 <= 0.0 ? 1 : 2);
   const double bm = km == 0 ? b1 : (km == 1 ? b2 : 0.0);
-  const double ib = 1.0 / (bp - bm);
+  const double ib = frcp(bp - bm);
   const double bpm = bp * bm;
   const double ml = L.r * ul, mr = R.r * ur;
   const double el = L.r * L.h - L.p, er = R.r * R.h - R.p;
@@ -292,7 +292,7 @@ PKH_HD void hlle_rev(const FState& L, const FState& R, double gm1, const double 
     gL[6] -= gbm;
   }
   // ab = sqrt(gm1 q)
-  const double gq = gab * gm1 * 0.5 / ab;
+  const double gq = gab * gm1 * 0.5 * frcp(ab);
   const double ghb = gq;
   double gvb[3];
   for (int c = 0; c < 3; ++c) gvb[c] = -gq * vb[c];
@@ -315,7 +315,7 @@ PKH_HD void hlle_rev(const FState& L, const FState& R, double gm1, const double 
 // Adjoint of the primitive recovery: gw (adjoint of rho, v, P) -> gu
 // (adjoint of rho, M, E) at the conserved state u.
 PKH_HD void prim_rev(const double u[NVAR], double gam, const double gw[NVAR], double gu[NVAR]) {
-  const double ir = 1.0 / u[0];
+  const double ir = frcp(u[0]);
   const double v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
   const double g1 = (gam - 1.0) * gw[4];
   gu[0] = gw[0] - (gw[1] * v0 + gw[2] * v1 + gw[3] * v2) * ir + g1 * 0.5 * (v0 * v0 + v1 * v1 + v2 * v2);

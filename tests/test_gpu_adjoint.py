@@ -33,10 +33,11 @@ def _gpu_grad(mesh, U0, tgt, cycles, ckpt, dV):
     return float(loss), U.grad.detach().cpu().numpy(), UN.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("recon1,ckpt", [(0, 2), (0, 5), (1, 3)])
-def test_gradient_matches_reference(recon1, ckpt):
-    print_case(f"adjoint vs reference recon1={recon1} ckpt={ckpt}")
-    N, blk, cycles = 16, 8, 5
+@pytest.mark.parametrize("recon1,ckpt,N,blk", [(0, 2, 16, 8), (0, 5, 16, 8), (1, 3, 16, 8),
+                                               (0, 2, 32, 16), (1, 2, 32, 32), (0, 3, 64, 32)])
+def test_gradient_matches_reference(recon1, ckpt, N, blk):
+    print_case(f"adjoint vs reference recon1={recon1} ckpt={ckpt} N={N} blk={blk}")
+    cycles = 5
     mesh, lv, n, nrb, U0, tgt = _setup(N, blk, stage1_recon=recon1, amp=3e-2)
     # a flow with velocities and pressure variations exercises every branch
     U0 = U0 + 0.05 * inputs.turbulent_box(lv, n, nrb, seed=9) - 0.05 * inputs.uniform_state(lv, n)
