@@ -21,7 +21,17 @@ sys.path.insert(0, ROOT)
 METRIC = "zone-cycles/s & %HBM peak (256^3 FP64 hydro); adjoint/forward cost ratio"
 HBM_PEAK_GBS = 8000.0
 N = 256
-KERNEL_SRC = os.path.join(ROOT, "paper_2202_12309_amd", "csrc", "pkh_kernels.hip")
+# sources of the stage kernels: the committed traffic counters are used only
+# while these are unchanged
+STAGE_SRCS = [os.path.join(ROOT, "paper_2202_12309_amd", "csrc", f)
+              for f in ("pkh_stage.hip", "pkh_device.h", "pkh_physics.h")]
+
+
+def stage_source_sha():
+    h = hashlib.sha256()
+    for f in STAGE_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def algorithmic_bytes(n):
@@ -51,7 +61,7 @@ def traffic_from_profile(kernel_sha):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(blk, cycles=2):
+def cpu_baseline(blk, cycles=16):
     """The oracle, as it stands, on the same 256^3 workload for a bounded
     number of cycles on this host's cores."""
     from oracle import oracle as orc
@@ -196,36 +206,9 @@ def amr_leg(cycles=200, regrid_every=10):
             "leaves_start": leaves0, "leaves_after_each_regrid": counts, "sim_time": t}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--block", type=int, default=32, choices=[16, 32, 64])
-    ap.add_argument("--graph", action="store_true", help="replay captured cycles")
-    ap.add_argument("--tile-rows", type=int, default=0, help="stage-kernel tile rows (0: default)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-amr", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a 1 GiB device copy (the HBM-counter calibration kernel)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def main_leg(args):
+    """The 256^3 hydro cycle: zone-cycles/s, stage-kernel times and the
+    corrector's roofline."""
     import torch
     from paper_2202_12309_amd import inputs
     from paper_2202_12309_amd.binding import Mesh
@@ -263,7 +246,7 @@ def main():
     roof = None
     if corr_ms:
         ach = b_corr * cells / (corr_ms / 1e3) / 1e9
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        sha = stage_source_sha()
         roof = {"bound": "hbm", "kernel": "stage_kernel<PLM> (corrector)",
                 "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
@@ -292,12 +275,55 @@ def main():
         "bytes_per_zone_cycle": round(b_cycle, 2),
         "kernel_avg_ms": {k: (round(v, 4) if v else None) for k, v in avg.items()},
         "sim_time": t,
-        "adjoint_forward_ratio": None,
-        "adjoint": None,
-        "batch": None,
-        "amr": None,
         "roofline": roof,
     }
+    del mesh
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--block", type=int, default=32, choices=[16, 32, 64])
+    ap.add_argument("--graph", action="store_true", help="replay captured cycles")
+    ap.add_argument("--tile-rows", type=int, default=0, help="stage-kernel tile rows (0: default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-main", action="store_true",
+                    help="skip the 256^3 leg (for profiling the other legs alone)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (the HBM-counter calibration kernel)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
+              "described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    blk = args.block
+    if args.no_main:
+        out = {"metric": METRIC, "value": None, "unit": "zone-cycles/s", "n_gpus": 1, "steps": 0,
+               "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": "main 256^3 leg skipped"}, "roofline": None}
+    else:
+        out = main_leg(args)
+    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None})
     if not args.no_adjoint:
         adj = adjoint_ratio()
         out["adjoint"] = adj
@@ -305,11 +331,9 @@ def main():
     if not args.no_amr:
         out["amr"] = amr_leg()
     if not args.no_batch:
-        del mesh
         torch.cuda.empty_cache()
         out["batch"] = batch_leg()
     if not args.no_cpu_baseline:
-        mesh = None
         out["cpu_baseline"] = cpu_baseline(blk)
     print(json.dumps(out))
 

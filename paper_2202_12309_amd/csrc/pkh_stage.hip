@@ -1,0 +1,485 @@
+// pkh_stage.hip -- the stage kernel of the Euler cycle for gfx950.
+//
+// Method (Parthenon, arXiv:2202.12309, Sec. 4.1): one stage of the two-stage
+// second-order finite-volume update, U_out = U_base - beta dt D(U_in), with
+// donor-cell (predictor) or piecewise-linear MC-limited (corrector)
+// reconstruction on primitive variables and HLLE fluxes with Einfeldt's
+// Roe-averaged wave speeds, over every block of a mesh in one launch.
+//
+// Layout: every state array is [block][var][k][j][i] with ghost width 2 on
+// each side, i (x) contiguous.
+#include <math.h>
+
+#include <algorithm>
+
+#include "pkh_device.h"
+
+namespace pkh {
+
+// ---------------------------------------------------------------------------
+// Stage kernel: U_out = U_base - beta*dt * D(U_in) over every block.
+//
+// A workgroup owns TJ rows of N1 cells of one block and streams through z.
+// Each thread loads its own cell of every plane (and, with the others, the
+// 2-cell halo of the tile), keeps its column's states in a register window
+// for the z faces, and stages the plane's face-state inputs in LDS for the
+// x and y faces, each of which is solved once. The predictor (donor cell)
+// stages per-cell HLLE inputs (sqrt(rho), c, h) so no face recomputes them;
+// the corrector stages primitives and reconstructs per face (PLM-MC). A
+// cell is finished once its upper z face is known; its x/y divergence waits
+// in a short register queue. Finished cells a same-level neighbour needs as
+// ghosts are written into that neighbour's ghost zone here.
+// ---------------------------------------------------------------------------
+
+// One tile (TJ rows of block blk starting at row j0) of a stage; rot
+// rotates which wave takes the tile's remainder faces.
+template <int RECON, int N1, int TJ>
+__device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0, int rot) {
+  constexpr int NT = N1 * TJ;
+  constexpr int P1 = N1 + 2 * NG;
+  constexpr int RW = TJ + 2 * NG;
+  constexpr int PLANE = RW * P1;
+  constexpr int NHALO = PLANE - NT;
+  constexpr int NX = TJ * (N1 + 1);
+  constexpr int NY = (TJ + 1) * N1;
+  constexpr int LAG = RECON ? 1 : 0;  // z face m is computed at plane m + LAG
+  constexpr int WN = RECON ? 4 : 2;   // z window length
+  constexpr int QN = 1 + LAG;         // x/y divergence queue length
+  constexpr int UQN = RECON ? 1 : 2;  // predictor: conserved own-cell queue length
+  constexpr int NQ = RECON ? 5 : 8;   // staged values per cell
+  constexpr int NWAVE = (NT + 63) / 64;
+  constexpr bool PF = !RECON;         // prefetch the next plane into registers
+  static_assert(NT % 64 == 0, "whole waves");
+
+  __shared__ double sQ[NQ][PLANE];
+  __shared__ double sFx[NV][NX];
+  __shared__ double sFy[NV][NY];
+  __shared__ double sRed[NWAVE];
+
+  const Geom& g = a.g;
+  const int tid = threadIdx.x;
+  const int ti = tid % N1, tj = tid / N1;
+
+  const BlockInfo bi = a.blocks[blk];
+  const double gam = g.gamma;
+  const double gm1 = gam - 1.0;
+  const double igm1 = 1.0 / gm1;
+  const double coef = a.beta * a.tm->dt;
+  const int64_t vs = g.vstride;
+  const double* __restrict__ in = a.uin + (int64_t)blk * g.bstride;
+  const double* base = a.ubase + (int64_t)blk * g.bstride;
+  double* out = a.uout + (int64_t)blk * g.bstride;
+  const int n2 = g.n2, n3 = g.n3;
+  const int j = j0 + tj;
+  const int fsz = NV * max(max(g.n1 * n2, g.n1 * n3), n2 * n3);  // face slot stride
+  double* fbuf = a.fbuf;
+  const int32_t* nb27 = a.nbr ? a.nbr + (int64_t)blk * 27 : nullptr;
+  const int own = (tj + NG) * P1 + ti + NG;  // this thread's cell in the LDS plane
+
+  FState w[WN];       // z window (column states)
+  double uq[UQN][NV];  // predictor: conserved own-cell values awaiting their update
+  double dq[QN][NV];  // x/y divergence awaiting the z faces
+  double fzp[NV];
+  bool bad = false;
+  double smax = 0.0;
+  const int mask = bi.finer_mask;
+
+#pragma unroll
+  for (int s = 0; s < WN; ++s) w[s] = FState{1.0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0, 1.0};
+#pragma unroll
+  for (int s = 0; s < QN; ++s)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dq[s][v] = 0.0;
+#pragma unroll
+  for (int s = 0; s < UQN; ++s)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uq[s][v] = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) fzp[v] = 0.0;
+
+  // stage one cell's inputs into LDS slot c; returns its state
+  auto stage_cell = [&](const double u[NV], int c) {
+    FState q;
+    double wp[NV];
+    bad |= !to_prim(u, gam, wp);
+    q.r = wp[0];
+    q.v0 = wp[1];
+    q.v1 = wp[2];
+    q.v2 = wp[3];
+    q.p = wp[4];
+    sQ[0][c] = q.r;
+    sQ[1][c] = q.v0;
+    sQ[2][c] = q.v1;
+    sQ[3][c] = q.v2;
+    sQ[4][c] = q.p;
+    if constexpr (!RECON) {
+      complete_state(q, gam, igm1);
+      sQ[5][c] = q.sr;
+      sQ[6][c] = q.c;
+      sQ[7][c] = q.h;
+    }
+    return q;
+  };
+  // face states of the face between LDS cells cm (lower) and c0 (upper),
+  // stride st between neighbours along the face normal
+  auto face_states = [&](int c0, int st, FState& L, FState& R) {
+    if constexpr (RECON) {
+      double wl[NV], wr[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double qm2 = sQ[v][c0 - 2 * st], qm1 = sQ[v][c0 - st], q0 = sQ[v][c0],
+                     qp1 = sQ[v][c0 + st];
+        wl[v] = qm1 + 0.5 * mc_slope(qm1 - qm2, q0 - qm1);
+        wr[v] = q0 - 0.5 * mc_slope(q0 - qm1, qp1 - q0);
+      }
+      L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+      R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+      complete_state(L, gam, igm1);
+      complete_state(R, gam, igm1);
+    } else {
+      const int cm = c0 - st;
+      L = FState{sQ[0][cm], sQ[1][cm], sQ[2][cm], sQ[3][cm], sQ[4][cm], sQ[5][cm], sQ[6][cm], sQ[7][cm]};
+      R = FState{sQ[0][c0], sQ[1][c0], sQ[2][c0], sQ[3][c0], sQ[4][c0], sQ[5][c0], sQ[6][c0], sQ[7][c0]};
+    }
+  };
+
+  // halo cell h of the plane (rows -2,-1 and TJ,TJ+1 of the tile, then the
+  // two cells at each end of the interior rows) -> its LDS slot
+  auto hcell = [&](int h) {
+    if (h < 2 * P1) return h;
+    if (h < 4 * P1) return (TJ + NG) * P1 + (h - 2 * P1);
+    const int hh = h - 4 * P1, r = hh >> 2, s4 = hh & 3;
+    return (r + NG) * P1 + (s4 < 2 ? s4 : P1 - 4 + s4);
+  };
+  constexpr int HMAX = PF ? (NHALO + NT - 1) / NT : 1;
+  double pu[NV], ph[HMAX][NV];  // prefetched own and halo cells of the next plane
+  if constexpr (PF) {
+    const double* pl = in + ((int64_t)(-1 - LAG + NG) * g.p2 + j0) * P1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) pu[v] = pl[v * vs + own];
+#pragma unroll
+    for (int hh = 0; hh < HMAX; ++hh) {
+      const int h = tid + hh * NT;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ph[hh][v] = h < NHALO ? pl[v * vs + hcell(h)] : 1.0;
+    }
+  }
+
+  for (int p = -1 - LAG; p < n3 + 1 + LAG; ++p) {
+    // --- stage plane p (rows j0-2 .. j0+TJ+1): own cell first, then halo.
+    // The predictor takes plane p from registers loaded while plane p-1 was
+    // being computed and starts the loads of plane p+1 right away.
+    {
+      double u[NV];
+      if constexpr (PF) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = pu[v];
+      } else {
+        const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + own];
+      }
+      const FState q = stage_cell(u, own);
+#pragma unroll
+      for (int s = 0; s < WN - 1; ++s) w[s] = w[s + 1];
+      w[WN - 1] = q;
+      if constexpr (!RECON) {
+#pragma unroll
+        for (int s = 0; s < UQN - 1; ++s)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) uq[s][v] = uq[s + 1][v];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uq[UQN - 1][v] = u[v];
+      }
+    }
+    if constexpr (PF) {
+#pragma unroll
+      for (int hh = 0; hh < HMAX; ++hh) {
+        const int h = tid + hh * NT;
+        if (h < NHALO) stage_cell(ph[hh], hcell(h));
+      }
+      if (p + 1 < n3 + 1 + LAG) {
+        const double* pn = in + ((int64_t)(p + 1 + NG) * g.p2 + j0) * P1;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pu[v] = pn[v * vs + own];
+#pragma unroll
+        for (int hh = 0; hh < HMAX; ++hh) {
+          const int h = tid + hh * NT;
+          if (h < NHALO) {
+            const int c = hcell(h);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ph[hh][v] = pn[v * vs + c];
+          }
+        }
+      }
+    } else {
+      const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
+      for (int h = tid; h < NHALO; h += NT) {
+        double u[NV];
+        const int c = hcell(h);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + c];
+        stage_cell(u, c);
+      }
+    }
+    __syncthreads();
+
+    // --- z face m between cells m-1 and m, then finish cell m-1
+    const int m = p - LAG;
+    if (m >= 0 && m <= n3) {
+      FState L, R;
+      double fz[NV];
+      if constexpr (RECON) {
+        const double c0[NV] = {w[0].r, w[0].v0, w[0].v1, w[0].v2, w[0].p};
+        const double c1[NV] = {w[1].r, w[1].v0, w[1].v1, w[1].v2, w[1].p};
+        const double c2[NV] = {w[2].r, w[2].v0, w[2].v1, w[2].v2, w[2].p};
+        const double c3[NV] = {w[3].r, w[3].v0, w[3].v1, w[3].v2, w[3].p};
+        double wl[NV], wr[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          wl[v] = c1[v] + 0.5 * mc_slope(c1[v] - c0[v], c2[v] - c1[v]);
+          wr[v] = c2[v] - 0.5 * mc_slope(c2[v] - c1[v], c3[v] - c2[v]);
+        }
+        L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+        R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+        complete_state(L, gam, igm1);
+        complete_state(R, gam, igm1);
+      } else {
+        L = w[0];
+        R = w[1];
+      }
+      hlle<2>(L, R, gm1, fz);
+      if (m == 0 && bi.fslot[ZLO] >= 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          fbuf[(int64_t)bi.fslot[ZLO] * fsz + ((int64_t)v * n2 + j) * N1 + ti] = fz[v];
+      }
+      if (m == n3 && bi.fslot[ZHI] >= 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          fbuf[(int64_t)bi.fslot[ZHI] * fsz + ((int64_t)v * n2 + j) * N1 + ti] = fz[v];
+      }
+      if (m >= 1) {
+        const int k = m - 1;
+        const int64_t o = ((int64_t)(k + NG) * g.p2 + (j + NG)) * P1 + ti + NG;
+        double un[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double du = dq[0][v] + (fz[v] - fzp[v]) * bi.idx[2];
+          const double ub = RECON ? base[v * vs + o] : uq[0][v];
+          un[v] = ub - coef * du;
+          out[v * vs + o] = un[v];
+        }
+        if (nb27) push_ghosts(a.uout, nb27, g, ti, j, k, un);
+        if (a.do_dt) {
+          const bool skip = ((mask >> XLO) & 1 && ti == 0) || ((mask >> XHI) & 1 && ti == N1 - 1) ||
+                            ((mask >> YLO) & 1 && j == 0) || ((mask >> YHI) & 1 && j == n2 - 1) ||
+                            ((mask >> ZLO) & 1 && k == 0) || ((mask >> ZHI) & 1 && k == n3 - 1);
+          if (!skip) {
+            double wn[NV];
+            bad |= !to_prim(un, gam, wn);
+            const double cs = fsqrt(gam * wn[4] * frcp(wn[0]));
+            const double sv = fmax(fmax((fabs(wn[1]) + cs) * bi.idx[0], (fabs(wn[2]) + cs) * bi.idx[1]),
+                                   (fabs(wn[3]) + cs) * bi.idx[2]);
+            smax = fmax(smax, sv);
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fzp[v] = fz[v];
+    }
+    // --- x and y faces of plane p, divergence into the queue. Each thread
+    // solves the lower x and y faces of its cell; the tile's upper x faces
+    // (one per row) and upper y faces (one per column) are spread over the
+    // first lanes of every wave so that all waves do the same number of
+    // solves between barriers.
+    if (p >= 0 && p < n3) {
+      // remainder jobs (the tile's upper x and y faces) go to consecutive
+      // threads starting at one wave, rotated with the plane and the
+      // workgroup so that no SIMD always gets the extra work
+      const int wr = (rot + p + 2) % NWAVE;
+      const int q = (tid - wr * 64 + NT) % NT;
+#pragma unroll 1
+      for (int slot = 0; slot < 3; ++slot) {
+        // slot 0: lower x face of the own cell; 1: lower y face; 2: upper x
+        // face of row q (q < TJ) or upper y face of column q - TJ
+        if (slot == 2 && q >= TJ + N1) break;
+        const int dir = slot == 0 ? 0 : (slot == 1 ? 1 : (q < TJ ? 0 : 1));
+        const int iy = q - TJ;
+        const int c0 = slot < 2 ? own : (dir == 0 ? (q + NG) * P1 + N1 + NG : (TJ + NG) * P1 + iy + NG);
+        FState L, R;
+        double fl[NV];
+        face_states(c0, dir == 0 ? 1 : P1, L, R);
+        hlle<-1>(L, R, gm1, fl, dir);
+        const int fo = slot < 2 ? (dir == 0 ? tj * (N1 + 1) + ti : tj * N1 + ti)
+                                : (dir == 0 ? q * (N1 + 1) + N1 : TJ * N1 + iy);
+        double* dstf = dir == 0 ? &sFx[0][fo] : &sFy[0][fo];
+        const int vstr = dir == 0 ? NX : NY;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dstf[v * vstr] = fl[v];
+        // fine-coarse faces: keep this leaf's flux for the correction
+        int fsl = -1;
+        int64_t o = 0, vst = 0;
+        if (dir == 0) {
+          const bool lo = slot == 0 && ti == 0, hi = slot == 2;
+          fsl = lo ? bi.fslot[XLO] : (hi ? bi.fslot[XHI] : -1);
+          o = (int64_t)p * n2 + (slot == 0 ? j : j0 + q);
+          vst = (int64_t)n3 * n2;
+        } else {
+          const bool lo = slot == 1 && j == 0, hi = slot == 2 && j0 + TJ == n2;
+          fsl = lo ? bi.fslot[YLO] : (hi ? bi.fslot[YHI] : -1);
+          o = (int64_t)p * N1 + (slot == 1 ? ti : iy);
+          vst = (int64_t)n3 * N1;
+        }
+        if (fsl >= 0) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) fbuf[(int64_t)fsl * fsz + v * vst + o] = fl[v];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < QN - 1; ++s)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        dq[QN - 1][v] = (sFx[v][tj * (N1 + 1) + ti + 1] - sFx[v][tj * (N1 + 1) + ti]) * bi.idx[0] +
+                        (sFy[v][(tj + 1) * N1 + ti] - sFy[v][tj * N1 + ti]) * bi.idx[1];
+    } else {
+      // keep the queue aligned with plane numbers on the leading planes
+#pragma unroll
+      for (int s = 0; s < QN - 1; ++s)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
+    }
+
+    __syncthreads();
+  }
+
+  if (a.do_dt) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off));
+    if ((tid & 63) == 0) sRed[tid >> 6] = smax;
+    __syncthreads();
+    if (tid == 0) {
+      double mx = sRed[0];
+      for (int q = 1; q < NWAVE; ++q) mx = fmax(mx, sRed[q]);
+      atomicMax(&a.tm->smax_bits, (unsigned long long)__double_as_longlong(mx));
+    }
+  }
+  if (bad) atomicOr(&a.tm->err, 1);
+}
+
+// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; map
+// consecutive items (tiles of a block, which share halo rows) to one XCD's L2.
+__device__ __forceinline__ int xcd_order(int wg, int nwg) {
+  return (nwg & 7) == 0 ? (wg & 7) * (nwg >> 3) + (wg >> 3) : wg;
+}
+
+// Occupancy: the corrector is held to 168 VGPRs (three waves per SIMD); the
+// predictor keeps the next plane's loads in flight in registers and runs
+// at two waves per SIMD.
+template <int RECON, int N1, int TJ>
+__global__ void __launch_bounds__(N1 * TJ, RECON ? 3 : 2) stage_kernel(StageLaunch a) {
+  const int ntj = a.g.n2 / TJ;
+  const int wg = xcd_order(blockIdx.x, gridDim.x);
+  const int blk = wg / ntj;
+  if (blk >= a.nblocks) return;
+  stage_tile<RECON, N1, TJ>(a, blk, (wg - blk * ntj) * TJ, wg);
+}
+
+// Grouped launch: the tiles of many independent meshes (same block width
+// and tile) in one grid; items[w] names the mesh, block and first row.
+template <int RECON, int N1, int TJ>
+__global__ void __launch_bounds__(N1 * TJ, RECON ? 3 : 2) stage_group_kernel(const StageLaunch* insts,
+                                                                 const GroupItem* items, int nitems) {
+  const int wg = xcd_order(blockIdx.x, gridDim.x);
+  if (wg >= nitems) return;
+  const GroupItem it = items[wg];
+  stage_tile<RECON, N1, TJ>(insts[it.inst], it.blk, it.j0, wg);
+}
+
+template <int RECON, int N1, int TJ>
+static hipError_t launch_group_t(const StageLaunch* insts, const GroupItem* items, int nitems,
+                                 hipStream_t s) {
+  const int nwg = (nitems + 7) / 8 * 8;
+  hipLaunchKernelGGL((stage_group_kernel<RECON, N1, TJ>), dim3((unsigned)nwg), dim3(N1 * TJ), 0, s, insts,
+                     items, nitems);
+  return hipGetLastError();
+}
+
+template <int RECON, int N1, int TJ>
+static hipError_t launch_stage_t(const StageLaunch& a, hipStream_t s) {
+  const int ntj = a.g.n2 / TJ;
+  int64_t nwg = (int64_t)a.nblocks * ntj;
+  nwg = (nwg + 7) / 8 * 8;
+  hipLaunchKernelGGL((stage_kernel<RECON, N1, TJ>), dim3((unsigned)nwg), dim3(N1 * TJ), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int N1, int TJ>
+static hipError_t launch_stage_n(const StageLaunch& a, hipStream_t s) {
+  return a.recon ? launch_stage_t<1, N1, TJ>(a, s) : launch_stage_t<0, N1, TJ>(a, s);
+}
+
+int stage_tile_rows(int n1, int n2, int tj) {
+  // compiled (N1, TJ) variants; the first is the default
+  static const int opts[4][3] = {{8, 8, 0}, {8, 16, 4}, {8, 4, 16}, {4, 2, 0}};
+  const int row = n1 == 8 ? 0 : n1 == 16 ? 1 : n1 == 32 ? 2 : n1 == 64 ? 3 : -1;
+  if (row < 0) return -1;
+  if (tj == 0) tj = opts[row][0];
+  for (int q = 0; q < 3; ++q)
+    if (opts[row][q] == tj && tj > 0 && n2 % tj == 0) return tj;
+  return -1;
+}
+
+hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
+                              const GroupItem* items, int nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+#define PKH_G(N1_, TJ_)                                                                 \
+  case N1_ * 100 + TJ_:                                                                 \
+    return recon ? launch_group_t<1, N1_, TJ_>(insts, items, nitems, s)                 \
+                 : launch_group_t<0, N1_, TJ_>(insts, items, nitems, s);
+  switch (n1 * 100 + tj) {
+    PKH_G(8, 8)
+    PKH_G(16, 8)
+    PKH_G(16, 16)
+    PKH_G(16, 4)
+    PKH_G(32, 8)
+    PKH_G(32, 4)
+    PKH_G(32, 16)
+    PKH_G(64, 4)
+    PKH_G(64, 2)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PKH_G
+}
+
+hipError_t launch_stage(const StageLaunch& a, hipStream_t s) {
+  const int tj = stage_tile_rows(a.g.n1, a.g.n2, a.tj);
+  switch (a.g.n1 * 100 + tj) {
+    case 808:
+      return launch_stage_n<8, 8>(a, s);
+    case 1608:
+      return launch_stage_n<16, 8>(a, s);
+    case 1616:
+      return launch_stage_n<16, 16>(a, s);
+    case 1604:
+      return launch_stage_n<16, 4>(a, s);
+    case 3208:
+      return launch_stage_n<32, 8>(a, s);
+    case 3204:
+      return launch_stage_n<32, 4>(a, s);
+    case 3216:
+      return launch_stage_n<32, 16>(a, s);
+    case 6404:
+      return launch_stage_n<64, 4>(a, s);
+    case 6402:
+      return launch_stage_n<64, 2>(a, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pkh
