@@ -95,8 +95,9 @@ struct GroupItem {
 hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
                               const GroupItem* items, int nitems, hipStream_t s);
 // Rows per workgroup tile actually used for a block of n1 x n2 cells and a
-// requested value (0: default); -1 if no compiled variant fits.
-int stage_tile_rows(int n1, int n2, int tj);
+// requested value (0: default, which for n1 = 32 depends on the blocks of the
+// launch, nblocks; 0 there means many); -1 if no compiled variant fits.
+int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0);
 // skip_same: leave ghost cells whose source is a same-level leaf alone
 // (the stage kernels already wrote them).
 hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,

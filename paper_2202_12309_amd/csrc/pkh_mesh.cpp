@@ -912,7 +912,7 @@ int pkh_set_tuning(pkh_mesh* m, const pkh_tuning* t) {
 int pkh_get_tuning(const pkh_mesh* m, pkh_tuning* t) {
   if (!m || !t) return fail(PKH_EINVAL, "null argument");
   *t = pkh_tuning{};
-  t->tile_rows = stage_tile_rows(m->g.n1, m->g.n2, m->tj);
+  t->tile_rows = stage_tile_rows(m->g.n1, m->g.n2, m->tj, m->nb());
   return PKH_OK;
 }
 
@@ -1326,7 +1326,7 @@ int pkh_batch_create(pkh_mesh* const* meshes, int32_t n, pkh_batch** out) {
     corr[q] = s;
     tms[q] = m->d_time;
     // group by block width and stage-1 reconstruction
-    const int tj = stage_tile_rows(m->g.n1, m->g.n2, m->tj);
+    const int tj = stage_tile_rows(m->g.n1, m->g.n2, m->tj, m->nb());
     bool placed = false;
     for (auto& gr : b->groups) {
       pkh_mesh* r = b->meshes[gr.members[0]];
@@ -1435,7 +1435,7 @@ int pkh_autotune(pkh_mesh* m, int32_t trial_cycles, pkh_tuning* out) {
   HIPCHK(hipEventCreate(&e1));
   const uint32_t flags = m->cfg.flags;
   m->cfg.flags &= ~PKH_FLAG_GRAPH;
-  int best = stage_tile_rows(m->g.n1, m->g.n2, m->tj);
+  int best = stage_tile_rows(m->g.n1, m->g.n2, m->tj, m->nb());
   float best_ms = 1e30f;
   for (int tj : kTileChoices) {
     if (stage_tile_rows(m->g.n1, m->g.n2, tj) != tj) continue;
