@@ -460,7 +460,7 @@ __device__ double pressure_nc(const double* c, int64_t vs, double gm1) {
   return gm1 * (e - ke);
 }
 
-__global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, Geom g) {
+__global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, const int32_t* nbr, Geom g) {
 #pragma clang fp contract(off)
   __shared__ double sRed[4];
   const int b = blockIdx.x;
@@ -473,8 +473,11 @@ __global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, 
     const double* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double pp = pressure_nc(cell + st[d], g.vstride, gm1);
-      const double pm = pressure_nc(cell - st[d], g.vstride, gm1);
+      // x neighbours beyond the block: the x neighbour's active cells
+      const double* cp = d == 0 && i == g.n1 - 1 ? u + xrow_cell(g, nbr, b, j, k, i + 1) : cell + st[d];
+      const double* cm = d == 0 && i == 0 ? u + xrow_cell(g, nbr, b, j, k, -1) : cell - st[d];
+      const double pp = pressure_nc(cp, g.vstride, gm1);
+      const double pm = pressure_nc(cm, g.vstride, gm1);
       mx = fmax(mx, fabs(pp - pm) / (pp + pm));
     }
   }
@@ -485,8 +488,9 @@ __global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, 
   if (threadIdx.x == 0) eta[b] = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
 }
 
-hipError_t launch_eta(double* eta, const double* u, int32_t nblocks, const Geom& g, hipStream_t s) {
-  hipLaunchKernelGGL(eta_kernel, dim3(nblocks), dim3(256), 0, s, eta, u, g);
+hipError_t launch_eta(double* eta, const double* u, const int32_t* nbr, int32_t nblocks, const Geom& g,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(eta_kernel, dim3(nblocks), dim3(256), 0, s, eta, u, nbr, g);
   return hipGetLastError();
 }
 
@@ -759,7 +763,8 @@ template <int RECON>
 __global__ void __launch_bounds__(256) adj_xlast_kernel(const double* __restrict__ U,
                                                         const double* __restrict__ lam,
                                                         double* __restrict__ xl, const BlockInfo* blocks,
-                                                        int nblocks, Geom g, const double* dtp, double beta) {
+                                                        const int32_t* __restrict__ nbr, int nblocks, Geom g,
+                                                        const double* dtp, double beta) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t rpb = (int64_t)g.n2 * g.n3;
   const int64_t nrows = rpb * nblocks;
@@ -774,9 +779,10 @@ __global__ void __launch_bounds__(256) adj_xlast_kernel(const double* __restrict
   const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
   const int64_t abase = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
   auto loadw = [&](int s, double w[NV]) {
+    const int64_t at = s < nd ? pbase + s : xrow_cell(g, nbr, b, j, k, s);
     double u[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = U[pbase + (int64_t)v * g.vstride + s];
+    for (int v = 0; v < NV; ++v) u[v] = U[at + (int64_t)v * g.vstride];
     to_prim(u, gam, w);
   };
   double mu[NV];
@@ -850,7 +856,8 @@ __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict_
                                                        const double* __restrict__ lam,
                                                        double* __restrict__ wbar,
                                                        const double* __restrict__ xl,
-                                                       const BlockInfo* blocks, int nblocks, Geom g,
+                                                       const BlockInfo* blocks,
+                                                       const int32_t* __restrict__ nbr, int nblocks, Geom g,
                                                        const double* dtp, double beta) {
   static_assert(N1 == 8 || N1 == 16 || N1 == 32 || N1 == 64, "row width");
   const int i = (int)(threadIdx.x % N1);
@@ -868,9 +875,10 @@ __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict_
   const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
   const int64_t abase = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
   auto loadw = [&](int s, double w[NV]) {
+    const int64_t at = (s >= 0 && s < N1) ? pbase + s : xrow_cell(g, nbr, b, j, k, s);
     double u[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = U[pbase + (int64_t)v * g.vstride + s];
+    for (int v = 0; v < NV; ++v) u[v] = U[at + (int64_t)v * g.vstride];
     to_prim(u, gam, w);
   };
   auto emit = [&](int s, const double a[NV]) {
@@ -1083,24 +1091,24 @@ __global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restr
 
 template <int RECON>
 static void launch_xrow(int n1, dim3 grid, hipStream_t s, const double* U, const double* lam, double* wx,
-                        const double* xl, const BlockInfo* blocks, int nblocks, const Geom& g,
-                        const double* dtp, double beta) {
+                        const double* xl, const BlockInfo* blocks, const int32_t* nbr, int nblocks,
+                        const Geom& g, const double* dtp, double beta) {
   switch (n1) {
     case 8:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 8>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nblocks, g, dtp,
-                         beta);
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 8>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nbr, nblocks, g,
+                         dtp, beta);
       break;
     case 16:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 16>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nblocks, g, dtp,
-                         beta);
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 16>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nbr, nblocks, g,
+                         dtp, beta);
       break;
     case 32:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 32>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nblocks, g, dtp,
-                         beta);
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 32>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nbr, nblocks, g,
+                         dtp, beta);
       break;
     default:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 64>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nblocks, g, dtp,
-                         beta);
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 64>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nbr, nblocks, g,
+                         dtp, beta);
   }
 }
 
@@ -1113,20 +1121,26 @@ hipError_t launch_adj_stage(int recon, const double* U, const double* lam, doubl
   const int64_t npen = (int64_t)nblocks * std::max(std::max((int64_t)g.n2 * g.n3, (int64_t)g.n1 * g.n3),
                                                    (int64_t)g.n1 * g.n2);
   const int64_t wstride = (int64_t)nblocks * g.bstride;
-  // x: last face of every row, then the rows face-parallel; y and z: pencils
+  // x: last face of every row, then the rows face-parallel; y and z: pencils.
+  // The x ghost cells of the stage kernels' outputs are not kept (the x
+  // kernels read the neighbours' active cells), so the row path is the only
+  // x path.
   const bool rows = adj_xrow_supported(g.n1) && xlast != nullptr;
-  if (rows) {
+  if (!rows) return hipErrorInvalidValue;
+  {
     const int64_t nrows = (int64_t)nblocks * g.n2 * g.n3;
     const dim3 gl((unsigned)((nrows + 255) / 256)), gr((unsigned)((nrows * g.n1 + 255) / 256));
     if (recon) {
-      hipLaunchKernelGGL(adj_xlast_kernel<1>, gl, dim3(256), 0, s, U, lam, xlast, blocks, nblocks, g, dtp, beta);
-      launch_xrow<1>(g.n1, gr, s, U, lam, wbar3, xlast, blocks, nblocks, g, dtp, beta);
+      hipLaunchKernelGGL(adj_xlast_kernel<1>, gl, dim3(256), 0, s, U, lam, xlast, blocks, nbr, nblocks, g, dtp,
+                         beta);
+      launch_xrow<1>(g.n1, gr, s, U, lam, wbar3, xlast, blocks, nbr, nblocks, g, dtp, beta);
     } else {
-      hipLaunchKernelGGL(adj_xlast_kernel<0>, gl, dim3(256), 0, s, U, lam, xlast, blocks, nblocks, g, dtp, beta);
-      launch_xrow<0>(g.n1, gr, s, U, lam, wbar3, xlast, blocks, nblocks, g, dtp, beta);
+      hipLaunchKernelGGL(adj_xlast_kernel<0>, gl, dim3(256), 0, s, U, lam, xlast, blocks, nbr, nblocks, g, dtp,
+                         beta);
+      launch_xrow<0>(g.n1, gr, s, U, lam, wbar3, xlast, blocks, nbr, nblocks, g, dtp, beta);
     }
   }
-  const int dir0 = rows ? 1 : 0;
+  const int dir0 = 1;
   dim3 grid((unsigned)((npen + 255) / 256), 3 - dir0);
   if (recon)
     hipLaunchKernelGGL(adj_pencils_kernel<1>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nblocks, g,

@@ -741,7 +741,7 @@ int pkh_flag_pressure_jump(pkh_mesh* m, double refine_above, double derefine_bel
   if ((rc = ensure_partials(m))) return rc;
   const int64_t nb = m->nb();
   std::vector<double> eta(nb);
-  HIPCHK(launch_eta(m->d_partial, m->A, (int32_t)nb, m->g, m->stream));
+  HIPCHK(launch_eta(m->d_partial, m->A, m->d_nbr, (int32_t)nb, m->g, m->stream));
   HIPCHK(hipMemcpyAsync(eta.data(), m->d_partial, nb * sizeof(double), hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
   if ((rc = check_err(m))) return rc;

@@ -30,6 +30,13 @@
 #ifndef PKH_PRED_WAVES
 #define PKH_PRED_WAVES 2
 #endif
+// planes of inputs kept in flight ahead of the one being computed
+#ifndef PKH_CORR_PFD
+#define PKH_CORR_PFD 1
+#endif
+#ifndef PKH_PRED_PFD
+#define PKH_PRED_PFD 1
+#endif
 
 namespace pkh {
 
@@ -56,7 +63,9 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   constexpr int P1 = N1 + 2 * NG;
   constexpr int RW = TJ + 2 * NG;
   constexpr int PLANE = RW * P1;
-  constexpr int NHALO = PLANE - NT;
+  // halo cells the faces read: rows -2, -1, TJ, TJ+1 over the active
+  // columns, and the two cells beyond each end of the interior rows
+  constexpr int NHALO = 4 * N1 + 4 * TJ;
   constexpr int NX = TJ * (N1 + 1);
   constexpr int NY = (TJ + 1) * N1;
   constexpr int LAG = RECON ? 1 : 0;  // z face m is computed at plane m + LAG
@@ -67,6 +76,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   constexpr int NWAVE = (NT + 63) / 64;
   constexpr bool PF = !RECON || PKH_CORR_PF;  // prefetch the next plane into registers
   constexpr bool BPF = RECON && PKH_CORR_BPF; // corrector: U^n of the next update one plane ahead
+  constexpr int PFD = PF ? (RECON ? PKH_CORR_PFD : PKH_PRED_PFD) : 1;  // planes in flight
   static_assert(NT % 64 == 0, "whole waves");
 
   __shared__ double sQ[NQ][PLANE];
@@ -92,6 +102,14 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   const int fsz = NV * max(max(g.n1 * n2, g.n1 * n3), n2 * n3);  // face slot stride
   double* fbuf = a.fbuf;
   const int32_t* nb27 = a.nbr ? a.nbr + (int64_t)blk * 27 : nullptr;
+  // x halo of interior rows: read from the active cells of same-level x
+  // neighbours (their last / first two columns) rather than from this
+  // block's ghost zone, which the stage kernels do not keep for x; a
+  // neighbour on another level (or no table) leaves it to the ghost zone
+  const int32_t nbxl = nb27 ? nb27[12] : -1, nbxr = nb27 ? nb27[14] : -1;
+  // offsets from this block's base to the x neighbours' matching cells
+  const int64_t dxl = nbxl >= 0 ? (int64_t)(nbxl - blk) * g.bstride + N1 : 0;
+  const int64_t dxr = nbxr >= 0 ? (int64_t)(nbxr - blk) * g.bstride - N1 : 0;
   const int own = (tj + NG) * P1 + ti + NG;  // this thread's cell in the LDS plane
 
   FState w[WN];       // z window (column states)
@@ -161,35 +179,62 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     }
   };
 
-  // halo cell h of the plane (rows -2,-1 and TJ,TJ+1 of the tile, then the
-  // two cells at each end of the interior rows) -> its LDS slot
+  // halo cell h of the plane (rows -2,-1 and TJ,TJ+1 of the tile over the
+  // active columns, then the two cells at each end of the interior rows) ->
+  // its LDS slot
   auto hcell = [&](int h) {
-    if (h < 2 * P1) return h;
-    if (h < 4 * P1) return (TJ + NG) * P1 + (h - 2 * P1);
-    const int hh = h - 4 * P1, r = hh >> 2, s4 = hh & 3;
+    if (h < 4 * N1) {
+      const int r = h / N1, i = h - r * N1;
+      return (r < 2 ? r : TJ + r) * P1 + NG + i;
+    }
+    const int hh = h - 4 * N1, r = hh >> 2, s4 = hh & 3;
     return (r + NG) * P1 + (s4 < 2 ? s4 : P1 - 4 + s4);
   };
+  // offset from this block's cell to the one halo cell h is read from
+  // (x-halo cells: the x neighbour's)
+  auto hshift = [&](int h) -> int64_t {
+    if (h < 4 * N1) return 0;
+    return ((h - 4 * N1) & 3) < 2 ? dxl : dxr;
+  };
   constexpr int HMAX = PF ? (NHALO + NT - 1) / NT : 1;
-  double pu[NV], ph[HMAX][NV];  // prefetched own and halo cells of the next plane
-  double ubn[NV];               // corrector: prefetched U^n of the next cell to update
+  // ring of PFD planes in flight: plane p is staged from slot (p - p_first)
+  // % PFD, which then receives plane p + PFD; the loop below is unrolled by
+  // PFD so every slot index is a compile-time constant
+  double pu[PFD][NV], ph[PFD][HMAX][NV];  // own and halo cells of planes ahead
+  double ubn[PFD][NV];                    // corrector: U^n of the next updates
+  const int p_first = -1 - LAG, p_end = n3 + 1 + LAG;
   if constexpr (BPF) {
-    const int64_t o0 = ((int64_t)NG * g.p2 + (j + NG)) * P1 + ti + NG;
+    // the update of cell c happens at plane p_first + 2 + 2 LAG + c
 #pragma unroll
-    for (int v = 0; v < NV; ++v) ubn[v] = base[v * vs + o0];
+    for (int c = 0; c < PFD; ++c) {
+      const int64_t oc = ((int64_t)(c + NG) * g.p2 + (j + NG)) * P1 + ti + NG;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ubn[(2 + 2 * LAG + c) % PFD][v] = base[v * vs + oc];
+    }
   }
   if constexpr (PF) {
-    const double* pl = in + ((int64_t)(-1 - LAG + NG) * g.p2 + j0) * P1;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) pu[v] = pl[v * vs + own];
+    for (int sl = 0; sl < PFD; ++sl) {
+      const double* pl = in + ((int64_t)(p_first + sl + NG) * g.p2 + j0) * P1;
 #pragma unroll
-    for (int hh = 0; hh < HMAX; ++hh) {
-      const int h = tid + hh * NT;
+      for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own];
+      // the halo is only read on the active planes
+      const bool act = p_first + sl >= 0 && p_first + sl < n3;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ph[hh][v] = h < NHALO ? pl[v * vs + hcell(h)] : 1.0;
+      for (int hh = 0; hh < HMAX; ++hh) {
+        const int h = tid + hh * NT;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          ph[sl][hh][v] = (act && h < NHALO) ? pl[hshift(h) + v * vs + hcell(h)] : 1.0;
+      }
     }
   }
 
-  for (int p = -1 - LAG; p < n3 + 1 + LAG; ++p) {
+  for (int pb = p_first; pb < p_end; pb += PFD)
+#pragma unroll
+  for (int sl = 0; sl < PFD; ++sl) {
+    const int p = pb + sl;
+    if (p >= p_end) break;  // plane count not a multiple of PFD (uniform)
     // --- stage plane p (rows j0-2 .. j0+TJ+1): own cell first, then halo.
     // The predictor takes plane p from registers loaded while plane p-1 was
     // being computed and starts the loads of plane p+1 right away.
@@ -197,7 +242,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       double u[NV];
       if constexpr (PF) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = pu[v];
+        for (int v = 0; v < NV; ++v) u[v] = pu[sl][v];
       } else {
         const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
 #pragma unroll
@@ -217,32 +262,38 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       }
     }
     if constexpr (PF) {
-#pragma unroll
-      for (int hh = 0; hh < HMAX; ++hh) {
-        const int h = tid + hh * NT;
-        if (h < NHALO) stage_cell(ph[hh], hcell(h));
-      }
-      if (p + 1 < n3 + 1 + LAG) {
-        const double* pn = in + ((int64_t)(p + 1 + NG) * g.p2 + j0) * P1;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) pu[v] = pn[v * vs + own];
+      if (p >= 0 && p < n3) {
 #pragma unroll
         for (int hh = 0; hh < HMAX; ++hh) {
           const int h = tid + hh * NT;
-          if (h < NHALO) {
-            const int c = hcell(h);
+          if (h < NHALO) stage_cell(ph[sl][hh], hcell(h));
+        }
+      }
+      if (p + PFD < p_end) {
+        const int64_t po = ((int64_t)(p + PFD + NG) * g.p2 + j0) * P1;
+        const double* pn = in + po;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) ph[hh][v] = pn[v * vs + c];
+        for (int v = 0; v < NV; ++v) pu[sl][v] = pn[v * vs + own];
+        const bool act = p + PFD >= 0 && p + PFD < n3;
+#pragma unroll
+        for (int hh = 0; hh < HMAX; ++hh) {
+          const int h = tid + hh * NT;
+          if (act && h < NHALO) {
+            const int c = hcell(h);
+            const int64_t hs = hshift(h);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ph[sl][hh][v] = pn[hs + v * vs + c];
           }
         }
       }
     } else {
-      const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
-      for (int h = tid; h < NHALO; h += NT) {
+      const int64_t po = ((int64_t)(p + NG) * g.p2 + j0) * P1;
+      for (int h = tid; h < NHALO && p >= 0 && p < n3; h += NT) {
         double u[NV];
         const int c = hcell(h);
+        const int64_t hs = hshift(h);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + c];
+        for (int v = 0; v < NV; ++v) u[v] = in[po + hs + v * vs + c];
         stage_cell(u, c);
       }
     }
@@ -290,17 +341,17 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const double du = dq[0][v] + (fz[v] - fzp[v]) * bi.idx[2];
-          const double ub = RECON ? (BPF ? ubn[v] : base[v * vs + o]) : uq[0][v];
+          const double ub = RECON ? (BPF ? ubn[sl][v] : base[v * vs + o]) : uq[0][v];
           un[v] = ub - coef * du;
           out[v * vs + o] = un[v];
         }
         if constexpr (BPF) {
-          if (k + 1 < n3) {
+          if (k + PFD < n3) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) ubn[v] = base[v * vs + o + (int64_t)g.p2 * P1];
+            for (int v = 0; v < NV; ++v) ubn[sl][v] = base[v * vs + o + (int64_t)PFD * g.p2 * P1];
           }
         }
-        if (nb27) push_ghosts(a.uout, nb27, g, ti, j, k, un);
+        if (nb27) push_yz_ghosts(a.uout, nb27, g, ti, j, k, un);
         if (a.do_dt) {
           const bool skip = ((mask >> XLO) & 1 && ti == 0) || ((mask >> XHI) & 1 && ti == N1 - 1) ||
                             ((mask >> YLO) & 1 && j == 0) || ((mask >> YHI) & 1 && j == n2 - 1) ||
