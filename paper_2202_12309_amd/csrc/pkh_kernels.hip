@@ -236,7 +236,6 @@ __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const Bloc
     if (touched) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) cell[v * g.vstride] = uc[v];
-      push_ghosts(u, nbr + (int64_t)b * 27, g, i, j, k, uc);
       if (do_dt) {
         double wn[NV];
         bad = !to_prim(uc, g.gamma, wn);
@@ -466,16 +465,17 @@ __global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, 
   const int b = blockIdx.x;
   const int ncell = g.n1 * g.n2 * g.n3;
   const double gm1 = g.gamma - 1.0;
-  const int64_t st[3] = {1, g.p1, (int64_t)g.p1 * g.p2};
   double mx = 0.0;
   for (int q = threadIdx.x; q < ncell; q += 256) {
     const int i = q % g.n1, j = (q / g.n1) % g.n2, k = q / (g.n1 * g.n2);
     const double* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      // x neighbours beyond the block: the x neighbour's active cells
-      const double* cp = d == 0 && i == g.n1 - 1 ? u + xrow_cell(g, nbr, b, j, k, i + 1) : cell + st[d];
-      const double* cm = d == 0 && i == 0 ? u + xrow_cell(g, nbr, b, j, k, -1) : cell - st[d];
+      // neighbours beyond the block: the face neighbour's active cells
+      const int ip = i + (d == 0), jp = j + (d == 1), kp = k + (d == 2);
+      const int im = i - (d == 0), jm = j - (d == 1), km = k - (d == 2);
+      const double* cp = u + nb_index(g, nbr, b, ip, jp, kp);
+      const double* cm = u + nb_index(g, nbr, b, im, jm, km);
       const double pp = pressure_nc(cp, g.vstride, gm1);
       const double pm = pressure_nc(cm, g.vstride, gm1);
       mx = fmax(mx, fabs(pp - pm) / (pp + pm));
@@ -562,8 +562,8 @@ namespace pkh {
 template <int RECON, int D>
 __device__ __forceinline__ void adj_pencil(const double* __restrict__ U, const double* __restrict__ lam,
                                            double* __restrict__ wbar, const BlockInfo* blocks,
-                                           int nblocks, const Geom& g, const double* dtp, double beta,
-                                           int64_t gid) {
+                                           const int32_t* __restrict__ nbr, int nblocks, const Geom& g,
+                                           const double* dtp, double beta, int64_t gid) {
   const int n[3] = {g.n1, g.n2, g.n3};
   constexpr int T1 = D == 0 ? 1 : 0, T2 = D == 2 ? 1 : 2;
   const int nt1 = n[T1], nt2 = n[T2], nd = n[D];
@@ -588,8 +588,14 @@ __device__ __forceinline__ void adj_pencil(const double* __restrict__ U, const d
   const int ps = pst[D], as = ast[D];
 
   auto loadu = [&](int s, double u[NV]) {
+    int64_t at = pbase + (int64_t)s * ps;
+    if (s < 0 || s >= nd) {
+      int cc[3] = {c3[0], c3[1], c3[2]};
+      cc[D] = s;
+      at = nb_index(g, nbr, b, cc[0], cc[1], cc[2]);
+    }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = U[pbase + (int64_t)v * g.vstride + (int64_t)s * ps];
+    for (int v = 0; v < NV; ++v) u[v] = U[at + (int64_t)v * g.vstride];
   };
   auto loadl = [&](int s, double l[NV]) {
 #pragma unroll
@@ -779,7 +785,7 @@ __global__ void __launch_bounds__(256) adj_xlast_kernel(const double* __restrict
   const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
   const int64_t abase = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
   auto loadw = [&](int s, double w[NV]) {
-    const int64_t at = s < nd ? pbase + s : xrow_cell(g, nbr, b, j, k, s);
+    const int64_t at = s < nd ? pbase + s : nb_index(g, nbr, b, s, j, k);
     double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = U[at + (int64_t)v * g.vstride];
@@ -875,7 +881,7 @@ __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict_
   const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
   const int64_t abase = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
   auto loadw = [&](int s, double w[NV]) {
-    const int64_t at = (s >= 0 && s < N1) ? pbase + s : xrow_cell(g, nbr, b, j, k, s);
+    const int64_t at = (s >= 0 && s < N1) ? pbase + s : nb_index(g, nbr, b, s, j, k);
     double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = U[at + (int64_t)v * g.vstride];
@@ -1023,18 +1029,19 @@ template <int RECON>
 __global__ void __launch_bounds__(256) adj_pencils_kernel(const double* __restrict__ U,
                                                           const double* __restrict__ lam,
                                                           double* __restrict__ wbar3, int64_t wstride,
-                                                          const BlockInfo* blocks, int nblocks, Geom g,
-                                                          const double* dtp, double beta, int dir0) {
+                                                          const BlockInfo* blocks, const int32_t* nbr,
+                                                          int nblocks, Geom g, const double* dtp, double beta,
+                                                          int dir0) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   switch (blockIdx.y + dir0) {
     case 0:
-      adj_pencil<RECON, 0>(U, lam, wbar3, blocks, nblocks, g, dtp, beta, gid);
+      adj_pencil<RECON, 0>(U, lam, wbar3, blocks, nbr, nblocks, g, dtp, beta, gid);
       break;
     case 1:
-      adj_pencil<RECON, 1>(U, lam, wbar3 + wstride, blocks, nblocks, g, dtp, beta, gid);
+      adj_pencil<RECON, 1>(U, lam, wbar3 + wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
       break;
     default:
-      adj_pencil<RECON, 2>(U, lam, wbar3 + 2 * wstride, blocks, nblocks, g, dtp, beta, gid);
+      adj_pencil<RECON, 2>(U, lam, wbar3 + 2 * wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
   }
 }
 
@@ -1143,11 +1150,11 @@ hipError_t launch_adj_stage(int recon, const double* U, const double* lam, doubl
   const int dir0 = 1;
   dim3 grid((unsigned)((npen + 255) / 256), 3 - dir0);
   if (recon)
-    hipLaunchKernelGGL(adj_pencils_kernel<1>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nblocks, g,
-                       dtp, beta, dir0);
+    hipLaunchKernelGGL(adj_pencils_kernel<1>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nbr, nblocks,
+                       g, dtp, beta, dir0);
   else
-    hipLaunchKernelGGL(adj_pencils_kernel<0>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nblocks, g,
-                       dtp, beta, dir0);
+    hipLaunchKernelGGL(adj_pencils_kernel<0>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nbr, nblocks,
+                       g, dtp, beta, dir0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)nblocks * g.n1 * g.n2 * g.n3;

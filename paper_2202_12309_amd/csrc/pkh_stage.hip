@@ -102,14 +102,24 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   const int fsz = NV * max(max(g.n1 * n2, g.n1 * n3), n2 * n3);  // face slot stride
   double* fbuf = a.fbuf;
   const int32_t* nb27 = a.nbr ? a.nbr + (int64_t)blk * 27 : nullptr;
-  // x halo of interior rows: read from the active cells of same-level x
-  // neighbours (their last / first two columns) rather than from this
-  // block's ghost zone, which the stage kernels do not keep for x; a
-  // neighbour on another level (or no table) leaves it to the ghost zone
-  const int32_t nbxl = nb27 ? nb27[12] : -1, nbxr = nb27 ? nb27[14] : -1;
-  // offsets from this block's base to the x neighbours' matching cells
-  const int64_t dxl = nbxl >= 0 ? (int64_t)(nbxl - blk) * g.bstride + N1 : 0;
-  const int64_t dxr = nbxr >= 0 ? (int64_t)(nbxr - blk) * g.bstride - N1 : 0;
+  // Cells beyond the block (the x halo of interior rows, the y halo rows of
+  // the tiles at the block's y faces, the z planes before and after it) are
+  // read from the active cells of the same-level face neighbours: the stage
+  // kernels keep no ghost zones for same-level faces. A face to a leaf on
+  // another level reads this block's ghost zone, which the fill kernel
+  // writes. Offsets from this block's cell to the cell read instead:
+  auto nbshift = [&](int q, int64_t within) -> int64_t {
+    const int32_t nb = nb27 ? nb27[q] : -1;
+    return nb >= 0 ? (int64_t)(nb - blk) * g.bstride + within : 0;
+  };
+  const int64_t dxl = nbshift(12, N1), dxr = nbshift(14, -N1);
+  const int64_t dyl = j0 == 0 ? nbshift(10, (int64_t)n2 * P1) : 0;
+  const int64_t dyh = j0 + TJ == n2 ? nbshift(16, -(int64_t)n2 * P1) : 0;
+  const int64_t dzl = nbshift(4, (int64_t)n3 * g.p2 * P1), dzh = nbshift(22, -(int64_t)n3 * g.p2 * P1);
+  // offset of plane p (row j0-2) of this block, or of the z neighbour's plane
+  auto pofs = [&](int p) -> int64_t {
+    return ((int64_t)(p + NG) * g.p2 + j0) * P1 + (p < 0 ? dzl : (p >= n3 ? dzh : 0));
+  };
   const int own = (tj + NG) * P1 + ti + NG;  // this thread's cell in the LDS plane
 
   FState w[WN];       // z window (column states)
@@ -191,9 +201,8 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     return (r + NG) * P1 + (s4 < 2 ? s4 : P1 - 4 + s4);
   };
   // offset from this block's cell to the one halo cell h is read from
-  // (x-halo cells: the x neighbour's)
   auto hshift = [&](int h) -> int64_t {
-    if (h < 4 * N1) return 0;
+    if (h < 4 * N1) return h < 2 * N1 ? dyl : dyh;
     return ((h - 4 * N1) & 3) < 2 ? dxl : dxr;
   };
   constexpr int HMAX = PF ? (NHALO + NT - 1) / NT : 1;
@@ -215,7 +224,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   if constexpr (PF) {
 #pragma unroll
     for (int sl = 0; sl < PFD; ++sl) {
-      const double* pl = in + ((int64_t)(p_first + sl + NG) * g.p2 + j0) * P1;
+      const double* pl = in + pofs(p_first + sl);
 #pragma unroll
       for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own];
       // the halo is only read on the active planes
@@ -244,7 +253,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 #pragma unroll
         for (int v = 0; v < NV; ++v) u[v] = pu[sl][v];
       } else {
-        const double* pl = in + ((int64_t)(p + NG) * g.p2 + j0) * P1;
+        const double* pl = in + pofs(p);
 #pragma unroll
         for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + own];
       }
@@ -270,7 +279,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
         }
       }
       if (p + PFD < p_end) {
-        const int64_t po = ((int64_t)(p + PFD + NG) * g.p2 + j0) * P1;
+        const int64_t po = pofs(p + PFD);
         const double* pn = in + po;
 #pragma unroll
         for (int v = 0; v < NV; ++v) pu[sl][v] = pn[v * vs + own];
@@ -287,7 +296,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
         }
       }
     } else {
-      const int64_t po = ((int64_t)(p + NG) * g.p2 + j0) * P1;
+      const int64_t po = pofs(p);
       for (int h = tid; h < NHALO && p >= 0 && p < n3; h += NT) {
         double u[NV];
         const int c = hcell(h);
@@ -351,7 +360,6 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
             for (int v = 0; v < NV; ++v) ubn[sl][v] = base[v * vs + o + (int64_t)PFD * g.p2 * P1];
           }
         }
-        if (nb27) push_yz_ghosts(a.uout, nb27, g, ti, j, k, un);
         if (a.do_dt) {
           const bool skip = ((mask >> XLO) & 1 && ti == 0) || ((mask >> XHI) & 1 && ti == N1 - 1) ||
                             ((mask >> YLO) & 1 && j == 0) || ((mask >> YHI) & 1 && j == n2 - 1) ||
