@@ -98,6 +98,10 @@ hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* inst
 // requested value (0: default, which for n1 = 32 depends on the blocks of the
 // launch, nblocks; 0 there means many); -1 if no compiled variant fits.
 int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0);
+// Ghost face regions of the (leaf, face) pairs jf[2 njf] (faces whose
+// neighbour is on another level).
+hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
+                             DevTime* tm, const int32_t* jf, int32_t njf, hipStream_t s);
 // skip_same: leave ghost cells whose source is a same-level leaf alone
 // (the stage kernels already wrote them).
 hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,

@@ -133,14 +133,11 @@ __device__ __forceinline__ void ghost_coord(int q, const Geom& g, int& i, int& j
   i = s < 2 ? s - NG : g.n1 + s - 2;
 }
 
-__global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* blocks, int nblocks,
-                                                   Geom g, LevelMaps M, DevTime* tm, int skip_same) {
-  const int ngc = 4 * g.p1 * g.p2 + 4 * g.n3 * g.p1 + 4 * g.n3 * g.n2;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y;
-  if (q >= ngc || b >= nblocks) return;
-  int i, j, k;
-  ghost_coord(q, g, i, j, k);
+// Value of ghost cell (i, j, k) of leaf b from the leaf data (copy,
+// restriction or prolongation); skip_same leaves cells whose source is a
+// same-level leaf alone.
+__device__ __forceinline__ void fill_cell(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& M,
+                                          DevTime* tm, int b, int i, int j, int k, int skip_same) {
   const BlockInfo bi = blocks[b];
   const int L = bi.level;
   const int n[3] = {g.n1, g.n2, g.n3};
@@ -169,6 +166,47 @@ __global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* b
       dst[v * g.vstride] = comp_val(u, blocks, M, g, L, J[0], J[1], J[2], v, &err);
   }
   if (err) atomicOr(&tm->err, 2);
+}
+
+// Every ghost region (all 26) of every leaf.
+__global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* blocks, int nblocks,
+                                                   Geom g, LevelMaps M, DevTime* tm, int skip_same) {
+  const int ngc = 4 * g.p1 * g.p2 + 4 * g.n3 * g.p1 + 4 * g.n3 * g.n2;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (q >= ngc || b >= nblocks) return;
+  int i, j, k;
+  ghost_coord(q, g, i, j, k);
+  fill_cell(u, blocks, g, M, tm, b, i, j, k, skip_same);
+}
+
+// The face regions (width 2, active transverse extent) listed in jf as
+// (leaf, face) pairs: the faces whose neighbour is on another level, the
+// only ghost cells the stage kernels read.
+__global__ void __launch_bounds__(256) fill_faces_kernel(double* u, const BlockInfo* blocks, Geom g, LevelMaps M,
+                                                         DevTime* tm, const int32_t* __restrict__ jf) {
+  const int2 rec = reinterpret_cast<const int2*>(jf)[blockIdx.y];
+  const int b = rec.x, d = rec.y >> 1, hi = rec.y & 1;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const int area = n[t1] * n[t2];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 2 * area) return;
+  const int s = q / area, r = q - s * area;
+  int c[3];
+  c[t1] = r % n[t1];
+  c[t2] = r / n[t1];
+  c[d] = hi ? n[d] + s : s - NG;
+  fill_cell(u, blocks, g, M, tm, b, c[0], c[1], c[2], 1);
+}
+
+hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
+                             DevTime* tm, const int32_t* jf, int32_t njf, hipStream_t s) {
+  if (njf <= 0) return hipSuccess;
+  const int area = std::max(std::max(g.n1 * g.n2, g.n1 * g.n3), g.n2 * g.n3);
+  dim3 grid((2 * area + 255) / 256, njf);
+  hipLaunchKernelGGL(fill_faces_kernel, grid, dim3(256), 0, s, u, blocks, g, maps, tm, jf);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,

@@ -188,6 +188,8 @@ struct pkh_mesh {
   int32_t ncblocks = 0;
   int32_t* d_nbr = nullptr;   // [leaf][27] same-level neighbours (-1: other level)
   bool need_fill = false;     // some ghost region has a neighbour at another level
+  int32_t* d_jf = nullptr;    // (leaf, face) pairs whose face neighbour is on another level
+  int32_t njf = 0;
   double* d_partial = nullptr;
   double* d_tot = nullptr;
   size_t partial_cap = 0;
@@ -240,6 +242,7 @@ void free_tables(pkh_mesh* m) {
   m->dfree(m->d_ff);
   m->dfree(m->d_ff_first);
   m->dfree(m->d_cblocks);
+  m->dfree(m->d_jf);
   m->dfree(m->d_nbr);
   m->d_nbr = nullptr;
   m->d_blocks = nullptr;
@@ -248,6 +251,8 @@ void free_tables(pkh_mesh* m) {
   m->d_ff = nullptr;
   m->d_ff_first = nullptr;
   m->d_cblocks = nullptr;
+  m->d_jf = nullptr;
+  m->njf = 0;
   m->ncblocks = 0;
 }
 
@@ -344,6 +349,18 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
           if (id < 0) need_fill = true;
         }
   }
+  // faces whose neighbour is on another level: the ghost regions the stage
+  // kernels read from the ghost zone (all same-level halos are read from the
+  // neighbours' active cells)
+  std::vector<int32_t> jf;
+  for (int64_t b = 0; b < nb; ++b) {
+    static const int slot[6] = {12, 14, 10, 16, 4, 22};
+    for (int f = 0; f < 6; ++f)
+      if (nbr[b * 27 + slot[f]] < 0) {
+        jf.push_back((int32_t)b);
+        jf.push_back(f);
+      }
+  }
   // level maps
   std::vector<int32_t> flat;
   for (int L = 0; L <= t.maxl; ++L) {
@@ -368,6 +385,8 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
     m->ncblocks = (int32_t)cblocks.size();
     if ((rc = upload_vec(m, &m->d_nbr, nbr))) return rc;
     m->need_fill = need_fill;
+    m->njf = (int32_t)(jf.size() / 2);
+    if (m->njf && (rc = upload_vec(m, &m->d_jf, jf))) return rc;
   }
   // the host vectors above are sources of asynchronous copies
   HIPCHK(hipStreamSynchronize(m->stream));
@@ -462,9 +481,9 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
                                m->ncblocks, m->g, m->d_time, 0.5, 0, m->d_fbuf, m->d_nbr,
                                m->stream));
   }
-  if (m->need_fill) {  // same-level ghosts were written by the stage kernel
+  if (m->njf) {  // ghost faces across level jumps (same-level halos are read directly)
     KTimer kt(m, 2, capturing);
-    HIPCHK(launch_fill(m->B, m->d_blocks, nb, m->g, m->maps, m->d_time, 1, m->stream));
+    HIPCHK(launch_fill_faces(m->B, m->d_blocks, m->g, m->maps, m->d_time, m->d_jf, m->njf, m->stream));
   }
   // corrector: U^{n+1} = U^n - dt D_PLM(U*), in place; CFL reduction fused
   s.uin = m->B;
@@ -483,9 +502,9 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
                                m->ncblocks, m->g, m->d_time, 1.0, 1, m->d_fbuf, m->d_nbr,
                                m->stream));
   }
-  if (m->need_fill) {
+  if (m->njf) {
     KTimer kt(m, 2, capturing);
-    HIPCHK(launch_fill(m->A, m->d_blocks, nb, m->g, m->maps, m->d_time, 1, m->stream));
+    HIPCHK(launch_fill_faces(m->A, m->d_blocks, m->g, m->maps, m->d_time, m->d_jf, m->njf, m->stream));
   }
   HIPCHK(launch_clock(m->d_time, mode_after, t_end, m->stream));
   return PKH_OK;
