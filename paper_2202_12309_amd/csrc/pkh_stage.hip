@@ -512,16 +512,17 @@ static hipError_t launch_stage_n(const StageLaunch& a, hipStream_t s) {
   return a.recon ? launch_stage_t<1, N1, TJ>(a, s) : launch_stage_t<0, N1, TJ>(a, s);
 }
 
-int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks) {
+int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks, int recon) {
   // compiled (N1, TJ) variants; the first is the default. For n1 = 32 the
-  // default is 16 rows once the launch has at least two rounds of waves at
-  // two waves per SIMD (4096 waves), else 8 (more, smaller workgroups).
+  // corrector's default is 16 rows once the launch has at least two rounds
+  // of waves at two waves per SIMD (4096 waves), else 8; the predictor's is
+  // 8 (measured at 256^3: 16 rows for the corrector, 8 for the predictor).
   static const int opts[4][3] = {{8, 8, 0}, {8, 16, 4}, {16, 8, 4}, {4, 2, 0}};
   const int row = n1 == 8 ? 0 : n1 == 16 ? 1 : n1 == 32 ? 2 : n1 == 64 ? 3 : -1;
   if (row < 0) return -1;
   if (tj == 0) {
     tj = opts[row][0];
-    if (n1 == 32 && nblocks > 0 && nblocks * n1 * n2 / 64 < 4096) tj = 8;
+    if (n1 == 32 && (!recon || (nblocks > 0 && nblocks * n1 * n2 / 64 < 4096))) tj = 8;
   }
   for (int q = 0; q < 3; ++q)
     if (opts[row][q] == tj && tj > 0 && n2 % tj == 0) return tj;
@@ -552,7 +553,7 @@ hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* inst
 }
 
 hipError_t launch_stage(const StageLaunch& a, hipStream_t s) {
-  const int tj = stage_tile_rows(a.g.n1, a.g.n2, a.tj, a.nblocks);
+  const int tj = stage_tile_rows(a.g.n1, a.g.n2, a.tj, a.nblocks, a.recon);
   switch (a.g.n1 * 100 + tj) {
     case 808:
       return launch_stage_n<8, 8>(a, s);
