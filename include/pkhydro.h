@@ -139,16 +139,23 @@ int pkh_state_download(pkh_mesh *mesh, double *dst, int32_t dst_on_device);
 
 /* Fill every ghost zone from the leaves' active data (Sec. 3.7: copy,
    restriction, prolongation, all 26 neighbour regions, periodic wrap) and
-   recompute the CFL timestep from the active data (Sec. 3.10). */
+   recompute the CFL timestep from the active data (Sec. 3.10). Inside
+   pkh_step the kernels read a same-level neighbour's cells directly and only
+   the face ghost regions that cross a level jump are refilled after each
+   stage; the other ghost cells keep the values of the last full fill. */
 int pkh_exchange_boundaries(pkh_mesh *mesh);
 
 /* Advance n_cycles full cycles (Sec. 4.1). Each cycle:
      dt  = CFL timestep of the current state, clamped to t_end - t when
            t_end is finite;
      U*  = U^n - dt/2 D(U^n)   (donor-cell or PLM faces, HLLE fluxes);
-     ghost fill of U*, with fine-coarse flux correction on multilevel meshes;
+     on multilevel meshes, fine-coarse flux correction and the ghost faces
+     across level jumps of U*;
      U^{n+1} = U^n - dt D_PLM(U*) (MC-limited PLM on primitives, HLLE);
-     ghost fill of U^{n+1}; t += dt; the next dt is reduced on the device.
+     the same for U^{n+1}; t += dt; the next dt is reduced on the device.
+   Halo cells at same-level faces are read from the neighbour's active
+   cells (the results equal those of a full ghost exchange after each
+   stage).
    No host synchronisation. With PKH_FLAG_GRAPH the cycles are replayed
    from a captured hipGraph. */
 int pkh_step(pkh_mesh *mesh, int32_t n_cycles, double t_end);
@@ -166,7 +173,8 @@ int pkh_set_refinement_flags(pkh_mesh *mesh, const int8_t *flags, int64_t n);
 /* Device refinement indicator (the paper leaves the criterion to the
    application; Sec. 2.1, Sec. 3.8). Per leaf, eta = the largest
    |P(i+e_d) - P(i-e_d)| / (P(i+e_d) + P(i-e_d)) over active cells i and
-   directions d, from the current state with ghosts filled; evaluated without
+   directions d (neighbour cells across a block face as for the stencil);
+   evaluated without
    FMA contraction and with correctly rounded division. Sets the mesh's flags
    to +1 where eta > refine_above, -1 where eta < derefine_below, else 0 (as
    pkh_set_refinement_flags would) and, when non-NULL, copies them to
@@ -267,7 +275,7 @@ int pkh_autotune(pkh_mesh *mesh, int32_t trial_cycles, pkh_tuning *out);
 enum {
   PKH_KT_PREDICTOR = 1u, /* stage-1 kernel */
   PKH_KT_CORRECTOR = 2u, /* stage-2 kernel (with the fused CFL reduction) */
-  PKH_KT_FILL = 4u,      /* ghost exchange kernel */
+  PKH_KT_FILL = 4u,      /* ghost fill kernel (faces across level jumps) */
   PKH_KT_FLUXCORR = 8u,  /* fine-coarse flux correction kernel */
   PKH_KT_ADJOINT = 16u   /* reverse sweep of one stage (pkh_adjoint) */
 };

@@ -793,9 +793,10 @@ __device__ __forceinline__ void adj_pencil(const double* __restrict__ U, const d
 // of one row and the face below it (face i, between cells i-1 and i), so
 // loads and stores are coalesced. Neighbour states and the contributions a
 // face makes to cells i-2 .. i+1 move between lanes by shuffles within the
-// segment. The face above the last cell (face n1) has no lane; a separate
-// pass computes it for every row first and leaves its contributions in a
-// side buffer (20 doubles per row) that the row pass merges.
+// segment. The face above the last cell (face n1) has no lane; it is
+// computed for every row alongside the y and z pencils and leaves its
+// contributions to cells n1-2 .. n1+1 in a side buffer (20 doubles per row)
+// that the exchange pass adds.
 // ---------------------------------------------------------------------------
 
 // Side-buffer slot q of row `row` (slot-major, rows fastest).
@@ -804,12 +805,10 @@ __device__ __forceinline__ int64_t xlast_at(int64_t nrows, int q, int64_t row) {
 }
 
 template <int RECON>
-__global__ void __launch_bounds__(256) adj_xlast_kernel(const double* __restrict__ U,
-                                                        const double* __restrict__ lam,
-                                                        double* __restrict__ xl, const BlockInfo* blocks,
-                                                        const int32_t* __restrict__ nbr, int nblocks, Geom g,
-                                                        const double* dtp, double beta) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adj_xlast(const double* __restrict__ U, const double* __restrict__ lam,
+                                          double* __restrict__ xl, const BlockInfo* blocks,
+                                          const int32_t* __restrict__ nbr, int nblocks, const Geom& g,
+                                          const double* dtp, double beta, int64_t row) {
   const int64_t rpb = (int64_t)g.n2 * g.n3;
   const int64_t nrows = rpb * nblocks;
   if (row >= nrows) return;
@@ -874,13 +873,18 @@ __global__ void __launch_bounds__(256) adj_xlast_kernel(const double* __restrict
     complete_state(Qb, gam, igm1);
     double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     hlle_rev<0>(Qa, Qb, gm1, mu, gL, gR);
-    double gw[NV] = {0, 0, 0, 0, 0};
-    complete_state_rev(Qb, gam, igm1, gR, gw);
-    // slots 0..7: derived-state adjoint of cell nd-1; 8..12: cell nd
+    // the reverse of the derived state is linear in its adjoint, so the face's
+    // part of cell nd-1 is reversed here on its own
+    double ga[NV] = {0, 0, 0, 0, 0}, gb[NV] = {0, 0, 0, 0, 0};
+    complete_state_rev(Qa, gam, igm1, gL, ga);
+    complete_state_rev(Qb, gam, igm1, gR, gb);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) xl[xlast_at(nrows, q, row)] = gL[q];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) xl[xlast_at(nrows, 8 + v, row)] = gw[v];
+    for (int v = 0; v < NV; ++v) {
+      xl[xlast_at(nrows, 0 * NV + v, row)] = 0.0;
+      xl[xlast_at(nrows, 1 * NV + v, row)] = ga[v];
+      xl[xlast_at(nrows, 2 * NV + v, row)] = gb[v];
+      xl[xlast_at(nrows, 3 * NV + v, row)] = 0.0;
+    }
   }
 }
 
@@ -899,7 +903,6 @@ template <int RECON, int N1>
 __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict__ U,
                                                        const double* __restrict__ lam,
                                                        double* __restrict__ wbar,
-                                                       const double* __restrict__ xl,
                                                        const BlockInfo* blocks,
                                                        const int32_t* __restrict__ nbr, int nblocks, Geom g,
                                                        const double* dtp, double beta) {
@@ -985,22 +988,16 @@ __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict_
       const double c3 = -gr[v] * 0.5 * gb1[v];
       const double f1 = shdn<N1>(c1, 1), f0 = shdn<N1>(c0, 2), b3 = shup<N1>(c3, 1);
       const double f0n = shdn<N1>(c0, 1);
-      // face n1 (side buffer): k0 -> cell n1-2, k1 -> n1-1, k2 -> n1, k3 -> n1+1
-      double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
-      if (i == N1 - 2) x0 = xl[xlast_at(nrows, 0 * NV + v, row)];
-      if (last) {
-        x1 = xl[xlast_at(nrows, 1 * NV + v, row)];
-        x2 = xl[xlast_at(nrows, 2 * NV + v, row)];
-        x3 = xl[xlast_at(nrows, 3 * NV + v, row)];
-      }
+      // face n1 has no lane: its parts of cells n1-2 .. n1+1 come from the
+      // side buffer in the exchange pass
       double a = c2 + (first ? 0.0 : b3);
-      a += last ? x1 : f1;
-      a += (i >= N1 - 2) ? x0 : f0;
+      a += last ? 0.0 : f1;
+      a += (i >= N1 - 2) ? 0.0 : f0;
       own[v] = a;
       gm2[v] = c0;         // lane 0: cell -2
       gm1c[v] = c1 + f0n;  // lane 0: cell -1
-      gp3[v] = c3 + x2;    // last lane: cell n1
-      gp4[v] = x3;         // last lane: cell n1+1
+      gp3[v] = c3;         // last lane: cell n1
+      gp4[v] = 0.0;        // last lane: cell n1+1
     }
     emit(i, own);
     if (first) {
@@ -1039,9 +1036,7 @@ __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict_
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double nb = shdn<N1>(gL[q], 1);
-      double x = 0.0;
-      if (last) x = xl[xlast_at(nrows, q, row)];
-      gQ[q] = gR[q] + (last ? x : nb);
+      gQ[q] = gR[q] + (last ? 0.0 : nb);  // face n1's part: side buffer
     }
     double gw[NV] = {0, 0, 0, 0, 0};
     complete_state_rev(Q, gam, igm1, gQ, gw);
@@ -1054,32 +1049,31 @@ __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict_
       emit(-2, zero5);
     }
     if (last) {
-      double gn[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) gn[v] = xl[xlast_at(nrows, 8 + v, row)];
-      emit(N1, gn);
+      emit(N1, zero5);
       emit(N1 + 1, zero5);
     }
   }
 }
 
+// One launch for the y pencils, the z pencils and the last x face of every
+// row (blockIdx.y = 0, 1, 2).
 template <int RECON>
 __global__ void __launch_bounds__(256) adj_pencils_kernel(const double* __restrict__ U,
                                                           const double* __restrict__ lam,
                                                           double* __restrict__ wbar3, int64_t wstride,
-                                                          const BlockInfo* blocks, const int32_t* nbr,
-                                                          int nblocks, Geom g, const double* dtp, double beta,
-                                                          int dir0) {
+                                                          double* __restrict__ xl, const BlockInfo* blocks,
+                                                          const int32_t* nbr, int nblocks, Geom g,
+                                                          const double* dtp, double beta) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  switch (blockIdx.y + dir0) {
+  switch (blockIdx.y) {
     case 0:
-      adj_pencil<RECON, 0>(U, lam, wbar3, blocks, nbr, nblocks, g, dtp, beta, gid);
-      break;
-    case 1:
       adj_pencil<RECON, 1>(U, lam, wbar3 + wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
       break;
-    default:
+    case 1:
       adj_pencil<RECON, 2>(U, lam, wbar3 + 2 * wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
+      break;
+    default:
+      adj_xlast<RECON>(U, lam, xl, blocks, nbr, nblocks, g, dtp, beta, gid);
   }
 }
 
@@ -1090,7 +1084,8 @@ __global__ void __launch_bounds__(256) adj_pencils_kernel(const double* __restri
 __global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restrict__ wbar,
                                                            int64_t wstride,
                                                            const double* __restrict__ U,
-                                                           const int32_t* __restrict__ nbr, Geom g,
+                                                           const int32_t* __restrict__ nbr,
+                                                           const double* __restrict__ xl, Geom g,
                                                            int64_t total, double* out,
                                                            const double* add0, const double* add1) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1120,6 +1115,19 @@ __global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restr
   if (j >= g.n2 - NG) add_copy(0, 1, 0);
   if (k < NG) add_copy(0, 0, -1);
   if (k >= g.n3 - NG) add_copy(0, 0, 1);
+  // the last x face of a row (side buffer): cells n1-2, n1-1 of this row, and
+  // through the x-lower neighbour's row, cells n1, n1+1 beyond it (= 0, 1 here)
+  const int64_t rpb = (int64_t)g.n2 * g.n3, nrows = rpb * (total / ncell);
+  if (i >= g.n1 - 2) {
+    const int64_t row = (int64_t)b * rpb + (int64_t)k * g.n2 + j;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gw[v] += xl[xlast_at(nrows, (i - (g.n1 - 2)) * NV + v, row)];
+  }
+  if (i < 2 && nb27[12] >= 0) {
+    const int64_t row = (int64_t)nb27[12] * rpb + (int64_t)k * g.n2 + j;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gw[v] += xl[xlast_at(nrows, (2 + i) * NV + v, row)];
+  }
   double u[NV], gu[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = U[own + (int64_t)v * g.vstride];
@@ -1136,23 +1144,23 @@ __global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restr
 
 template <int RECON>
 static void launch_xrow(int n1, dim3 grid, hipStream_t s, const double* U, const double* lam, double* wx,
-                        const double* xl, const BlockInfo* blocks, const int32_t* nbr, int nblocks,
+                        const BlockInfo* blocks, const int32_t* nbr, int nblocks,
                         const Geom& g, const double* dtp, double beta) {
   switch (n1) {
     case 8:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 8>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nbr, nblocks, g,
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 8>), grid, dim3(256), 0, s, U, lam, wx, blocks, nbr, nblocks, g,
                          dtp, beta);
       break;
     case 16:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 16>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nbr, nblocks, g,
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 16>), grid, dim3(256), 0, s, U, lam, wx, blocks, nbr, nblocks, g,
                          dtp, beta);
       break;
     case 32:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 32>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nbr, nblocks, g,
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 32>), grid, dim3(256), 0, s, U, lam, wx, blocks, nbr, nblocks, g,
                          dtp, beta);
       break;
     default:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 64>), grid, dim3(256), 0, s, U, lam, wx, xl, blocks, nbr, nblocks, g,
+      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 64>), grid, dim3(256), 0, s, U, lam, wx, blocks, nbr, nblocks, g,
                          dtp, beta);
   }
 }
@@ -1163,41 +1171,29 @@ hipError_t launch_adj_stage(int recon, const double* U, const double* lam, doubl
                             const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                             const int32_t* nbr, const double* dtp, double beta, double* out,
                             const double* add0, const double* add1, hipStream_t s) {
-  const int64_t npen = (int64_t)nblocks * std::max(std::max((int64_t)g.n2 * g.n3, (int64_t)g.n1 * g.n3),
-                                                   (int64_t)g.n1 * g.n2);
+  // x: the rows face-parallel (this launch) and the last face of every row
+  // (with the pencils); y and z: pencils. The x ghost cells of the stage
+  // kernels' outputs are not kept (the x kernels read the neighbours' active
+  // cells), so the row path is the only x path.
+  if (!adj_xrow_supported(g.n1) || xlast == nullptr) return hipErrorInvalidValue;
+  const int64_t nrows = (int64_t)nblocks * g.n2 * g.n3;
+  const int64_t npen = std::max(std::max((int64_t)nblocks * g.n1 * g.n3, (int64_t)nblocks * g.n1 * g.n2), nrows);
   const int64_t wstride = (int64_t)nblocks * g.bstride;
-  // x: last face of every row, then the rows face-parallel; y and z: pencils.
-  // The x ghost cells of the stage kernels' outputs are not kept (the x
-  // kernels read the neighbours' active cells), so the row path is the only
-  // x path.
-  const bool rows = adj_xrow_supported(g.n1) && xlast != nullptr;
-  if (!rows) return hipErrorInvalidValue;
-  {
-    const int64_t nrows = (int64_t)nblocks * g.n2 * g.n3;
-    const dim3 gl((unsigned)((nrows + 255) / 256)), gr((unsigned)((nrows * g.n1 + 255) / 256));
-    if (recon) {
-      hipLaunchKernelGGL(adj_xlast_kernel<1>, gl, dim3(256), 0, s, U, lam, xlast, blocks, nbr, nblocks, g, dtp,
-                         beta);
-      launch_xrow<1>(g.n1, gr, s, U, lam, wbar3, xlast, blocks, nbr, nblocks, g, dtp, beta);
-    } else {
-      hipLaunchKernelGGL(adj_xlast_kernel<0>, gl, dim3(256), 0, s, U, lam, xlast, blocks, nbr, nblocks, g, dtp,
-                         beta);
-      launch_xrow<0>(g.n1, gr, s, U, lam, wbar3, xlast, blocks, nbr, nblocks, g, dtp, beta);
-    }
+  const dim3 gr((unsigned)((nrows * g.n1 + 255) / 256)), gp((unsigned)((npen + 255) / 256), 3);
+  if (recon) {
+    hipLaunchKernelGGL(adj_pencils_kernel<1>, gp, dim3(256), 0, s, U, lam, wbar3, wstride, xlast, blocks, nbr,
+                       nblocks, g, dtp, beta);
+    launch_xrow<1>(g.n1, gr, s, U, lam, wbar3, blocks, nbr, nblocks, g, dtp, beta);
+  } else {
+    hipLaunchKernelGGL(adj_pencils_kernel<0>, gp, dim3(256), 0, s, U, lam, wbar3, wstride, xlast, blocks, nbr,
+                       nblocks, g, dtp, beta);
+    launch_xrow<0>(g.n1, gr, s, U, lam, wbar3, blocks, nbr, nblocks, g, dtp, beta);
   }
-  const int dir0 = 1;
-  dim3 grid((unsigned)((npen + 255) / 256), 3 - dir0);
-  if (recon)
-    hipLaunchKernelGGL(adj_pencils_kernel<1>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nbr, nblocks,
-                       g, dtp, beta, dir0);
-  else
-    hipLaunchKernelGGL(adj_pencils_kernel<0>, grid, dim3(256), 0, s, U, lam, wbar3, wstride, blocks, nbr, nblocks,
-                       g, dtp, beta, dir0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)nblocks * g.n1 * g.n2 * g.n3;
   hipLaunchKernelGGL(adj_exchange_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, wbar3, wstride,
-                     U, nbr, g, total, out, add0, add1);
+                     U, nbr, xlast, g, total, out, add0, add1);
   return hipGetLastError();
 }
 
