@@ -209,7 +209,7 @@ typedef struct pkh_tape pkh_tape;
 
 /* Tape for the mesh; ckpt_every >= 1. Device memory: one active-state copy
    per checkpoint (allocated as cycles are recorded) plus 2*ckpt_every + 1
-   ghost-filled states for recomputation and 3 for the reverse sweep.
+   ghost-filled states for recomputation and 2 for the reverse sweep.
    PKH_EINVAL on multilevel meshes. */
 int pkh_tape_create(pkh_mesh *mesh, int32_t ckpt_every, pkh_tape **out);
 int pkh_tape_destroy(pkh_tape *tape);

@@ -132,11 +132,11 @@ hipError_t launch_regrid_data(double* unew, const BlockInfo* bnew, const int32_t
 
 // Reverse mode of one stage U_out = U_base - beta*dt*D(U_in) w.r.t. U_in
 // (same-level meshes): out = add0 + add1 + (dD/dU_in)^T-term of lam;
-// U is the padded, ghost-filled U_in; wbar scratch for three padded
-// states (one per direction); xlast scratch of 20 doubles per x-row (the
-// last face of each row; nullptr: x by pencils); dt is read from dtp on
+// U is the padded U_in (halos read from the face neighbours); wyz scratch
+// for two padded states (the y and z primitive adjoints); xside scratch of
+// 20 doubles per x-row (the parts across x faces); dt is read from dtp on
 // the device.
-hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar, double* xlast,
+hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wyz, double* xside,
                             const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                             const int32_t* nbr, const double* dtp, double beta, double* out,
                             const double* add0, const double* add1, hipStream_t s);

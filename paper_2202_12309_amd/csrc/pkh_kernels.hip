@@ -787,25 +787,72 @@ __device__ __forceinline__ void adj_pencil(const double* __restrict__ U, const d
 }
 
 // ---------------------------------------------------------------------------
-// x direction of the reverse sweep, face-parallel along rows. A pencil walk
-// along x would put every lane of a wave on a different row of the
-// contiguous dimension; here lane i of an n1-wide lane segment owns cell i
-// of one row and the face below it (face i, between cells i-1 and i), so
-// loads and stores are coalesced. Neighbour states and the contributions a
-// face makes to cells i-2 .. i+1 move between lanes by shuffles within the
-// segment. The face above the last cell (face n1) has no lane; it is
-// computed for every row alongside the y and z pencils and leaves its
-// contributions to cells n1-2 .. n1+1 in a side buffer (20 doubles per row)
-// that the exchange pass adds.
+// x direction of the reverse sweep and the closing of each cell, one pass
+// face-parallel along rows. A pencil walk along x would put every lane of a
+// wave on a different row of the contiguous dimension; here lane i of an
+// n1-wide lane segment owns cell i of one row and the face below it (face
+// i, between cells i-1 and i), so loads and stores are coalesced. Neighbour
+// states and the contributions a face makes to cells i-2 .. i+1 move between
+// lanes by shuffles within the segment. Everything that crosses a block's x
+// face - the face itself (with the face adjoints of both blocks combined)
+// and the parts of the two faces beside it that reach across - is computed
+// once per boundary row beforehand, alongside the y and z pencils, into a
+// side buffer of 20 doubles per row. The row pass then completes each cell:
+// its x part, the side-buffer part, its y and z parts and those of its
+// ghost copies in the y and z neighbours, the primitive-to-conserved
+// adjoint at its state, and the identity terms of the cycle.
 // ---------------------------------------------------------------------------
 
-// Side-buffer slot q of row `row` (slot-major, rows fastest).
-__device__ __forceinline__ int64_t xlast_at(int64_t nrows, int q, int64_t row) {
+// Side-buffer slot q of row `row` (slot-major, rows fastest). For the x
+// face between the row of block X and the same row of its x-upper
+// neighbour R, indexed by X's row: slots 0, 1 hold the parts for X's cells
+// n1-2, n1-1, slots 2, 3 those for R's cells 0, 1.
+__device__ __forceinline__ int64_t xside_at(int64_t nrows, int q, int64_t row) {
   return (int64_t)q * nrows + row;
 }
 
+// Adjoint of one PLM face normal to D from the primitives of cells f-2 ..
+// f+1 (Wa .. Wd) and the face adjoint mu: the parts c0 .. c3 of the four
+// cells' primitive adjoints.
+template <int D>
+__device__ __forceinline__ void plm_face_rev(const double Wa[NV], const double Wb[NV], const double Wc[NV],
+                                             const double Wd[NV], const double mu[NV], double gam,
+                                             double c0[NV], double c1[NV], double c2[NV], double c3[NV]) {
+  const double gm1 = gam - 1.0, igm1 = 1.0 / gm1;
+  double ga0[NV], gb0[NV], ga1[NV], gb1[NV], wl[NV], wr[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double s0 = mc_slope(Wb[v] - Wa[v], Wc[v] - Wb[v]);
+    mc_branch(Wb[v] - Wa[v], Wc[v] - Wb[v], ga0[v], gb0[v]);
+    const double s1 = mc_slope(Wc[v] - Wb[v], Wd[v] - Wc[v]);
+    mc_branch(Wc[v] - Wb[v], Wd[v] - Wc[v], ga1[v], gb1[v]);
+    wl[v] = Wb[v] + 0.5 * s0;
+    wr[v] = Wc[v] - 0.5 * s1;
+  }
+  FState L{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+  FState R{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+  complete_state(L, gam, igm1);
+  complete_state(R, gam, igm1);
+  double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  hlle_rev<D>(L, R, gm1, mu, gL, gR);
+  double gl[NV] = {0, 0, 0, 0, 0}, gr[NV] = {0, 0, 0, 0, 0};
+  complete_state_rev(L, gam, igm1, gL, gl);
+  complete_state_rev(R, gam, igm1, gR, gr);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    c0[v] = -gl[v] * 0.5 * ga0[v];
+    c1[v] = gl[v] * (1.0 + 0.5 * ga0[v] - 0.5 * gb0[v]) + gr[v] * 0.5 * ga1[v];
+    c2[v] = gl[v] * 0.5 * gb0[v] + gr[v] * (1.0 - 0.5 * ga1[v] + 0.5 * gb1[v]);
+    c3[v] = -gr[v] * 0.5 * gb1[v];
+  }
+}
+
+// The crossing parts at the x face above row `row` of block X (cells n1-1 |
+// 0 of X and R). PLM: the face itself with both face adjoints, the k3 part
+// of X's face n1-1 and the k0 part of R's face 1. Donor cell: the face
+// itself.
 template <int RECON>
-__device__ __forceinline__ void adj_xlast(const double* __restrict__ U, const double* __restrict__ lam,
+__device__ __forceinline__ void adj_xside(const double* __restrict__ U, const double* __restrict__ lam,
                                           double* __restrict__ xl, const BlockInfo* blocks,
                                           const int32_t* __restrict__ nbr, int nblocks, const Geom& g,
                                           const double* dtp, double beta, int64_t row) {
@@ -816,53 +863,49 @@ __device__ __forceinline__ void adj_xlast(const double* __restrict__ U, const do
   const int r = (int)(row - (int64_t)b * rpb);
   const int j = r % g.n2, k = r / g.n2;
   const int nd = g.n1;
+  const int32_t rb = nbr[(int64_t)b * 27 + 14];
+  if (rb < 0) {  // a face to another level: not part of a single-level sweep
+#pragma unroll
+    for (int q = 0; q < 4 * NV; ++q) xl[xside_at(nrows, q, row)] = 0.0;
+    return;
+  }
   const double gam = g.gamma, gm1 = gam - 1.0, igm1 = 1.0 / gm1;
   const double coef = beta * (*dtp) * blocks[b].idx[0];
-  const int64_t pbase = (int64_t)b * g.bstride + ((int64_t)(k + NG) * g.p2 + (j + NG)) * g.p1 + NG;
   const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
-  const int64_t abase = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
+  const int64_t lx = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
+  const int64_t lr = (int64_t)rb * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
   auto loadw = [&](int s, double w[NV]) {
-    const int64_t at = s < nd ? pbase + s : nb_index(g, nbr, b, s, j, k);
+    const int64_t at = nb_index(g, nbr, b, s, j, k);
     double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = U[at + (int64_t)v * g.vstride];
     to_prim(u, gam, w);
   };
-  double mu[NV];
+  double muB[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) mu[v] = -coef * lam[abase + (int64_t)v * ncell + (nd - 1)];
+  for (int v = 0; v < NV; ++v) muB[v] = coef * (lam[lr + (int64_t)v * ncell] - lam[lx + (int64_t)v * ncell + nd - 1]);
+  double o0[NV], o1[NV], o2[NV], o3[NV];
   if constexpr (RECON) {
-    double W0[NV], W1[NV], W2[NV], W3[NV];  // cells nd-2 .. nd+1
-    loadw(nd - 2, W0);
-    loadw(nd - 1, W1);
-    loadw(nd, W2);
-    loadw(nd + 1, W3);
-    double ga0[NV], gb0[NV], ga1[NV], gb1[NV], wl[NV], wr[NV];
+    double W0[NV], W1[NV], W2[NV], W3[NV], W4[NV], W5[NV];  // cells n1-3 .. n1+2
+    loadw(nd - 3, W0);
+    loadw(nd - 2, W1);
+    loadw(nd - 1, W2);
+    loadw(nd, W3);
+    loadw(nd + 1, W4);
+    loadw(nd + 2, W5);
+    double muA[NV], muC[NV], t0[NV], t1[NV], t2[NV], t3[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double s0 = mc_slope(W1[v] - W0[v], W2[v] - W1[v]);
-      mc_branch(W1[v] - W0[v], W2[v] - W1[v], ga0[v], gb0[v]);
-      const double s1 = mc_slope(W2[v] - W1[v], W3[v] - W2[v]);
-      mc_branch(W2[v] - W1[v], W3[v] - W2[v], ga1[v], gb1[v]);
-      wl[v] = W1[v] + 0.5 * s0;
-      wr[v] = W2[v] - 0.5 * s1;
+      muA[v] = coef * (lam[lx + (int64_t)v * ncell + nd - 1] - lam[lx + (int64_t)v * ncell + nd - 2]);
+      muC[v] = coef * (lam[lr + (int64_t)v * ncell + 1] - lam[lr + (int64_t)v * ncell]);
     }
-    FState L{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
-    FState R{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
-    complete_state(L, gam, igm1);
-    complete_state(R, gam, igm1);
-    double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    hlle_rev<0>(L, R, gm1, mu, gL, gR);
-    double gl[NV] = {0, 0, 0, 0, 0}, gr[NV] = {0, 0, 0, 0, 0};
-    complete_state_rev(L, gam, igm1, gL, gl);
-    complete_state_rev(R, gam, igm1, gR, gr);
+    plm_face_rev<0>(W1, W2, W3, W4, muB, gam, o0, o1, o2, o3);
+    plm_face_rev<0>(W0, W1, W2, W3, muA, gam, t0, t1, t2, t3);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      xl[xlast_at(nrows, 0 * NV + v, row)] = -gl[v] * 0.5 * ga0[v];
-      xl[xlast_at(nrows, 1 * NV + v, row)] = gl[v] * (1.0 + 0.5 * ga0[v] - 0.5 * gb0[v]) + gr[v] * 0.5 * ga1[v];
-      xl[xlast_at(nrows, 2 * NV + v, row)] = gl[v] * 0.5 * gb0[v] + gr[v] * (1.0 - 0.5 * ga1[v] + 0.5 * gb1[v]);
-      xl[xlast_at(nrows, 3 * NV + v, row)] = -gr[v] * 0.5 * gb1[v];
-    }
+    for (int v = 0; v < NV; ++v) o2[v] += t3[v];  // X's face n1-1 -> R's cell 0
+    plm_face_rev<0>(W2, W3, W4, W5, muC, gam, t0, t1, t2, t3);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) o1[v] += t0[v];  // R's face 1 -> X's cell n1-1
   } else {
     double wa[NV], wb[NV];
     loadw(nd - 1, wa);
@@ -872,19 +915,20 @@ __device__ __forceinline__ void adj_xlast(const double* __restrict__ U, const do
     complete_state(Qa, gam, igm1);
     complete_state(Qb, gam, igm1);
     double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    hlle_rev<0>(Qa, Qb, gm1, mu, gL, gR);
-    // the reverse of the derived state is linear in its adjoint, so the face's
-    // part of cell nd-1 is reversed here on its own
-    double ga[NV] = {0, 0, 0, 0, 0}, gb[NV] = {0, 0, 0, 0, 0};
-    complete_state_rev(Qa, gam, igm1, gL, ga);
-    complete_state_rev(Qb, gam, igm1, gR, gb);
+    hlle_rev<0>(Qa, Qb, gm1, muB, gL, gR);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      xl[xlast_at(nrows, 0 * NV + v, row)] = 0.0;
-      xl[xlast_at(nrows, 1 * NV + v, row)] = ga[v];
-      xl[xlast_at(nrows, 2 * NV + v, row)] = gb[v];
-      xl[xlast_at(nrows, 3 * NV + v, row)] = 0.0;
-    }
+    for (int v = 0; v < NV; ++v) o0[v] = o1[v] = o2[v] = o3[v] = 0.0;
+    // the reverse of the derived state is linear in its adjoint, so the
+    // face's parts of the two cells are reversed here on their own
+    complete_state_rev(Qa, gam, igm1, gL, o1);
+    complete_state_rev(Qb, gam, igm1, gR, o2);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    xl[xside_at(nrows, 0 * NV + v, row)] = o0[v];
+    xl[xside_at(nrows, 1 * NV + v, row)] = o1[v];
+    xl[xside_at(nrows, 2 * NV + v, row)] = o2[v];
+    xl[xside_at(nrows, 3 * NV + v, row)] = o3[v];
   }
 }
 
@@ -899,13 +943,19 @@ __device__ __forceinline__ double shdn(double x, int d) {
   return __shfl_down(x, d, W);
 }
 
+// The row pass. out = add0 + add1 + (dD/dU_in)^T-term of lam at every
+// active cell (add0, add1 may be null); wyz: the y and z primitive-adjoint
+// arrays (padded, wstride apart); xl: the side buffer.
 template <int RECON, int N1>
 __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict__ U,
                                                        const double* __restrict__ lam,
-                                                       double* __restrict__ wbar,
+                                                       const double* __restrict__ wyz, int64_t wstride,
+                                                       const double* __restrict__ xl,
                                                        const BlockInfo* blocks,
                                                        const int32_t* __restrict__ nbr, int nblocks, Geom g,
-                                                       const double* dtp, double beta) {
+                                                       const double* dtp, double beta, double* __restrict__ out,
+                                                       const double* __restrict__ add0,
+                                                       const double* __restrict__ add1) {
   static_assert(N1 == 8 || N1 == 16 || N1 == 32 || N1 == 64, "row width");
   const int i = (int)(threadIdx.x % N1);
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / N1;
@@ -921,279 +971,180 @@ __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict_
   const int64_t pbase = (int64_t)b * g.bstride + ((int64_t)(k + NG) * g.p2 + (j + NG)) * g.p1 + NG;
   const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
   const int64_t abase = (int64_t)b * NV * ncell + ((int64_t)k * g.n2 + j) * g.n1;
-  auto loadw = [&](int s, double w[NV]) {
+  const int32_t* nb27 = nbr + (int64_t)b * 27;
+  auto loadu = [&](int s, double u[NV]) {
     const int64_t at = (s >= 0 && s < N1) ? pbase + s : nb_index(g, nbr, b, s, j, k);
-    double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = U[at + (int64_t)v * g.vstride];
-    to_prim(u, gam, w);
   };
-  auto emit = [&](int s, const double a[NV]) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) wbar[pbase + (int64_t)v * g.vstride + s] = a[v];
-  };
-  // face i adjoint: coef * (lam(i) - lam(i-1)), lam(-1) = 0
+  // face i adjoint: coef * (lam(i) - lam(i-1)); face 0 crosses the block's
+  // x face and is left to the side buffer (mu = 0 here)
   double mu[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const double l0 = lam[abase + (int64_t)v * ncell + i];
     const double lm = shup<N1>(l0, 1);
-    mu[v] = coef * (l0 - (i > 0 ? lm : 0.0));
+    mu[v] = i > 0 ? coef * (l0 - lm) : 0.0;
   }
   const bool first = i == 0, last = i == N1 - 1;
+  double uown[NV], gw[NV];
+  loadu(i, uown);
 
   if constexpr (RECON) {
-    // own cell, and the ghost cell a segment-edge lane needs: lane 0 cell -2,
-    // lane 1 cell -1, last lane cell n1
-    double W[NV], Wx[NV];
-    loadw(i, W);
-    const int sx = i == 0 ? -2 : (i == 1 ? -1 : N1);
-    loadw(sx, Wx);
+    // own cell, and the cell beyond the segment an edge lane needs for the
+    // states of its face: lane 0 cell -2, lane 1 cell -1, last lane cell n1
+    double W[NV], Wx[NV], ux[NV];
+    to_prim(uown, gam, W);
+    loadu(i == 0 ? -2 : (i == 1 ? -1 : N1), ux);
+    to_prim(ux, gam, Wx);
     double Wm1[NV], Wm2[NV], Wp1[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const double a1 = shup<N1>(W[v], 1), a2 = shup<N1>(W[v], 2), p1 = shdn<N1>(W[v], 1);
-      const double gm = shdn<N1>(Wx[v], 1);  // lane 0 <- lane 1's ghost (cell -1)
+      const double gm = shdn<N1>(Wx[v], 1);  // lane 0 <- lane 1's cell -1
       Wm1[v] = first ? gm : a1;
       Wm2[v] = first ? Wx[v] : (i == 1 ? Wx[v] : a2);
       Wp1[v] = last ? Wx[v] : p1;
     }
-    double ga0[NV], gb0[NV], ga1[NV], gb1[NV], wl[NV], wr[NV];
+    double c0[NV], c1[NV], c2[NV], c3[NV];
+    plm_face_rev<0>(Wm2, Wm1, W, Wp1, mu, gam, c0, c1, c2, c3);
+    // the in-block parts of cell i: faces i-1 .. i+2 of this row; the
+    // parts reaching across a block face are in the side buffer
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      // slope of cell i-1 (left state of the face) and of cell i (right state)
-      const double s0 = mc_slope(Wm1[v] - Wm2[v], W[v] - Wm1[v]);
-      mc_branch(Wm1[v] - Wm2[v], W[v] - Wm1[v], ga0[v], gb0[v]);
-      const double s1 = mc_slope(W[v] - Wm1[v], Wp1[v] - W[v]);
-      mc_branch(W[v] - Wm1[v], Wp1[v] - W[v], ga1[v], gb1[v]);
-      wl[v] = Wm1[v] + 0.5 * s0;
-      wr[v] = W[v] - 0.5 * s1;
-    }
-    FState L{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
-    FState R{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
-    complete_state(L, gam, igm1);
-    complete_state(R, gam, igm1);
-    double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    hlle_rev<0>(L, R, gm1, mu, gL, gR);
-    double gl[NV] = {0, 0, 0, 0, 0}, gr[NV] = {0, 0, 0, 0, 0};
-    complete_state_rev(L, gam, igm1, gL, gl);
-    complete_state_rev(R, gam, igm1, gR, gr);
-    // contributions of face i to cells i-2 .. i+1, summed per cell across lanes
-    double own[NV], gm2[NV], gm1c[NV], gp3[NV], gp4[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double c0 = -gl[v] * 0.5 * ga0[v];
-      const double c1 = gl[v] * (1.0 + 0.5 * ga0[v] - 0.5 * gb0[v]) + gr[v] * 0.5 * ga1[v];
-      const double c2 = gl[v] * 0.5 * gb0[v] + gr[v] * (1.0 - 0.5 * ga1[v] + 0.5 * gb1[v]);
-      const double c3 = -gr[v] * 0.5 * gb1[v];
-      const double f1 = shdn<N1>(c1, 1), f0 = shdn<N1>(c0, 2), b3 = shup<N1>(c3, 1);
-      const double f0n = shdn<N1>(c0, 1);
-      // face n1 has no lane: its parts of cells n1-2 .. n1+1 come from the
-      // side buffer in the exchange pass
-      double a = c2 + (first ? 0.0 : b3);
+      const double f1 = shdn<N1>(c1[v], 1), f0 = shdn<N1>(c0[v], 2), b3 = shup<N1>(c3[v], 1);
+      double a = c2[v] + (first ? 0.0 : b3);
       a += last ? 0.0 : f1;
       a += (i >= N1 - 2) ? 0.0 : f0;
-      own[v] = a;
-      gm2[v] = c0;         // lane 0: cell -2
-      gm1c[v] = c1 + f0n;  // lane 0: cell -1
-      gp3[v] = c3;         // last lane: cell n1
-      gp4[v] = 0.0;        // last lane: cell n1+1
-    }
-    emit(i, own);
-    if (first) {
-      emit(-2, gm2);
-      emit(-1, gm1c);
-    }
-    if (last) {
-      emit(N1, gp3);
-      emit(N1 + 1, gp4);
+      gw[v] = a;
     }
   } else {
-    // donor cell: face i joins cells i-1 and i; each lane forms its cell's
-    // derived state, lane 0 also that of cell -1
+    // donor cell: face i joins cells i-1 and i
     double W[NV];
-    loadw(i, W);
+    to_prim(uown, gam, W);
     FState Q{W[0], W[1], W[2], W[3], W[4], 0, 0, 0};
     complete_state(Q, gam, igm1);
-    FState Qm;
-    {
-      const double m[8] = {shup<N1>(Q.r, 1),  shup<N1>(Q.v0, 1), shup<N1>(Q.v1, 1), shup<N1>(Q.v2, 1),
-                           shup<N1>(Q.p, 1),  shup<N1>(Q.sr, 1), shup<N1>(Q.c, 1),  shup<N1>(Q.h, 1)};
-      Qm = FState{m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7]};
-    }
-    FState Qg = Q;
-    if (first) {
-      double Wg[NV];
-      loadw(-1, Wg);
-      Qg = FState{Wg[0], Wg[1], Wg[2], Wg[3], Wg[4], 0, 0, 0};
-      complete_state(Qg, gam, igm1);
-      Qm = Qg;
-    }
+    const FState Qm{shup<N1>(Q.r, 1),  shup<N1>(Q.v0, 1), shup<N1>(Q.v1, 1), shup<N1>(Q.v2, 1),
+                    shup<N1>(Q.p, 1),  shup<N1>(Q.sr, 1), shup<N1>(Q.c, 1),  shup<N1>(Q.h, 1)};
     double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    hlle_rev<0>(Qm, Q, gm1, mu, gL, gR);
-    // cell i: right-state part of face i plus left-state part of face i+1
+    hlle_rev<0>(Qm, Q, gm1, mu, gL, gR);  // lane 0: mu = 0 (its Qm is its own state)
     double gQ[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double nb = shdn<N1>(gL[q], 1);
-      gQ[q] = gR[q] + (last ? 0.0 : nb);  // face n1's part: side buffer
+      gQ[q] = gR[q] + (last ? 0.0 : nb);
     }
-    double gw[NV] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gw[v] = 0.0;
     complete_state_rev(Q, gam, igm1, gQ, gw);
-    emit(i, gw);
-    const double zero5[NV] = {0, 0, 0, 0, 0};
-    if (first) {
-      double gg[NV] = {0, 0, 0, 0, 0};
-      complete_state_rev(Qg, gam, igm1, gL, gg);
-      emit(-1, gg);
-      emit(-2, zero5);
-    }
-    if (last) {
-      emit(N1, zero5);
-      emit(N1 + 1, zero5);
-    }
+  }
+  // parts across the block's x faces
+  if (i >= N1 - 2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gw[v] += xl[xside_at(nrows, (i - (N1 - 2)) * NV + v, row)];
+  }
+  if (i < 2 && nb27[12] >= 0) {
+    const int64_t lrow = (int64_t)nb27[12] * rpb + r;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gw[v] += xl[xside_at(nrows, (2 + i) * NV + v, lrow)];
+  }
+  // y and z parts of the cell and of its ghost copies in the y and z neighbours
+  const int64_t own = pbase + i;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    gw[v] += wyz[own + (int64_t)v * g.vstride] + wyz[wstride + own + (int64_t)v * g.vstride];
+  auto add_copy = [&](int dy, int dz) {
+    const int32_t nb = nb27[(dz + 1) * 9 + (dy + 1) * 3 + 1];
+    if (nb < 0) return;
+    const double* wd = wyz + (dy ? 0 : wstride);
+    const int64_t o = (int64_t)nb * g.bstride + pad_index(g, i, j - dy * g.n2, k - dz * g.n3);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gw[v] += wd[o + (int64_t)v * g.vstride];
+  };
+  if (j < NG) add_copy(-1, 0);
+  if (j >= g.n2 - NG) add_copy(1, 0);
+  if (k < NG) add_copy(0, -1);
+  if (k >= g.n3 - NG) add_copy(0, 1);
+  double gu[NV];
+  prim_rev(uown, gam, gw, gu);
+  const int64_t ao = abase + i;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double o = gu[v];
+    if (add0) o += add0[ao + (int64_t)v * ncell];
+    if (add1) o += add1[ao + (int64_t)v * ncell];
+    out[ao + (int64_t)v * ncell] = o;
   }
 }
 
-// One launch for the y pencils, the z pencils and the last x face of every
-// row (blockIdx.y = 0, 1, 2).
+// One launch for the y pencils, the z pencils and the x-face side buffer
+// (blockIdx.y = 0, 1, 2).
 template <int RECON>
 __global__ void __launch_bounds__(256) adj_pencils_kernel(const double* __restrict__ U,
                                                           const double* __restrict__ lam,
-                                                          double* __restrict__ wbar3, int64_t wstride,
+                                                          double* __restrict__ wyz, int64_t wstride,
                                                           double* __restrict__ xl, const BlockInfo* blocks,
                                                           const int32_t* nbr, int nblocks, Geom g,
                                                           const double* dtp, double beta) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   switch (blockIdx.y) {
     case 0:
-      adj_pencil<RECON, 1>(U, lam, wbar3 + wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
+      adj_pencil<RECON, 1>(U, lam, wyz, blocks, nbr, nblocks, g, dtp, beta, gid);
       break;
     case 1:
-      adj_pencil<RECON, 2>(U, lam, wbar3 + 2 * wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
+      adj_pencil<RECON, 2>(U, lam, wyz + wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
       break;
     default:
-      adj_xlast<RECON>(U, lam, xl, blocks, nbr, nblocks, g, dtp, beta, gid);
-  }
-}
-
-// Transposed ghost exchange and primitive-to-conserved adjoint, one thread
-// per active cell: the cell's own primitive adjoint plus those of its ghost
-// copies in the face neighbours, mapped through the primitive recovery at
-// the cell's state, plus optional addends.
-__global__ void __launch_bounds__(256) adj_exchange_kernel(const double* __restrict__ wbar,
-                                                           int64_t wstride,
-                                                           const double* __restrict__ U,
-                                                           const int32_t* __restrict__ nbr,
-                                                           const double* __restrict__ xl, Geom g,
-                                                           int64_t total, double* out,
-                                                           const double* add0, const double* add1) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= total) return;
-  const int64_t ncell = (int64_t)g.n1 * g.n2 * g.n3;
-  const int b = (int)(q / ncell);
-  const int c = (int)(q - (int64_t)b * ncell);
-  const int i = c % g.n1, j = (c / g.n1) % g.n2, k = c / (g.n1 * g.n2);
-  const int32_t* nb27 = nbr + (int64_t)b * 27;
-  double gw[NV];
-  const int64_t own = (int64_t)b * g.bstride + pad_index(g, i, j, k);
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
-    gw[v] = (wbar[own + (int64_t)v * g.vstride] + wbar[wstride + own + (int64_t)v * g.vstride]) +
-            wbar[2 * wstride + own + (int64_t)v * g.vstride];
-  auto add_copy = [&](int dx, int dy, int dz) {
-    const int32_t nb = nb27[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
-    if (nb < 0) return;
-    const double* wd = wbar + (dx ? 0 : (dy ? wstride : 2 * wstride));
-    const int64_t o = (int64_t)nb * g.bstride + pad_index(g, i - dx * g.n1, j - dy * g.n2, k - dz * g.n3);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) gw[v] += wd[o + (int64_t)v * g.vstride];
-  };
-  if (i < NG) add_copy(-1, 0, 0);
-  if (i >= g.n1 - NG) add_copy(1, 0, 0);
-  if (j < NG) add_copy(0, -1, 0);
-  if (j >= g.n2 - NG) add_copy(0, 1, 0);
-  if (k < NG) add_copy(0, 0, -1);
-  if (k >= g.n3 - NG) add_copy(0, 0, 1);
-  // the last x face of a row (side buffer): cells n1-2, n1-1 of this row, and
-  // through the x-lower neighbour's row, cells n1, n1+1 beyond it (= 0, 1 here)
-  const int64_t rpb = (int64_t)g.n2 * g.n3, nrows = rpb * (total / ncell);
-  if (i >= g.n1 - 2) {
-    const int64_t row = (int64_t)b * rpb + (int64_t)k * g.n2 + j;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) gw[v] += xl[xlast_at(nrows, (i - (g.n1 - 2)) * NV + v, row)];
-  }
-  if (i < 2 && nb27[12] >= 0) {
-    const int64_t row = (int64_t)nb27[12] * rpb + (int64_t)k * g.n2 + j;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) gw[v] += xl[xlast_at(nrows, (2 + i) * NV + v, row)];
-  }
-  double u[NV], gu[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = U[own + (int64_t)v * g.vstride];
-  prim_rev(u, g.gamma, gw, gu);
-  const int64_t ao = (int64_t)b * NV * ncell + c;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double r = gu[v];
-    if (add0) r += add0[ao + v * ncell];
-    if (add1) r += add1[ao + v * ncell];
-    out[ao + v * ncell] = r;
+      adj_xside<RECON>(U, lam, xl, blocks, nbr, nblocks, g, dtp, beta, gid);
   }
 }
 
 template <int RECON>
-static void launch_xrow(int n1, dim3 grid, hipStream_t s, const double* U, const double* lam, double* wx,
-                        const BlockInfo* blocks, const int32_t* nbr, int nblocks,
-                        const Geom& g, const double* dtp, double beta) {
+static void launch_xrow(int n1, dim3 grid, hipStream_t s, const double* U, const double* lam, const double* wyz,
+                        int64_t wstride, const double* xl, const BlockInfo* blocks, const int32_t* nbr,
+                        int nblocks, const Geom& g, const double* dtp, double beta, double* out,
+                        const double* add0, const double* add1) {
+#define PKH_XROW(N)                                                                                            \
+  hipLaunchKernelGGL((adj_xrow_kernel<RECON, N>), grid, dim3(256), 0, s, U, lam, wyz, wstride, xl, blocks, nbr, \
+                     nblocks, g, dtp, beta, out, add0, add1)
   switch (n1) {
     case 8:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 8>), grid, dim3(256), 0, s, U, lam, wx, blocks, nbr, nblocks, g,
-                         dtp, beta);
+      PKH_XROW(8);
       break;
     case 16:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 16>), grid, dim3(256), 0, s, U, lam, wx, blocks, nbr, nblocks, g,
-                         dtp, beta);
+      PKH_XROW(16);
       break;
     case 32:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 32>), grid, dim3(256), 0, s, U, lam, wx, blocks, nbr, nblocks, g,
-                         dtp, beta);
+      PKH_XROW(32);
       break;
     default:
-      hipLaunchKernelGGL((adj_xrow_kernel<RECON, 64>), grid, dim3(256), 0, s, U, lam, wx, blocks, nbr, nblocks, g,
-                         dtp, beta);
+      PKH_XROW(64);
   }
+#undef PKH_XROW
 }
 
 bool adj_xrow_supported(int n1) { return n1 == 8 || n1 == 16 || n1 == 32 || n1 == 64; }
 
-hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wbar3, double* xlast,
+hipError_t launch_adj_stage(int recon, const double* U, const double* lam, double* wyz, double* xside,
                             const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                             const int32_t* nbr, const double* dtp, double beta, double* out,
                             const double* add0, const double* add1, hipStream_t s) {
-  // x: the rows face-parallel (this launch) and the last face of every row
-  // (with the pencils); y and z: pencils. The x ghost cells of the stage
-  // kernels' outputs are not kept (the x kernels read the neighbours' active
-  // cells), so the row path is the only x path.
-  if (!adj_xrow_supported(g.n1) || xlast == nullptr) return hipErrorInvalidValue;
+  // y and z pencils with the x-face side buffer, then the rows (x and the
+  // closing of every cell)
+  if (!adj_xrow_supported(g.n1) || xside == nullptr) return hipErrorInvalidValue;
   const int64_t nrows = (int64_t)nblocks * g.n2 * g.n3;
   const int64_t npen = std::max(std::max((int64_t)nblocks * g.n1 * g.n3, (int64_t)nblocks * g.n1 * g.n2), nrows);
   const int64_t wstride = (int64_t)nblocks * g.bstride;
   const dim3 gr((unsigned)((nrows * g.n1 + 255) / 256)), gp((unsigned)((npen + 255) / 256), 3);
   if (recon) {
-    hipLaunchKernelGGL(adj_pencils_kernel<1>, gp, dim3(256), 0, s, U, lam, wbar3, wstride, xlast, blocks, nbr,
+    hipLaunchKernelGGL(adj_pencils_kernel<1>, gp, dim3(256), 0, s, U, lam, wyz, wstride, xside, blocks, nbr,
                        nblocks, g, dtp, beta);
-    launch_xrow<1>(g.n1, gr, s, U, lam, wbar3, blocks, nbr, nblocks, g, dtp, beta);
+    launch_xrow<1>(g.n1, gr, s, U, lam, wyz, wstride, xside, blocks, nbr, nblocks, g, dtp, beta, out, add0, add1);
   } else {
-    hipLaunchKernelGGL(adj_pencils_kernel<0>, gp, dim3(256), 0, s, U, lam, wbar3, wstride, xlast, blocks, nbr,
+    hipLaunchKernelGGL(adj_pencils_kernel<0>, gp, dim3(256), 0, s, U, lam, wyz, wstride, xside, blocks, nbr,
                        nblocks, g, dtp, beta);
-    launch_xrow<0>(g.n1, gr, s, U, lam, wbar3, blocks, nbr, nblocks, g, dtp, beta);
+    launch_xrow<0>(g.n1, gr, s, U, lam, wyz, wstride, xside, blocks, nbr, nblocks, g, dtp, beta, out, add0, add1);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t total = (int64_t)nblocks * g.n1 * g.n2 * g.n3;
-  hipLaunchKernelGGL(adj_exchange_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, wbar3, wstride,
-                     U, nbr, xlast, g, total, out, add0, add1);
   return hipGetLastError();
 }
 

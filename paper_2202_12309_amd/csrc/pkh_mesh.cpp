@@ -974,8 +974,8 @@ struct pkh_tape {
   int32_t dts_cap = 0;
   std::vector<double*> S;        // recomputed ghost-filled U^n, K + 1 of them
   std::vector<double*> Us;       // recomputed ghost-filled U*, K of them
-  double* wbar = nullptr;        // padded primitive-adjoint scratch, one per direction
-  double* xlast = nullptr;       // last x-face of every row, 20 doubles per row
+  double* wbar = nullptr;        // padded primitive-adjoint scratch for y and z
+  double* xlast = nullptr;       // parts across x faces, 20 doubles per row
   double* lam[3] = {nullptr, nullptr, nullptr};  // active-layout adjoints
   DevTime* d_time = nullptr;     // clock for recomputation (dt from the record)
 };
@@ -1061,7 +1061,7 @@ int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
     ok = t->Us.back() != nullptr;
   }
   if (ok) {
-    t->wbar = (double*)m->dalloc(3 * pb);
+    t->wbar = (double*)m->dalloc(2 * pb);
     t->xlast = (double*)m->dalloc((size_t)m->nb() * m->g.n2 * m->g.n3 * 20 * sizeof(double));
     for (auto& l : t->lam) l = (double*)m->dalloc(active_bytes(m));
     t->d_time = (DevTime*)m->dalloc(sizeof(DevTime));
