@@ -37,11 +37,11 @@ __device__ __forceinline__ int64_t pad_index(const Geom& g, int i, int j, int k)
   return ((int64_t)(k + NG) * g.p2 + (j + NG)) * g.p1 + (i + NG);
 }
 
-// Composite value at level L, global cell J (any integers; wrapped here):
-// leaf value at level L; restriction of the level-(L+1) leaves; or, while
-// regridding, the containing coarser cell (injection).
-__device__ double comp_val(const double* u, const BlockInfo* blocks, const LevelMaps& M,
-                           const Geom& g, int L, int J0, int J1, int J2, int v, int* err) {
+// Composite value at level L, global cell J (any integers; wrapped here),
+// all five variables: leaf value at level L; restriction of the level-(L+1)
+// leaves; or, while regridding, the containing coarser cell (injection).
+__device__ void comp_val(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L,
+                         int J0, int J1, int J2, double out[NV], int* err) {
   const int n[3] = {g.n1, g.n2, g.n3};
   int J[3] = {J0, J1, J2}, b[3];
 #pragma unroll
@@ -50,56 +50,76 @@ __device__ double comp_val(const double* u, const BlockInfo* blocks, const Level
     b[d] = J[d] / n[d];
   }
   int32_t id = leaf_at(M, L, b[0], b[1], b[2]);
-  if (id >= 0)
-    return u[(int64_t)id * g.bstride + v * g.vstride +
-             pad_index(g, J[0] - b[0] * n[0], J[1] - b[1] * n[1], J[2] - b[2] * n[2])];
+  if (id >= 0) {
+    const double* c = u + (int64_t)id * g.bstride +
+                      pad_index(g, J[0] - b[0] * n[0], J[1] - b[1] * n[1], J[2] - b[2] * n[2]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = c[v * g.vstride];
+    return;
+  }
   for (int Lc = L - 1; Lc >= 0; --Lc) {
     const int sh = L - Lc;
     id = leaf_at(M, Lc, b[0] >> sh, b[1] >> sh, b[2] >> sh);
     if (id >= 0) {
       const BlockInfo bc = blocks[id];
-      return u[(int64_t)id * g.bstride + v * g.vstride +
-               pad_index(g, (J[0] >> sh) - bc.lx * n[0], (J[1] >> sh) - bc.ly * n[1],
-                         (J[2] >> sh) - bc.lz * n[2])];
+      const double* c = u + (int64_t)id * g.bstride +
+                        pad_index(g, (J[0] >> sh) - bc.lx * n[0], (J[1] >> sh) - bc.ly * n[1],
+                                  (J[2] >> sh) - bc.lz * n[2]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] = c[v * g.vstride];
+      return;
     }
   }
   if (L + 1 > M.maxl) {
     *err = 1;
-    return 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+    return;
   }
-  double f[8];
+  const double* fc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int F0 = 2 * J[0] + (c & 1), F1 = 2 * J[1] + ((c >> 1) & 1), F2 = 2 * J[2] + ((c >> 2) & 1);
     const int32_t fid = leaf_at(M, L + 1, F0 / n[0], F1 / n[1], F2 / n[2]);
     if (fid < 0) {
       *err = 1;
-      return 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] = 0.0;
+      return;
     }
     const BlockInfo bf = blocks[fid];
-    f[c] = u[(int64_t)fid * g.bstride + v * g.vstride +
-             pad_index(g, F0 - bf.lx * n[0], F1 - bf.ly * n[1], F2 - bf.lz * n[2])];
+    fc[c] = u + (int64_t)fid * g.bstride + pad_index(g, F0 - bf.lx * n[0], F1 - bf.ly * n[1], F2 - bf.lz * n[2]);
   }
-  return 0.125 * (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])));
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int64_t o = (int64_t)v * g.vstride;
+    out[v] = 0.125 * (((fc[0][o] + fc[1][o]) + (fc[2][o] + fc[3][o])) +
+                      ((fc[4][o] + fc[5][o]) + (fc[6][o] + fc[7][o])));
+  }
 }
 
 // Linear prolongation to fine cell F (level L) from the composite field at
-// level L-1 with minmod slopes; the fine centre sits a quarter coarse width
-// from the coarse centre along each axis.
-__device__ double prolong_val(const double* u, const BlockInfo* blocks, const LevelMaps& M,
-                              const Geom& g, int L, int F0, int F1, int F2, int v, int* err) {
-  const int I0 = F0 >> 1, I1 = F1 >> 1, I2 = F2 >> 1;  // F >= 0 here
-  const double c0 = comp_val(u, blocks, M, g, L - 1, I0, I1, I2, v, err);
-  const double s0 = minmod(c0 - comp_val(u, blocks, M, g, L - 1, I0 - 1, I1, I2, v, err),
-                           comp_val(u, blocks, M, g, L - 1, I0 + 1, I1, I2, v, err) - c0);
-  const double s1 = minmod(c0 - comp_val(u, blocks, M, g, L - 1, I0, I1 - 1, I2, v, err),
-                           comp_val(u, blocks, M, g, L - 1, I0, I1 + 1, I2, v, err) - c0);
-  const double s2 = minmod(c0 - comp_val(u, blocks, M, g, L - 1, I0, I1, I2 - 1, v, err),
-                           comp_val(u, blocks, M, g, L - 1, I0, I1, I2 + 1, v, err) - c0);
-  const double t0 = (F0 & 1) ? s0 : -s0;
-  const double t1 = (F1 & 1) ? s1 : -s1;
-  const double t2 = (F2 & 1) ? s2 : -s2;
-  return c0 + 0.25 * ((t0 + t1) + t2);
+// level L-1 with minmod slopes, all five variables; the fine centre sits a
+// quarter coarse width from the coarse centre along each axis.
+__device__ void prolong_val(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L,
+                            int F0, int F1, int F2, double out[NV], int* err) {
+  const int I[3] = {F0 >> 1, F1 >> 1, F2 >> 1};  // F >= 0 here
+  const int odd[3] = {F0 & 1, F1 & 1, F2 & 1};
+  double c0[NV], t[3][NV];
+  comp_val(u, blocks, M, g, L - 1, I[0], I[1], I[2], c0, err);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double m[NV], q[NV];
+    comp_val(u, blocks, M, g, L - 1, I[0] - (d == 0), I[1] - (d == 1), I[2] - (d == 2), m, err);
+    comp_val(u, blocks, M, g, L - 1, I[0] + (d == 0), I[1] + (d == 1), I[2] + (d == 2), q, err);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double sd = minmod(c0[v] - m[v], q[v] - c0[v]);
+      t[d][v] = odd[d] ? sd : -sd;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = c0[v] + 0.25 * ((t[0][v] + t[1][v]) + t[2][v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,13 +178,13 @@ __device__ __forceinline__ void fill_cell(double* u, const BlockInfo* blocks, co
     return;
   }
   int err = 0;
-  if (L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0) {
-    for (int v = 0; v < NV; ++v)
-      dst[v * g.vstride] = prolong_val(u, blocks, M, g, L, J[0], J[1], J[2], v, &err);
-  } else {
-    for (int v = 0; v < NV; ++v)
-      dst[v * g.vstride] = comp_val(u, blocks, M, g, L, J[0], J[1], J[2], v, &err);
-  }
+  double val[NV];
+  if (L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0)
+    prolong_val(u, blocks, M, g, L, J[0], J[1], J[2], val, &err);
+  else
+    comp_val(u, blocks, M, g, L, J[0], J[1], J[2], val, &err);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dst[v * g.vstride] = val[v];
   if (err) atomicOr(&tm->err, 2);
 }
 
@@ -552,17 +572,17 @@ __global__ void __launch_bounds__(256) regrid_kernel(double* unew, const BlockIn
   double* dst = unew + (int64_t)r * g.bstride + pad_index(g, i, j, k);
   const int J0 = bn.lx * g.n1 + i, J1 = bn.ly * g.n2 + j, J2 = bn.lz * g.n3 + k;
   int err = 0;
-  for (int v = 0; v < NV; ++v) {
-    double val;
-    if (kd == 0) {
-      val = uold[(int64_t)s * g.bstride + v * g.vstride + pad_index(g, i, j, k)];
-    } else if (kd == 1) {
-      val = prolong_val(uold, bold, M, g, bn.level, J0, J1, J2, v, &err);
-    } else {
-      val = comp_val(uold, bold, M, g, bn.level, J0, J1, J2, v, &err);
-    }
-    dst[v * g.vstride] = val;
+  double val[NV];
+  if (kd == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) val[v] = uold[(int64_t)s * g.bstride + v * g.vstride + pad_index(g, i, j, k)];
+  } else if (kd == 1) {
+    prolong_val(uold, bold, M, g, bn.level, J0, J1, J2, val, &err);
+  } else {
+    comp_val(uold, bold, M, g, bn.level, J0, J1, J2, val, &err);
   }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dst[v * g.vstride] = val[v];
   if (err) atomicOr(&tm->err, 2);
 }
 
