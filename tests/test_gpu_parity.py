@@ -138,6 +138,36 @@ def test_graph_replay_equals_eager():
         assert a.time() == b.time()
 
 
+def test_graph_replay_equals_eager_two_levels_with_regrid():
+    """Multilevel cycle (flux correction and level-jump face fill in the
+    captured graph), replayed several times, then a regrid (the graph is
+    rebuilt for the new mesh) and more replays: bitwise equal to eager."""
+    print_case("graph replay vs eager, two levels, regrid")
+    from paper_2202_12309_amd.binding import Mesh
+    nrb, n = (4, 4, 4), (8, 8, 8)
+    lv = inputs.sphere_refined_leaves(nrb, radius=0.3)
+    a = Mesh((32, 32, 32), n, lv, max_level=1)
+    b = Mesh((32, 32, 32), n, lv, max_level=1, graph=True)
+    U0 = inputs.blast(a.leaves(), n, nrb)
+    a.upload(U0)
+    b.upload(U0)
+    for rep in range(3):
+        a.step(3)
+        b.step(3)
+        assert np.array_equal(a.download(), b.download()), rep
+        assert a.time() == b.time()
+    fa, _ = a.flag_pressure_jump(0.1, 0.02)
+    fb, _ = b.flag_pressure_jump(0.1, 0.02)
+    assert np.array_equal(fa, fb)
+    a.regrid()
+    b.regrid()
+    assert np.array_equal(a.leaves(), b.leaves())
+    for rep in range(2):
+        a.step(3)
+        b.step(3)
+        assert np.array_equal(a.download(), b.download()), rep
+
+
 def test_deterministic_repeat():
     print_case("determinism")
     from paper_2202_12309_amd.binding import Mesh
