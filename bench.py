@@ -215,6 +215,44 @@ def amr_leg(cycles=200, regrid_every=10):
             "leaves_start": leaves0, "leaves_after_each_regrid": counts, "sim_time": t}
 
 
+def deep_amr_leg(cycles=10):
+    """The paper's multilevel mesh: 256^3 root grid in blocks of 32^3, a
+    centred cube of side 0.4 refined to level 3 (296, 1216, 1352 and 21952
+    leaves on levels 0-3: 24,816 blocks, 813M zones), a spherical blast
+    inside the refined cube, static mesh. Zone-cycles/s over the timed
+    cycles and the per-kernel split (stage kernels, level-jump face fill,
+    flux correction)."""
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+    n, nrb = (32, 32, 32), (8, 8, 8)
+    lv = inputs.cube_refined_leaves(nrb)
+    mesh = Mesh((256,) * 3, n, lv, max_level=3)
+    U0 = inputs.blast(mesh.leaves(), n, nrb)
+    mesh.upload(U0)
+    del U0
+    mesh.step(2)  # warm-up
+    mesh.sync()
+    mesh.kernel_timing(Mesh.KT_PREDICTOR | Mesh.KT_CORRECTOR | Mesh.KT_FILL | Mesh.KT_FLUXCORR)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(mesh.stream)
+    mesh.step(cycles)
+    ev1.record(mesh.stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kt = mesh.kernel_times()
+    mesh.sync()
+    cells = len(lv) * n[0] * n[1] * n[2]
+    counts = [int((lv[:, 0] == L).sum()) for L in range(4)]
+    out = {"workload": "paper multilevel mesh: 256^3 root, 32^3 blocks, 0.4 cube to level 3, blast",
+           "leaves_per_level": counts, "cells": cells, "cycles_timed": cycles,
+           "ms_per_cycle": round(ms / cycles, 4), "zone_cycles_per_s": cells * cycles / (ms / 1e3),
+           "kernel_ms_per_cycle": {k: round(v[0] / cycles, 4) for k, v in kt.items() if v[1]}}
+    mesh.close()
+    return out
+
+
 def main_leg(args):
     """The 256^3 hydro cycle: zone-cycles/s, stage-kernel times and the
     corrector's roofline."""
@@ -305,6 +343,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--deep-amr", action="store_true",
+                    help="also run the paper's four-level mesh (813M zones, ~130 GB of HBM)")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the 256^3 leg (for profiling the other legs alone)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -334,7 +374,7 @@ def main():
                "config": {"workload": "main 256^3 leg skipped"}, "roofline": None}
     else:
         out = main_leg(args)
-    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None})
+    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None, "deep_amr": None})
     if not args.no_adjoint:
         adj = adjoint_ratio()
         out["adjoint"] = adj
@@ -344,6 +384,9 @@ def main():
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batch"] = batch_leg()
+    if args.deep_amr:
+        torch.cuda.empty_cache()
+        out["deep_amr"] = deep_amr_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(blk)
     print(json.dumps(out))

@@ -74,6 +74,68 @@ def sphere_refined_leaves(nrb, center=(0.5, 0.5, 0.5), radius=0.25, xmin=(0, 0, 
     return np.array(out, dtype=np.int32)
 
 
+def cube_refined_leaves(nrb, lo=0.3, hi=0.7, max_level=3):
+    """Leaves of a mesh on the unit cube with nrb level-0 blocks whose
+    cubic region (lo, hi)^3 is refined to max_level: level by level, every
+    leaf whose open extent meets the open cube is split into 8 children,
+    then leaves are refined until every leaf's face, edge and corner
+    neighbours are at most one level coarser (periodic). With 8^3 root
+    blocks, the 0.4-side cube centred in the box and three levels this
+    gives the paper's multilevel mesh (296, 1216, 1352, 21952 blocks on
+    levels 0-3). Returns [n][4] (level, lx, ly, lz), unordered."""
+    leaves = {(0, x, y, z) for z in range(nrb[2]) for y in range(nrb[1]) for x in range(nrb[0])}
+
+    def nbl(L, d):
+        return nrb[d] << L
+
+    def cover(L, x, y, z):
+        for Lc in range(L, -1, -1):
+            sh = L - Lc
+            key = (Lc, x >> sh, y >> sh, z >> sh)
+            if key in leaves:
+                return key
+        return None
+
+    def split(leaf):
+        L, x, y, z = leaf
+        leaves.discard(leaf)
+        for c in range(8):
+            leaves.add((L + 1, 2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + ((c >> 2) & 1)))
+
+    def meets(leaf):
+        L, x, y, z = leaf
+        for d, c in enumerate((x, y, z)):
+            w = 1.0 / nbl(L, d)
+            if not (c * w < hi and (c + 1) * w > lo):
+                return False
+        return True
+
+    def balance():
+        changed = True
+        while changed:
+            changed = False
+            for leaf in sorted(leaves, reverse=True):
+                if leaf not in leaves or leaf[0] < 2:
+                    continue
+                L, x, y, z = leaf
+                for dz in (-1, 0, 1):
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            if not (dx or dy or dz):
+                                continue
+                            q = (L, (x + dx) % nbl(L, 0), (y + dy) % nbl(L, 1), (z + dz) % nbl(L, 2))
+                            c = cover(*q)
+                            if c is not None and c[0] < L - 1:
+                                split(c)
+                                changed = True
+
+    for L in range(max_level):
+        for leaf in [lf for lf in leaves if lf[0] == L and meets(lf)]:
+            split(leaf)
+        balance()
+    return np.array(sorted(leaves), dtype=np.int32)
+
+
 def cell_centers(leaf, n, nrb, xmin=(0.0, 0.0, 0.0), xmax=(1.0, 1.0, 1.0)):
     """Cell-centre coordinates (x, y, z), each shaped [n3][n2][n1]."""
     lev, lx, ly, lz = (int(v) for v in leaf)
@@ -195,7 +257,21 @@ def blast(leaves, n, nrb, p_in=100.0, p_out=0.1, r=0.1, rho0=1.0, center=(0.5, 0
     """Spherical blast: uniform density at rest, pressure p_in where the cell
     centre lies within r of the centre, else p_out."""
     U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    # the outer state everywhere (as _to_conserved gives it), then the leaves
+    # that can hold a cell centre inside the ball cell by cell
+    U[:, 0] = rho0
+    U[:, 1:4] = 0.0
+    U[:, 4] = p_out / (gamma - 1.0) + 0.5 * rho0 * 0.0
     for b, lf in enumerate(leaves):
+        lev = int(lf[0])
+        d2 = 0.0
+        for d in range(3):
+            w = (xmax[d] - xmin[d]) / (nrb[d] << lev)
+            lo = xmin[d] + int(lf[1 + d]) * w
+            near = min(max(center[d], lo), lo + w)
+            d2 += (near - center[d]) ** 2
+        if d2 >= r * r:
+            continue
         x, y, z = cell_centers(lf, n, nrb, xmin, xmax)
         d2 = (x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2
         p = np.where(d2 < r * r, p_in, p_out)

@@ -313,3 +313,19 @@ def test_pressure_jump_step_and_flags():
         assert eta[b] == want  # every leaf touches x = 1 or the periodic seam
     flags = np.where(eta > 0.1, 1, np.where(eta < 0.02, -1, 0))
     assert np.all(flags == 1)
+
+
+def test_paper_multilevel_mesh_block_counts():
+    """The leaf generator reproduces the paper's multilevel mesh (the cube
+    centred in the box, 2:1 balance over face, edge and corner neighbours)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "multilevel_mesh_blocks.json")))
+    nrb = (g["root_cells"] // g["block"],) * 3
+    half = g["cube_side"] / 2
+    lv = inputs.cube_refined_leaves(nrb, 0.5 - half, 0.5 + half, g["max_level"])
+    counts = [int((lv[:, 0] == L).sum()) for L in range(g["max_level"] + 1)]
+    assert counts == g["blocks_per_level"]
+    # a valid, 2:1-balanced tiling the oracle accepts (with blocks of 8^3)
+    m = OracleMesh((8, 8, 8), nrb, lv, max_level=g["max_level"])
+    assert m.nleaves == len(lv)
