@@ -343,8 +343,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
-    ap.add_argument("--deep-amr", action="store_true",
-                    help="also run the paper's four-level mesh (813M zones, ~130 GB of HBM)")
+    ap.add_argument("--no-deep-amr", action="store_true",
+                    help="skip the paper's four-level mesh (813M zones, ~130 GB of HBM)")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the 256^3 leg (for profiling the other legs alone)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -384,7 +384,7 @@ def main():
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batch"] = batch_leg()
-    if args.deep_amr:
+    if not args.no_deep_amr:
         torch.cuda.empty_cache()
         out["deep_amr"] = deep_amr_leg()
     if not args.no_cpu_baseline:
