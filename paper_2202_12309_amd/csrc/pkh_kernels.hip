@@ -200,24 +200,114 @@ __global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* b
   fill_cell(u, blocks, g, M, tm, b, i, j, k, skip_same);
 }
 
+// Restriction at level L, global cell J (in range): the 8 level-(L+1)
+// cells below it lie in one fine leaf (blocks have even edges), so the leaf
+// is looked up once; the sum is paired as in comp_val.
+__device__ __forceinline__ void restrict_val(const double* u, const BlockInfo* blocks, const LevelMaps& M,
+                                             const Geom& g, int L, const int J[3], double out[NV], int* err) {
+  const int F[3] = {2 * J[0], 2 * J[1], 2 * J[2]};
+  const int32_t fid = leaf_at(M, L + 1, F[0] / g.n1, F[1] / g.n2, F[2] / g.n3);
+  if (fid < 0) {
+    *err = 1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+    return;
+  }
+  const BlockInfo bf = blocks[fid];
+  const double* f = u + (int64_t)fid * g.bstride +
+                    pad_index(g, F[0] - bf.lx * g.n1, F[1] - bf.ly * g.n2, F[2] - bf.lz * g.n3);
+  const int64_t sx = 1, sy = g.p1, sz = (int64_t)g.p1 * g.p2;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double* c = f + (int64_t)v * g.vstride;
+    out[v] = 0.125 * (((c[0] + c[sx]) + (c[sy] + c[sy + sx])) + ((c[sz] + c[sz + sx]) + (c[sz + sy] + c[sz + sy + sx])));
+  }
+}
+
 // The face regions (width 2, active transverse extent) listed in jf as
 // (leaf, face) pairs: the faces whose neighbour is on another level, the
-// only ghost cells the stage kernels read.
+// only ghost cells the stage kernels read. The region across one face is
+// one block of the leaf's level, so a face is either wholly inside a
+// coarser leaf or wholly refined. Coarser: the 2-deep slab is one coarse
+// cell deep and aligned to coarse cells; eight lanes share one coarse
+// cell: lane l forms the composite value of stencil point l (the cell, then
+// its -x, +x, -y, +y, -z, +z neighbours; lane 7 repeats the cell), the
+// lanes swap them by shuffles, and lane o writes fine child o. Refined: one
+// thread per ghost cell, restriction of its 8 fine cells.
 __global__ void __launch_bounds__(256) fill_faces_kernel(double* u, const BlockInfo* blocks, Geom g, LevelMaps M,
                                                          DevTime* tm, const int32_t* __restrict__ jf) {
   const int2 rec = reinterpret_cast<const int2*>(jf)[blockIdx.y];
   const int b = rec.x, d = rec.y >> 1, hi = rec.y & 1;
+  const BlockInfo bi = blocks[b];
+  const int L = bi.level;
   const int n[3] = {g.n1, g.n2, g.n3};
   const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-  const int area = n[t1] * n[t2];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= 2 * area) return;
-  const int s = q / area, r = q - s * area;
-  int c[3];
-  c[t1] = r % n[t1];
-  c[t2] = r / n[t1];
-  c[d] = hi ? n[d] + s : s - NG;
-  fill_cell(u, blocks, g, M, tm, b, c[0], c[1], c[2], 1);
+  int bl[3] = {bi.lx, bi.ly, bi.lz};
+  bl[d] = wrap_i(bl[d] + (hi ? 1 : -1), g.nrb[d] << L);
+  const bool coarser = L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0;
+  double* ub = u + (int64_t)b * g.bstride;
+  int err = 0;
+  if (coarser) {
+    // Uniform per workgroup (one face per blockIdx.y): whole 8-lane groups
+    // leave together, so the shuffles below see only live groups.
+    const int m1 = n[t1] >> 1, m2 = n[t2] >> 1;
+    const int cq = q >> 3, l = q & 7;
+    if (cq >= m1 * m2) return;
+    int c[3];  // first fine ghost cell of this group's 2x2x2 children, leaf coordinates
+    c[t1] = 2 * (cq % m1);
+    c[t2] = 2 * (cq / m1);
+    c[d] = hi ? n[d] : -NG;
+    int I[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int lo = e == 0 ? bi.lx : (e == 1 ? bi.ly : bi.lz);
+      I[e] = wrap_i(lo * n[e] + c[e], (g.nrb[e] * n[e]) << L) >> 1;
+    }
+    const int se = (l - 1) >> 1, sg = (l & 1) ? -1 : 1;  // lanes 1..6: axis and side
+    const bool ctr = l == 0 || l == 7;
+    double val[NV];
+    comp_val(u, blocks, M, g, L - 1, I[0] + (!ctr && se == 0 ? sg : 0), I[1] + (!ctr && se == 1 ? sg : 0),
+             I[2] + (!ctr && se == 2 ? sg : 0), val, &err);
+    const int base = threadIdx.x & ~7 & 63;
+    const int o = l;
+    double outv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double c0 = __shfl(val[v], base, 64);
+      double t[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const double mv = __shfl(val[v], base + 1 + 2 * e, 64);
+        const double pv = __shfl(val[v], base + 2 + 2 * e, 64);
+        const double sd = minmod(c0 - mv, pv - c0);
+        t[e] = ((o >> e) & 1) ? sd : -sd;
+      }
+      outv[v] = c0 + 0.25 * ((t[0] + t[1]) + t[2]);
+    }
+    // c[e] is even in every direction, so child o sits on the odd side
+    // along e exactly when bit e of o is set.
+    double* dst = ub + pad_index(g, c[0] + (o & 1), c[1] + ((o >> 1) & 1), c[2] + ((o >> 2) & 1));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dst[v * g.vstride] = outv[v];
+  } else {
+    const int area = n[t1] * n[t2];
+    if (q >= 2 * area) return;
+    const int s = q / area, r = q - s * area;
+    int c[3];
+    c[t1] = r % n[t1];
+    c[t2] = r / n[t1];
+    c[d] = hi ? n[d] + s : s - NG;
+    const int J[3] = {wrap_i(bi.lx * n[0] + c[0], (g.nrb[0] * n[0]) << L),
+                      wrap_i(bi.ly * n[1] + c[1], (g.nrb[1] * n[1]) << L),
+                      wrap_i(bi.lz * n[2] + c[2], (g.nrb[2] * n[2]) << L)};
+    double val[NV];
+    restrict_val(u, blocks, M, g, L, J, val, &err);
+    double* dst = ub + pad_index(g, c[0], c[1], c[2]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dst[v * g.vstride] = val[v];
+  }
+  if (err) atomicOr(&tm->err, 2);
 }
 
 hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
@@ -238,13 +328,44 @@ hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, cons
   return hipGetLastError();
 }
 
+// q-th cell of the outer layer of a block (a coordinate at 0 or n - 1):
+// the two z planes, then for each inner plane its two y rows and the two
+// x ends of each inner row. False past the last one.
+__device__ __forceinline__ bool shell_coord(int q, const Geom& g, int& i, int& j, int& k) {
+  const int plane = g.n1 * g.n2;
+  if (q < 0) return false;
+  if (q < 2 * plane) {
+    const bool top = q >= plane;
+    k = top ? g.n3 - 1 : 0;
+    const int r = top ? q - plane : q;
+    j = r / g.n1;
+    i = r - j * g.n1;
+    return true;
+  }
+  q -= 2 * plane;
+  const int per = 2 * g.n1 + 2 * (g.n2 - 2);
+  if (q >= (g.n3 - 2) * per) return false;
+  k = 1 + q / per;
+  int r = q - (k - 1) * per;
+  if (r < 2 * g.n1) {
+    const bool top = r >= g.n1;
+    j = top ? g.n2 - 1 : 0;
+    i = top ? r - g.n1 : r;
+    return true;
+  }
+  r -= 2 * g.n1;
+  j = 1 + (r >> 1);
+  i = (r & 1) ? g.n1 - 1 : 0;
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // Flux correction as reflux: on each coarse face bordering finer leaves the
 // coarse flux is replaced by the area mean of the 4 fine fluxes,
-// U += +-beta*dt/dx * (F_own - F_fine). One thread per cell of a coarse
-// block that has such faces; the cell applies all of its faces in x, y, z
-// order, then (corrector stage) contributes to the CFL reduction the stage
-// kernel skipped for it.
+// U += +-beta*dt/dx * (F_own - F_fine). One thread per outer-layer cell of
+// a coarse block that has such faces; a cell on one of them applies all of
+// its faces in x, y, z order, then (corrector stage) contributes to the CFL
+// reduction the stage kernel skipped for it.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const BlockInfo* blocks,
@@ -257,12 +378,14 @@ __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const Bloc
   const int c = blockIdx.y;
   const int b = cblocks[c];
   const BlockInfo bi = blocks[b];
-  const int ncell = g.n1 * g.n2 * g.n3;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   double smax = 0.0;
   bool bad = false;
-  if (q < ncell) {
-    const int i = q % g.n1, j = (q / g.n1) % g.n2, k = q / (g.n1 * g.n2);
+  int i, j, k;
+  if (shell_coord(q, g, i, j, k) &&
+      ((((bi.finer_mask >> XLO) & 1) && i == 0) || (((bi.finer_mask >> XHI) & 1) && i == g.n1 - 1) ||
+       (((bi.finer_mask >> YLO) & 1) && j == 0) || (((bi.finer_mask >> YHI) & 1) && j == g.n2 - 1) ||
+       (((bi.finer_mask >> ZLO) & 1) && k == 0) || (((bi.finer_mask >> ZHI) & 1) && k == g.n3 - 1))) {
     const int n[3] = {g.n1, g.n2, g.n3};
     const int cc[3] = {i, j, k};
     const int fsz = NV * max(max(g.n1 * g.n2, g.n1 * g.n3), g.n2 * g.n3);
@@ -321,8 +444,8 @@ hipError_t launch_flux_correct(double* u, const BlockInfo* blocks, const FineFac
                                const Geom& g, DevTime* tm, double beta, int32_t do_dt,
                                const double* fbuf, const int32_t* nbr, hipStream_t s) {
   if (ncblocks == 0) return hipSuccess;
-  const int ncell = g.n1 * g.n2 * g.n3;
-  dim3 grid((ncell + 255) / 256, ncblocks);
+  const int nshell = 2 * g.n1 * g.n2 + (g.n3 - 2) * (2 * g.n1 + 2 * (g.n2 - 2));
+  dim3 grid((nshell + 255) / 256, ncblocks);
   hipLaunchKernelGGL(flux_correct_kernel, grid, dim3(256), 0, s, u, blocks, ff, ff_first, cblocks,
                      g, tm, beta, do_dt, fbuf, nbr);
   return hipGetLastError();
@@ -526,7 +649,6 @@ __global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, 
   double mx = 0.0;
   for (int q = threadIdx.x; q < ncell; q += 256) {
     const int i = q % g.n1, j = (q / g.n1) % g.n2, k = q / (g.n1 * g.n2);
-    const double* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       // neighbours beyond the block: the face neighbour's active cells
