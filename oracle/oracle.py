@@ -26,7 +26,7 @@ def lib():
             _build.build()
         L = C.CDLL(path)
         L.orc_create.argtypes = [_I32, _I32, C.c_int32, _D, _D, C.c_double, C.c_double,
-                                 C.c_int32, _I32, C.c_int64, C.POINTER(C.c_void_p)]
+                                 C.c_int32, _I32, _I32, C.c_int64, C.POINTER(C.c_void_p)]
         L.orc_create.restype = C.c_int
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_nleaves.argtypes = [C.c_void_p]
@@ -63,6 +63,10 @@ class OracleError(RuntimeError):
     pass
 
 
+# Boundary kinds per face (x-, x+, y-, y+, z-, z+).
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+
+
 def threads():
     """OpenMP threads the oracle uses."""
     return int(lib().orc_threads())
@@ -95,20 +99,24 @@ class OracleMesh:
     """Block mesh held by the C oracle.
 
     nblock: cells per block (n1, n2, n3); nroot_blocks: level-0 blocks per
-    dimension; leaves: iterable of (level, lx, ly, lz).
+    dimension; leaves: iterable of (level, lx, ly, lz); bc: boundary kind
+    per face (x-, x+, y-, y+, z-, z+), BC_* values.
     """
 
     def __init__(self, nblock, nroot_blocks, leaves, gamma=5.0 / 3.0, cfl=0.3,
-                 xmin=(0.0, 0.0, 0.0), xmax=(1.0, 1.0, 1.0), max_level=0, stage1_recon=0):
+                 xmin=(0.0, 0.0, 0.0), xmax=(1.0, 1.0, 1.0), max_level=0, stage1_recon=0,
+                 bc=(BC_PERIODIC,) * 6):
         n = np.array(nblock, dtype=np.int32)
         nrb = np.array(nroot_blocks, dtype=np.int32)
         locs = np.ascontiguousarray(np.array(leaves, dtype=np.int32).reshape(-1, 4))
         xmn = np.array(xmin, dtype=np.float64)
         xmx = np.array(xmax, dtype=np.float64)
+        bca = np.array(bc, dtype=np.int32)
+        assert bca.shape == (6,)
         h = C.c_void_p()
         rc = lib().orc_create(n.ctypes.data_as(_I32), nrb.ctypes.data_as(_I32), int(max_level),
                               _dp(xmn), _dp(xmx), float(gamma), float(cfl), int(stage1_recon),
-                              locs.ctypes.data_as(_I32), len(locs), C.byref(h))
+                              bca.ctypes.data_as(_I32), locs.ctypes.data_as(_I32), len(locs), C.byref(h))
         if rc != 0:
             raise OracleError(f"orc_create failed with {rc}")
         self._h = h
@@ -119,6 +127,7 @@ class OracleMesh:
         self.xmin = tuple(xmn)
         self.xmax = tuple(xmx)
         self.max_level = max_level
+        self.bc = tuple(int(x) for x in bca)
 
     def __del__(self):
         h = getattr(self, "_h", None)

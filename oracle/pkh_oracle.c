@@ -24,6 +24,13 @@
  *     correction.
  *   - Sec. 3.8: periodic derefinement, tree rebuilt on (de)refinement.
  *   - Sec. 3.10: global reductions (the CFL timestep, conserved totals).
+ *   - Boundaries of the domain, per face: periodic, outflow (zero-gradient:
+ *     a ghost cell takes the value of the nearest cell inside) or
+ *     reflecting (a ghost cell takes the value of its mirror image across
+ *     the face with the normal momentum negated). A ghost cell outside the
+ *     domain is first mapped to its image inside, then evaluated like any
+ *     ghost cell there (copy, restriction or prolongation), so the rule
+ *     also covers the coarse cells a prolongation stencil reaches.
  *
  * Ghost values are evaluated as a pure function of the leaves' active data
  * (nothing is cached between stages), so the fill order cannot matter.
@@ -41,6 +48,7 @@
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ETILING = -2, ORC_EBALANCE = -3,
        ORC_ENOMEM = -4, ORC_EPHYS = -6 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_REFLECT = 2 };
 
 typedef struct {
   int n[3];          /* active cells per block along x, y, z */
@@ -49,6 +57,7 @@ typedef struct {
   double xmin[3], xmax[3];
   double gamma, cfl;
   int recon1;        /* stage-1 reconstruction: 0 donor cell, 1 PLM */
+  int bc[6];         /* per face x-, x+, y-, y+, z-, z+: ORC_BC_* */
   int64_t nl;        /* number of leaves */
   int32_t *loc;      /* [nl][4]: level, lx, ly, lz */
   double *U;         /* [nl][5][n3][n2][n1], conserved, active cells */
@@ -152,26 +161,71 @@ static double dxl(const orc_mesh *m, int L, int d) {
   return (m->xmax[d] - m->xmin[d]) / (double)ncel_dim(m, L, d);
 }
 
-/* Leaf id whose block location at level L is b (periodically wrapped), or -1. */
+static int periodic(const orc_mesh *m, int d) { return m->bc[2 * d] == ORC_BC_PERIODIC; }
+
+/* Block location b of level L brought into the domain: wrapped along
+   periodic directions. Returns 0 (and leaves w undefined) when b lies
+   outside the domain along a non-periodic direction. */
+static int block_in_domain(const orc_mesh *m, int L, const int64_t b[3], int64_t w[3]) {
+  for (int d = 0; d < 3; ++d) {
+    int64_t nb = nblk_dim(m, L, d);
+    if (periodic(m, d)) w[d] = wrap(b[d], nb);
+    else if (b[d] < 0 || b[d] >= nb) return 0;
+    else w[d] = b[d];
+  }
+  return 1;
+}
+
+/* Leaf id whose block location at level L is b (wrapped along periodic
+   directions), or -1 (also outside the domain). */
 static int32_t leaf_at(const orc_mesh *m, int L, const int64_t b[3]) {
   if (L < 0 || L > m->maxl) return -1;
-  int64_t x = wrap(b[0], nblk_dim(m, L, 0));
-  int64_t y = wrap(b[1], nblk_dim(m, L, 1));
-  int64_t z = wrap(b[2], nblk_dim(m, L, 2));
-  return m->map[L][(z * nblk_dim(m, L, 1) + y) * nblk_dim(m, L, 0) + x];
+  int64_t w[3];
+  if (!block_in_domain(m, L, b, w)) return -1;
+  return m->map[L][(w[2] * nblk_dim(m, L, 1) + w[1]) * nblk_dim(m, L, 0) + w[0]];
 }
 
 /* Leaf at a level below L that contains block location b of level L, or -1.
    Writes its level to *lc. */
 static int32_t coarser_leaf(const orc_mesh *m, int L, const int64_t b[3], int *lc) {
+  int64_t w[3];
+  if (!block_in_domain(m, L, b, w)) return -1;
   for (int Lc = L - 1; Lc >= 0; --Lc) {
     int s = L - Lc;
     int64_t bw[3];
-    for (int d = 0; d < 3; ++d) bw[d] = wrap(b[d], nblk_dim(m, L, d)) >> s;
+    for (int d = 0; d < 3; ++d) bw[d] = w[d] >> s;
     int32_t id = leaf_at(m, Lc, bw);
     if (id >= 0) { *lc = Lc; return id; }
   }
   return -1;
+}
+
+/* Global cell J of level L mapped into the domain: wrapped along periodic
+   directions; along the others a cell beyond a face goes to the nearest
+   cell inside (outflow) or to its mirror image (reflecting). Returns the
+   set of reflected directions as bits (bit d: the momentum along d of the
+   image changes sign). */
+static int cell_in_domain(const orc_mesh *m, int L, const int64_t Jin[3], int64_t J[3]) {
+  int flip = 0;
+  for (int d = 0; d < 3; ++d) {
+    int64_t N = ncel_dim(m, L, d);
+    J[d] = Jin[d];
+    if (periodic(m, d)) { J[d] = wrap(J[d], N); continue; }
+    int side = J[d] < 0 ? 0 : (J[d] >= N ? 1 : -1);
+    if (side < 0) continue;
+    if (m->bc[2 * d + side] == ORC_BC_OUTFLOW) {
+      J[d] = side ? N - 1 : 0;
+    } else {
+      J[d] = side ? 2 * N - 1 - J[d] : -1 - J[d];
+      flip ^= 1 << d;
+    }
+  }
+  return flip;
+}
+
+/* Sign of variable v of an image reflected along the directions in flip. */
+static double image_sign(int flip, int v) {
+  return (v >= 1 && v <= 3 && ((flip >> (v - 1)) & 1)) ? -1.0 : 1.0;
 }
 
 static double uat(const orc_mesh *m, const double *U, int64_t id, int v,
@@ -193,13 +247,11 @@ static double restrict8(const double f[2][2][2]) {
    The last case is reached only while regridding. */
 static double comp(const orc_mesh *m, const double *U, int L, const int64_t Jin[3], int v) {
   int64_t J[3], b[3];
-  for (int d = 0; d < 3; ++d) {
-    J[d] = wrap(Jin[d], ncel_dim(m, L, d));
-    b[d] = J[d] / m->n[d];
-  }
+  const double sg = image_sign(cell_in_domain(m, L, Jin, J), v);
+  for (int d = 0; d < 3; ++d) b[d] = J[d] / m->n[d];
   int32_t id = leaf_at(m, L, b);
   if (id >= 0)
-    return uat(m, U, id, v, J[0] - b[0] * m->n[0], J[1] - b[1] * m->n[1], J[2] - b[2] * m->n[2]);
+    return sg * uat(m, U, id, v, J[0] - b[0] * m->n[0], J[1] - b[1] * m->n[1], J[2] - b[2] * m->n[2]);
   int lc;
   id = coarser_leaf(m, L, b, &lc);
   if (id >= 0) {
@@ -207,8 +259,8 @@ static double comp(const orc_mesh *m, const double *U, int L, const int64_t Jin[
     int64_t Jc[3];
     for (int d = 0; d < 3; ++d) Jc[d] = J[d] >> s;
     const int32_t *lo = m->loc + 4 * id;
-    return uat(m, U, id, v, Jc[0] - (int64_t)lo[1] * m->n[0], Jc[1] - (int64_t)lo[2] * m->n[1],
-               Jc[2] - (int64_t)lo[3] * m->n[2]);
+    return sg * uat(m, U, id, v, Jc[0] - (int64_t)lo[1] * m->n[0], Jc[1] - (int64_t)lo[2] * m->n[1],
+                    Jc[2] - (int64_t)lo[3] * m->n[2]);
   }
   double f[2][2][2];
   for (int c = 0; c < 2; ++c)
@@ -217,16 +269,13 @@ static double comp(const orc_mesh *m, const double *U, int L, const int64_t Jin[
         int64_t Jf[3] = {2 * J[0] + a, 2 * J[1] + bb, 2 * J[2] + c};
         f[c][bb][a] = comp(m, U, L + 1, Jf, v);
       }
-  return restrict8(f);
+  return sg * restrict8(f);
 }
 
-/* Value of a ghost cell of a level-L leaf at global level-L cell J. */
-static double ghost_value(orc_mesh *m, const double *U, int L, const int64_t Jin[3], int v) {
-  int64_t J[3], b[3];
-  for (int d = 0; d < 3; ++d) {
-    J[d] = wrap(Jin[d], ncel_dim(m, L, d));
-    b[d] = J[d] / m->n[d];
-  }
+/* Ghost value at a level-L cell J inside the domain (O6 rules). */
+static double ghost_inside(orc_mesh *m, const double *U, int L, const int64_t J[3], int v) {
+  int64_t b[3];
+  for (int d = 0; d < 3; ++d) b[d] = J[d] / m->n[d];
   int32_t id = leaf_at(m, L, b);
   if (id >= 0)  /* same level: copy */
     return uat(m, U, id, v, J[0] - b[0] * m->n[0], J[1] - b[1] * m->n[1], J[2] - b[2] * m->n[2]);
@@ -258,6 +307,15 @@ static double ghost_value(orc_mesh *m, const double *U, int L, const int64_t Jin
         f[c][bb][a] = comp(m, U, L + 1, Jf, v);
       }
   return restrict8(f);
+}
+
+/* Value of a ghost cell of a level-L leaf at global level-L cell J: the
+   value of its image in the domain (the cell itself where it lies inside),
+   times the image's momentum signs. */
+static double ghost_value(orc_mesh *m, const double *U, int L, const int64_t Jin[3], int v) {
+  int64_t J[3];
+  const double sg = image_sign(cell_in_domain(m, L, Jin, J), v);
+  return sg * ghost_inside(m, U, L, J, v);
 }
 
 /* Padded copy [5][n3+4][n2+4][n1+4] of leaf id: active cells from U, ghost
@@ -336,9 +394,9 @@ static void flux_correct(orc_mesh *m, double **F) {
     if (L >= m->maxl) continue;
     for (int d = 0; d < 3; ++d)
       for (int s = 0; s < 2; ++s) {
-        int64_t nb[3] = {lo[1], lo[2], lo[3]};
-        nb[d] += s ? 1 : -1;
-        for (int e = 0; e < 3; ++e) nb[e] = wrap(nb[e], nblk_dim(m, L, e));
+        int64_t nb0[3] = {lo[1], lo[2], lo[3]}, nb[3];
+        nb0[d] += s ? 1 : -1;
+        if (!block_in_domain(m, L, nb0, nb)) continue; /* domain boundary */
         if (leaf_at(m, L, nb) >= 0) continue;
         int lc;
         if (coarser_leaf(m, L, nb, &lc) >= 0) continue;
@@ -528,8 +586,8 @@ static int build_maps(orc_mesh *m) {
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
           if (!dx && !dy && !dz) continue;
-          int64_t nb[3] = {lo[1] + dx, lo[2] + dy, lo[3] + dz};
-          for (int e = 0; e < 3; ++e) nb[e] = wrap(nb[e], nblk_dim(m, L, e));
+          int64_t nb0[3] = {lo[1] + dx, lo[2] + dy, lo[3] + dz}, nb[3];
+          if (!block_in_domain(m, L, nb0, nb)) continue; /* beyond the domain boundary */
           if (leaf_at(m, L, nb) >= 0) continue;
           int lc;
           if (coarser_leaf(m, L, nb, &lc) >= 0) {
@@ -564,9 +622,15 @@ void orc_destroy(void *h) {
    stored in Morton order of their deepest-level corner. */
 int orc_create(const int32_t *n, const int32_t *nrb, int32_t maxl, const double *xmin,
                const double *xmax, double gamma, double cfl, int32_t recon1,
-               const int32_t *locs, int64_t nl, void **out) {
+               const int32_t *bc, const int32_t *locs, int64_t nl, void **out) {
   *out = NULL;
   if (maxl < 0 || maxl > MAXLEV || nl <= 0) return ORC_EINVAL;
+  for (int f = 0; f < 6; ++f) {
+    int k = bc ? bc[f] : ORC_BC_PERIODIC;
+    if (k < ORC_BC_PERIODIC || k > ORC_BC_REFLECT) return ORC_EINVAL;
+    /* a periodic direction is periodic on both faces */
+    if ((k == ORC_BC_PERIODIC) != ((bc ? bc[f ^ 1] : ORC_BC_PERIODIC) == ORC_BC_PERIODIC)) return ORC_EINVAL;
+  }
   for (int d = 0; d < 3; ++d) {
     if (n[d] < 2 || nrb[d] < 1 || (n[d] & 1)) return ORC_EINVAL;
     if (maxl > 0 && n[d] < 8) return ORC_EINVAL;
@@ -584,6 +648,7 @@ int orc_create(const int32_t *n, const int32_t *nrb, int32_t maxl, const double 
   m->gamma = gamma;
   m->cfl = cfl;
   m->recon1 = recon1;
+  for (int f = 0; f < 6; ++f) m->bc[f] = bc ? bc[f] : ORC_BC_PERIODIC;
   m->nl = nl;
   m->loc = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)nl);
   m->U = (double *)calloc((size_t)(nl * NV * ncell(m)), sizeof(double));
@@ -752,8 +817,8 @@ int orc_regrid(void *h, const int8_t *flags, int64_t nflags) {
       for (int dy = -1; dy <= 1 && ok; ++dy)
         for (int dx = -1; dx <= 1 && ok; ++dx) {
           if (!dx && !dy && !dz) continue;
-          int64_t q[3] = {p[0] + dx, p[1] + dy, p[2] + dz};
-          for (int e = 0; e < 3; ++e) q[e] = wrap(q[e], nblk_dim(m, L - 1, e));
+          int64_t q0[3] = {p[0] + dx, p[1] + dy, p[2] + dz}, q[3];
+          if (!block_in_domain(m, L - 1, q0, q)) continue;
           int32_t id = leaf_at(m, L - 1, q);
           int lc;
           if (id >= 0 || cover_coarser(m, L - 1, q, &lc) >= 0) continue;

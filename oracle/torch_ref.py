@@ -1,4 +1,4 @@
-"""Uniform periodic grid formulation in plain PyTorch CPU FP64 ops.
+"""Uniform grid formulation in plain PyTorch CPU FP64 ops.
 
 TEST INFRASTRUCTURE. An independent re-derivation of the same update as the
 C oracle, written on one global array ``[5][N3][N2][N1]`` with neighbours
@@ -6,6 +6,12 @@ taken by ``torch.roll`` (no blocks, no ghost zones, no tables), so it
 cross-checks the C oracle's block decomposition and ghost exchange. Through
 autograd it is also the reference gradient of the adjoint: the timestep of
 each cycle is detached (frozen), every other operation is differentiated.
+
+Domain boundaries other than periodic (``bc`` per face x-, x+, y-, y+, z-,
+z+: 0 periodic, 1 outflow, 2 reflecting) extend the array by two cells
+beyond each face along the direction being differenced: the nearest cell
+(outflow, zero gradient) or the mirror image with the normal velocity
+negated (reflecting); fluxes are then taken on all N+1 faces.
 
 Method (Parthenon paper Sec. 4.1; readings of the Athena++ lineage):
   * primitive variables w = (rho, v, P), P = (gamma-1)(E - |M|^2/(2 rho));
@@ -80,7 +86,7 @@ def hlle_flux(wl, wr, d, gamma, log=None):
 
 
 def face_flux(W, d, recon, gamma, log=None):
-    """Flux at the lower face (i - 1/2 along d) of every cell."""
+    """Flux at the lower face (i - 1/2 along d) of every cell (periodic)."""
     ax = _DIM[d]
     q0 = W
     qm1 = torch.roll(W, 1, ax)
@@ -93,12 +99,57 @@ def face_flux(W, d, recon, gamma, log=None):
     return hlle_flux(wl, wr, d, gamma, log)
 
 
-def divergence(U, recon, gamma, dx, log=None):
+def extend(W, d, bc):
+    """Primitive array W with two cells added beyond each face along d, per
+    the boundary kind of that face: wrapped, the nearest cell (outflow), or
+    the mirror image with velocity component d negated (reflecting)."""
+    ax = _DIM[d]
+    n = W.shape[ax]
+    sign = torch.ones(5, dtype=W.dtype)
+    sign[1 + d] = -1.0
+    sign = sign.view(5, *([1] * (W.dim() - 1)))
+    sides = []
+    for side in (0, 1):
+        kind = bc[2 * d + side]
+        edge = W.narrow(ax, 0, 2) if side == 0 else W.narrow(ax, n - 2, 2)
+        if kind == 0:
+            g = W.narrow(ax, n - 2, 2) if side == 0 else W.narrow(ax, 0, 2)
+        elif kind == 1:
+            one = W.narrow(ax, 0, 1) if side == 0 else W.narrow(ax, n - 1, 1)
+            g = torch.cat([one, one], ax)
+        elif kind == 2:
+            g = torch.flip(edge, (ax,)) * sign
+        else:
+            raise ValueError(f"unknown boundary kind {kind}")
+        sides.append(g)
+    return torch.cat([sides[0], W, sides[1]], ax)
+
+
+def face_flux_bc(W, d, recon, gamma, bc, log=None):
+    """Fluxes on the N+1 faces along d (face f between cells f-1 and f)."""
+    ax = _DIM[d]
+    n = W.shape[ax]
+    Wp = extend(W, d, bc)
+    qm2, qm1, q0, qp1 = (Wp.narrow(ax, o, n + 1) for o in range(4))
+    if recon == 0:
+        return hlle_flux(qm1, q0, d, gamma, log)
+    wl = qm1 + 0.5 * mc_slope(qm1 - qm2, q0 - qm1, log)
+    wr = q0 - 0.5 * mc_slope(q0 - qm1, qp1 - q0, log)
+    return hlle_flux(wl, wr, d, gamma, log)
+
+
+def divergence(U, recon, gamma, dx, log=None, bc=None):
     W = to_prim(U, gamma)
     D = None
     for d in range(3):
-        F = face_flux(W, d, recon, gamma, log)
-        term = (torch.roll(F, -1, _DIM[d]) - F) / dx[d]
+        ax = _DIM[d]
+        if bc is None:
+            F = face_flux(W, d, recon, gamma, log)
+            term = (torch.roll(F, -1, ax) - F) / dx[d]
+        else:
+            F = face_flux_bc(W, d, recon, gamma, bc, log)
+            n = W.shape[ax]
+            term = (F.narrow(ax, 1, n) - F.narrow(ax, 0, n)) / dx[d]
         D = term if D is None else D + term
     return D
 
@@ -113,24 +164,25 @@ def cfl_dt(U, gamma, cfl, dx):
     return cfl * best
 
 
-def cycle(U, dt, gamma, dx, stage1_recon=0, log=None):
-    Us = U - 0.5 * dt * divergence(U, stage1_recon, gamma, dx, log)
-    return U - dt * divergence(Us, 1, gamma, dx, log)
+def cycle(U, dt, gamma, dx, stage1_recon=0, log=None, bc=None):
+    Us = U - 0.5 * dt * divergence(U, stage1_recon, gamma, dx, log, bc)
+    return U - dt * divergence(Us, 1, gamma, dx, log, bc)
 
 
-def run(U, ncycles, gamma=5.0 / 3.0, cfl=0.3, dx=None, stage1_recon=0, dts=None, log=None):
+def run(U, ncycles, gamma=5.0 / 3.0, cfl=0.3, dx=None, stage1_recon=0, dts=None, log=None, bc=None):
     """Advance ncycles; the timestep is evaluated from the detached state
     (or taken from ``dts``). Returns (U, list of dt). With ``log`` a list,
     every limiter and wave-speed branch taken is appended to it (int8
     tensors), so two runs are on the same smooth piece of the map exactly
-    when their logs are equal."""
+    when their logs are equal. ``bc``: boundary kind per face (None:
+    periodic through ``torch.roll``)."""
     if dx is None:
         dx = tuple(1.0 / U.shape[3 - d] for d in range(3))
     used = []
     for c in range(ncycles):
         dt = cfl_dt(U.detach(), gamma, cfl, dx) if dts is None else torch.as_tensor(dts[c], dtype=U.dtype)
         used.append(float(dt))
-        U = cycle(U, dt, gamma, dx, stage1_recon, log)
+        U = cycle(U, dt, gamma, dx, stage1_recon, log, bc)
     return U, used
 
 
