@@ -56,7 +56,15 @@ enum pkh_status {
   PKH_ESTATE = -7    /* call not valid in the handle's current state */
 };
 
-enum { PKH_BC_PERIODIC = 0 };
+/* Boundary kind of a domain face. PERIODIC: the face is glued to the
+   opposite one (both faces of a direction periodic or neither). OUTFLOW:
+   a ghost cell beyond the face takes the value of the nearest cell inside
+   (zero gradient). REFLECT: a ghost cell takes the value of its mirror
+   image across the face with the momentum normal to the face negated.
+   Beyond a wall the image is evaluated like any ghost cell there (copy,
+   restriction or prolongation), and a prolongation stencil that reaches
+   past a wall at the coarse level uses the coarse image cells. */
+enum { PKH_BC_PERIODIC = 0, PKH_BC_OUTFLOW = 1, PKH_BC_REFLECT = 2 };
 enum { PKH_RECON_DC = 0, PKH_RECON_PLM = 1 };
 enum { PKH_LIMITER_MC = 0 };
 /* pkh_config.flags */
@@ -73,8 +81,8 @@ enum { PKH_FLAG_GRAPH = 1u /* replay captured cycles with hipGraphs */ };
  *   max_level  deepest refinement level (0..7).
  *   xmin/xmax  domain extent; gamma the ideal-gas ratio; cfl the Courant
  *              number of the timestep.
- *   bc[6]      boundary kind per face (x-, x+, y-, y+, z-, z+); only
- *              PKH_BC_PERIODIC is accepted.
+ *   bc[6]      boundary kind per face (x-, x+, y-, y+, z-, z+), PKH_BC_*.
+ *              The reverse mode and batches take periodic meshes only.
  *   stage1_recon PKH_RECON_DC (predictor-corrector, default) or PKH_RECON_PLM.
  *   limiter    PKH_LIMITER_MC.
  *   regrid_every  informational: the caller's derefinement cadence.
@@ -138,19 +146,20 @@ int pkh_state_upload(pkh_mesh *mesh, const double *src, int32_t src_on_device);
 int pkh_state_download(pkh_mesh *mesh, double *dst, int32_t dst_on_device);
 
 /* Fill every ghost zone from the leaves' active data (Sec. 3.7: copy,
-   restriction, prolongation, all 26 neighbour regions, periodic wrap) and
-   recompute the CFL timestep from the active data (Sec. 3.10). Inside
-   pkh_step the kernels read a same-level neighbour's cells directly and only
-   the face ghost regions that cross a level jump are refilled after each
-   stage; the other ghost cells keep the values of the last full fill. */
+   restriction, prolongation, all 26 neighbour regions; periodic wrap or
+   the wall images of PKH_BC_*) and recompute the CFL timestep from the
+   active data (Sec. 3.10). Inside pkh_step the kernels read a same-level
+   neighbour's cells directly and only the face ghost regions that cross a
+   level jump or a wall are refilled after each stage; the other ghost
+   cells keep the values of the last full fill. */
 int pkh_exchange_boundaries(pkh_mesh *mesh);
 
 /* Advance n_cycles full cycles (Sec. 4.1). Each cycle:
      dt  = CFL timestep of the current state, clamped to t_end - t when
            t_end is finite;
      U*  = U^n - dt/2 D(U^n)   (donor-cell or PLM faces, HLLE fluxes);
-     on multilevel meshes, fine-coarse flux correction and the ghost faces
-     across level jumps of U*;
+     on multilevel meshes, fine-coarse flux correction; the ghost faces
+     across level jumps and walls of U*;
      U^{n+1} = U^n - dt D_PLM(U*) (MC-limited PLM on primitives, HLLE);
      the same for U^{n+1}; t += dt; the next dt is reduced on the device.
    Halo cells at same-level faces are read from the neighbour's active

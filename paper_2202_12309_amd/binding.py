@@ -140,18 +140,22 @@ def _as_locs(leaves):
     return locs, len(arr)
 
 
+# Boundary kinds per face (pkh_config.bc: x-, x+, y-, y+, z-, z+).
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+
+
 class Mesh:
     """A block mesh resident on the GPU.
 
     nroot: level-0 cells per dimension; nblock: cells per block; leaves:
-    (level, lx, ly, lz) rows. The library stores leaves in Morton order:
-    :meth:`leaves` returns that storage order, which every state array uses
-    (``[nleaves][5][n3][n2][n1]``).
+    (level, lx, ly, lz) rows; bc: boundary kind per face (BC_*). The
+    library stores leaves in Morton order: :meth:`leaves` returns that
+    storage order, which every state array uses (``[nleaves][5][n3][n2][n1]``).
     """
 
     def __init__(self, nroot, nblock, leaves, gamma=5.0 / 3.0, cfl=0.3, xmin=(0.0, 0.0, 0.0),
                  xmax=(1.0, 1.0, 1.0), max_level=0, stage1_recon=0, graph=False, device=0,
-                 stream=None, torch_alloc=True):
+                 stream=None, torch_alloc=True, bc=(0,) * 6):
         import torch
         self.torch = torch
         self.device = device
@@ -171,7 +175,7 @@ class Mesh:
         cfg.gamma = float(gamma)
         cfg.cfl = float(cfl)
         for f in range(6):
-            cfg.bc[f] = 0
+            cfg.bc[f] = int(bc[f])
         cfg.stage1_recon = int(stage1_recon)
         cfg.limiter = 0
         cfg.regrid_every = 0

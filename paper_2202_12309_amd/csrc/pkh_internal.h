@@ -11,6 +11,8 @@ constexpr int NG = 2;  // ghost width (PLM needs two cells beside a face)
 
 // Face slots of a block: 2*d + s, d = 0 (x), 1 (y), 2 (z); s = 0 low, 1 high.
 enum : int { XLO = 0, XHI = 1, YLO = 2, YHI = 3, ZLO = 4, ZHI = 5 };
+// Boundary kinds of a domain face (the values of pkh_config.bc).
+enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
 
 // Per-leaf data the kernels read.
 struct BlockInfo {
@@ -53,6 +55,7 @@ struct Geom {
   int64_t vstride;      // doubles per variable of one padded block
   int64_t bstride;      // doubles per padded block (5 * vstride)
   int32_t nrb[3];       // level-0 blocks per dim
+  int32_t bc[6];        // boundary kind per face (x-, x+, y-, y+, z-, z+)
   double gamma;
 };
 

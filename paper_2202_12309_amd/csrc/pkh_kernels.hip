@@ -37,18 +37,13 @@ __device__ __forceinline__ int64_t pad_index(const Geom& g, int i, int j, int k)
   return ((int64_t)(k + NG) * g.p2 + (j + NG)) * g.p1 + (i + NG);
 }
 
-// Composite value at level L, global cell J (any integers; wrapped here),
-// all five variables: leaf value at level L; restriction of the level-(L+1)
-// leaves; or, while regridding, the containing coarser cell (injection).
-__device__ void comp_val(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L,
-                         int J0, int J1, int J2, double out[NV], int* err) {
+// Composite value at level L of a global cell J inside the domain, all five
+// variables: leaf value at level L; restriction of the level-(L+1) leaves;
+// or, while regridding, the containing coarser cell (injection).
+__device__ void comp_val_inside(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g,
+                                int L, const int J[3], double out[NV], int* err) {
   const int n[3] = {g.n1, g.n2, g.n3};
-  int J[3] = {J0, J1, J2}, b[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    J[d] = wrap_i(J[d], (g.nrb[d] * n[d]) << L);
-    b[d] = J[d] / n[d];
-  }
+  const int b[3] = {J[0] / n[0], J[1] / n[1], J[2] / n[2]};
   int32_t id = leaf_at(M, L, b[0], b[1], b[2]);
   if (id >= 0) {
     const double* c = u + (int64_t)id * g.bstride +
@@ -96,6 +91,51 @@ __device__ void comp_val(const double* u, const BlockInfo* blocks, const LevelMa
     out[v] = 0.125 * (((fc[0][o] + fc[1][o]) + (fc[2][o] + fc[3][o])) +
                       ((fc[4][o] + fc[5][o]) + (fc[6][o] + fc[7][o])));
   }
+}
+
+// Global cell J of level L (at most one domain length outside) brought into
+// the domain: wrapped along periodic directions; beyond an outflow face the
+// nearest cell inside, beyond a reflecting face the mirror image. Returns
+// the reflected directions in bits 0-2 (the image's momentum along them
+// changes sign) and bit 3 when J was moved across a wall.
+__device__ __forceinline__ int cell_in_domain(const Geom& g, int L, int J[3]) {
+  const int n[3] = {g.n1, g.n2, g.n3};
+  int code = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int N = (g.nrb[d] * n[d]) << L;
+    if (g.bc[2 * d] == BC_PERIODIC) {
+      J[d] = wrap_i(J[d], N);
+    } else if (J[d] < 0 || J[d] >= N) {
+      const int hi = J[d] >= N;
+      code |= 8;
+      if (g.bc[2 * d + hi] == BC_OUTFLOW) {
+        J[d] = hi ? N - 1 : 0;
+      } else {
+        J[d] = hi ? 2 * N - 1 - J[d] : -1 - J[d];
+        code |= 1 << d;
+      }
+    }
+  }
+  return code;
+}
+
+// Momentum signs of an image reflected along the directions in code.
+__device__ __forceinline__ void apply_image_signs(int code, double out[NV]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if ((code >> d) & 1) out[1 + d] = -out[1 + d];
+}
+
+// Composite value at level L, global cell J (any integers within a domain
+// length; brought into the domain here): beyond a wall, the value of the
+// image cell with its momentum signs.
+__device__ void comp_val(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L,
+                         int J0, int J1, int J2, double out[NV], int* err) {
+  int J[3] = {J0, J1, J2};
+  const int code = cell_in_domain(g, L, J);
+  comp_val_inside(u, blocks, M, g, L, J, out, err);
+  apply_image_signs(code, out);
 }
 
 // Linear prolongation to fine cell F (level L) from the composite field at
@@ -154,35 +194,34 @@ __device__ __forceinline__ void ghost_coord(int q, const Geom& g, int& i, int& j
 }
 
 // Value of ghost cell (i, j, k) of leaf b from the leaf data (copy,
-// restriction or prolongation); skip_same leaves cells whose source is a
-// same-level leaf alone.
+// restriction or prolongation); a ghost cell beyond a wall takes the value
+// of its image inside the domain, with the image's momentum signs.
+// skip_same leaves cells inside the domain whose source is a same-level
+// leaf alone.
 __device__ __forceinline__ void fill_cell(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& M,
                                           DevTime* tm, int b, int i, int j, int k, int skip_same) {
   const BlockInfo bi = blocks[b];
   const int L = bi.level;
   const int n[3] = {g.n1, g.n2, g.n3};
-  int J[3] = {bi.lx * g.n1 + i, bi.ly * g.n2 + j, bi.lz * g.n3 + k}, bl[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    J[d] = wrap_i(J[d], (g.nrb[d] * n[d]) << L);
-    bl[d] = J[d] / n[d];
-  }
+  int J[3] = {bi.lx * g.n1 + i, bi.ly * g.n2 + j, bi.lz * g.n3 + k};
+  const int code = cell_in_domain(g, L, J);
+  const int bl[3] = {J[0] / n[0], J[1] / n[1], J[2] / n[2]};
   double* dst = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
+  int err = 0;
+  double val[NV];
   const int32_t id = leaf_at(M, L, bl[0], bl[1], bl[2]);
   if (id >= 0) {  // same level: copy
-    if (skip_same) return;
+    if (skip_same && !(code & 8)) return;
     const double* src = u + (int64_t)id * g.bstride +
                         pad_index(g, J[0] - bl[0] * n[0], J[1] - bl[1] * n[1], J[2] - bl[2] * n[2]);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) dst[v * g.vstride] = src[v * g.vstride];
-    return;
-  }
-  int err = 0;
-  double val[NV];
-  if (L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0)
+    for (int v = 0; v < NV; ++v) val[v] = src[v * g.vstride];
+  } else if (L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0) {
     prolong_val(u, blocks, M, g, L, J[0], J[1], J[2], val, &err);
-  else
-    comp_val(u, blocks, M, g, L, J[0], J[1], J[2], val, &err);
+  } else {
+    comp_val_inside(u, blocks, M, g, L, J, val, &err);
+  }
+  apply_image_signs(code, val);
 #pragma unroll
   for (int v = 0; v < NV; ++v) dst[v * g.vstride] = val[v];
   if (err) atomicOr(&tm->err, 2);
@@ -225,8 +264,9 @@ __device__ __forceinline__ void restrict_val(const double* u, const BlockInfo* b
 }
 
 // The face regions (width 2, active transverse extent) listed in jf as
-// (leaf, face) pairs: the faces whose neighbour is on another level, the
-// only ghost cells the stage kernels read. The region across one face is
+// (leaf, face | wall kind << 3) pairs: the faces whose neighbour is on
+// another level or beyond a wall, the only ghost cells the stage kernels
+// read. Across a level jump, the region across one face is
 // one block of the leaf's level, so a face is either wholly inside a
 // coarser leaf or wholly refined. Coarser: the 2-deep slab is one coarse
 // cell deep and aligned to coarse cells; eight lanes share one coarse
@@ -237,16 +277,40 @@ __device__ __forceinline__ void restrict_val(const double* u, const BlockInfo* b
 __global__ void __launch_bounds__(256) fill_faces_kernel(double* u, const BlockInfo* blocks, Geom g, LevelMaps M,
                                                          DevTime* tm, const int32_t* __restrict__ jf) {
   const int2 rec = reinterpret_cast<const int2*>(jf)[blockIdx.y];
-  const int b = rec.x, d = rec.y >> 1, hi = rec.y & 1;
-  const BlockInfo bi = blocks[b];
-  const int L = bi.level;
+  const int b = rec.x, d = (rec.y & 7) >> 1, hi = rec.y & 1, wall = rec.y >> 3;
   const int n[3] = {g.n1, g.n2, g.n3};
   const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  double* ub = u + (int64_t)b * g.bstride;
+  if (wall) {
+    // a face on the domain boundary: the image of each ghost cell lies in
+    // the leaf itself (the nearest layer for outflow, the mirror layer for
+    // reflection, normal momentum negated)
+    const int area = n[t1] * n[t2];
+    if (q >= 2 * area) return;
+    const int s = q / area, r = q - s * area;
+    int c[3], src[3];
+    c[t1] = src[t1] = r % n[t1];
+    c[t2] = src[t2] = r / n[t1];
+    c[d] = hi ? n[d] + s : s - NG;
+    if (wall == BC_OUTFLOW)
+      src[d] = hi ? n[d] - 1 : 0;
+    else
+      src[d] = hi ? 2 * n[d] - 1 - c[d] : -1 - c[d];
+    const double* sp = ub + pad_index(g, src[0], src[1], src[2]);
+    double* dp = ub + pad_index(g, c[0], c[1], c[2]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double x = sp[v * g.vstride];
+      dp[v * g.vstride] = (wall == BC_REFLECT && v == 1 + d) ? -x : x;
+    }
+    return;
+  }
+  const BlockInfo bi = blocks[b];
+  const int L = bi.level;
   int bl[3] = {bi.lx, bi.ly, bi.lz};
   bl[d] = wrap_i(bl[d] + (hi ? 1 : -1), g.nrb[d] << L);
   const bool coarser = L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0;
-  double* ub = u + (int64_t)b * g.bstride;
   int err = 0;
   if (coarser) {
     // Uniform per workgroup (one face per blockIdx.y): whole 8-lane groups

@@ -44,6 +44,8 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int MAXL = 7;
+static_assert(BC_PERIODIC == PKH_BC_PERIODIC && BC_OUTFLOW == PKH_BC_OUTFLOW && BC_REFLECT == PKH_BC_REFLECT,
+              "device boundary kinds follow pkh_config.bc");
 
 int64_t wrapl(int64_t a, int64_t n) {
   a %= n;
@@ -62,23 +64,32 @@ uint64_t spread_bits(uint64_t x) {
 struct Tree {
   int32_t nrb[3] = {1, 1, 1};
   int32_t maxl = 0;
+  bool periodic[3] = {true, true, true};
   std::vector<pkh_loc> leaves;
   std::vector<std::vector<int32_t>> map;  // per level
 
   int64_t nbd(int L, int d) const { return (int64_t)nrb[d] << L; }
 
+  // Block location (x,y,z) of level L wrapped along periodic directions;
+  // false when it lies beyond a non-periodic face of the domain.
+  bool inside(int L, int64_t& x, int64_t& y, int64_t& z) const {
+    int64_t* c[3] = {&x, &y, &z};
+    for (int d = 0; d < 3; ++d) {
+      if (periodic[d])
+        *c[d] = wrapl(*c[d], nbd(L, d));
+      else if (*c[d] < 0 || *c[d] >= nbd(L, d))
+        return false;
+    }
+    return true;
+  }
+
   int32_t at(int L, int64_t x, int64_t y, int64_t z) const {
-    if (L < 0 || L > maxl) return -1;
-    x = wrapl(x, nbd(L, 0));
-    y = wrapl(y, nbd(L, 1));
-    z = wrapl(z, nbd(L, 2));
+    if (L < 0 || L > maxl || !inside(L, x, y, z)) return -1;
     return map[L][(z * nbd(L, 1) + y) * nbd(L, 0) + x];
   }
   // Leaf at a coarser level containing block (x,y,z) of level L.
   int32_t coarser(int L, int64_t x, int64_t y, int64_t z, int* lc) const {
-    x = wrapl(x, nbd(L, 0));
-    y = wrapl(y, nbd(L, 1));
-    z = wrapl(z, nbd(L, 2));
+    if (!inside(L, x, y, z)) return -1;
     for (int c = L - 1; c >= 0; --c) {
       int s = L - c;
       int32_t id = at(c, x >> s, y >> s, z >> s);
@@ -136,7 +147,8 @@ struct Tree {
         for (int dy = -1; dy <= 1; ++dy)
           for (int dx = -1; dx <= 1; ++dx) {
             if (!dx && !dy && !dz) continue;
-            const int64_t x = l.lx1 + dx, y = l.lx2 + dy, z = l.lx3 + dz;
+            int64_t x = l.lx1 + dx, y = l.lx2 + dy, z = l.lx3 + dz;
+            if (!inside(l.level, x, y, z)) continue;  // beyond a wall: no neighbour
             if (at(l.level, x, y, z) >= 0) continue;
             int lc;
             if (coarser(l.level, x, y, z, &lc) >= 0) {
@@ -150,9 +162,7 @@ struct Tree {
               for (int e = 0; e < 3; ++e)
                 if ((del[e] < 0 && o[e] == 0) || (del[e] > 0 && o[e] == 1)) touch = false;
               if (!touch) continue;
-              const int64_t w[3] = {wrapl(x, nbd(l.level, 0)), wrapl(y, nbd(l.level, 1)),
-                                    wrapl(z, nbd(l.level, 2))};
-              if (at(l.level + 1, 2 * w[0] + o[0], 2 * w[1] + o[1], 2 * w[2] + o[2]) < 0)
+              if (at(l.level + 1, 2 * x + o[0], 2 * y + o[1], 2 * z + o[2]) < 0)
                 return fail(PKH_EBALANCE, "leaf %zu: finer neighbour two levels down", b);
             }
           }
@@ -303,7 +313,7 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
       const int d = f >> 1, s = f & 1;
       int64_t c[3] = {l.lx1, l.lx2, l.lx3};
       c[d] += s ? 1 : -1;
-      for (int e = 0; e < 3; ++e) c[e] = wrapl(c[e], t.nbd(l.level, e));
+      if (!t.inside(l.level, c[0], c[1], c[2])) continue;  // domain boundary
       if (t.at(l.level, c[0], c[1], c[2]) >= 0) continue;
       int lc;
       if (t.coarser(l.level, c[0], c[1], c[2], &lc) >= 0) continue;
@@ -349,16 +359,21 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
           if (id < 0) need_fill = true;
         }
   }
-  // faces whose neighbour is on another level: the ghost regions the stage
-  // kernels read from the ghost zone (all same-level halos are read from the
-  // neighbours' active cells)
+  // faces whose neighbour is on another level or beyond a wall: the ghost
+  // regions the stage kernels read from the ghost zone (all same-level halos
+  // are read from the neighbours' active cells). Record: leaf, then face
+  // | boundary kind << 3 (kind 0: a level jump).
   std::vector<int32_t> jf;
   for (int64_t b = 0; b < nb; ++b) {
     static const int slot[6] = {12, 14, 10, 16, 4, 22};
+    const pkh_loc& l = t.leaves[b];
     for (int f = 0; f < 6; ++f)
       if (nbr[b * 27 + slot[f]] < 0) {
+        int64_t c[3] = {l.lx1, l.lx2, l.lx3};
+        c[f >> 1] += (f & 1) ? 1 : -1;
+        const int kind = t.inside(l.level, c[0], c[1], c[2]) ? 0 : m->cfg.bc[f];
         jf.push_back((int32_t)b);
-        jf.push_back(f);
+        jf.push_back(f | kind << 3);
       }
   }
   // level maps
@@ -526,8 +541,12 @@ int check_config(const pkh_config* c) {
     if (!(c->xmax[d] > c->xmin[d])) return fail(PKH_EINVAL, "xmax must exceed xmin");
   }
   if (c->nblock[1] % tj) return fail(PKH_EINVAL, "nblock[1] must be a multiple of %d", tj);
-  for (int f = 0; f < 6; ++f)
-    if (c->bc[f] != PKH_BC_PERIODIC) return fail(PKH_EINVAL, "only periodic boundaries are supported");
+  for (int f = 0; f < 6; ++f) {
+    if (c->bc[f] != PKH_BC_PERIODIC && c->bc[f] != PKH_BC_OUTFLOW && c->bc[f] != PKH_BC_REFLECT)
+      return fail(PKH_EINVAL, "bc[%d] = %d is not a boundary kind", f, c->bc[f]);
+    if ((c->bc[f] == PKH_BC_PERIODIC) != (c->bc[f ^ 1] == PKH_BC_PERIODIC))
+      return fail(PKH_EINVAL, "a periodic direction must be periodic on both faces");
+  }
   if (c->stage1_recon != PKH_RECON_DC && c->stage1_recon != PKH_RECON_PLM)
     return fail(PKH_EINVAL, "stage1_recon must be PKH_RECON_DC or PKH_RECON_PLM");
   if (c->limiter != PKH_LIMITER_MC) return fail(PKH_EINVAL, "only the MC limiter is supported");
@@ -567,7 +586,10 @@ int pkh_mesh_create(const pkh_config* cfg, const pkh_loc* blocks, int64_t nblock
   m->af = alloc;
   m->ffn = free_fn;
   m->actx = alloc_ctx;
-  for (int d = 0; d < 3; ++d) m->tree.nrb[d] = cfg->nroot[d] / cfg->nblock[d];
+  for (int d = 0; d < 3; ++d) {
+    m->tree.nrb[d] = cfg->nroot[d] / cfg->nblock[d];
+    m->tree.periodic[d] = cfg->bc[2 * d] == PKH_BC_PERIODIC;
+  }
   m->tree.maxl = cfg->max_level;
   m->tree.leaves.assign(blocks, blocks + nblocks);
   m->tree.sort_morton();
@@ -585,6 +607,7 @@ int pkh_mesh_create(const pkh_config* cfg, const pkh_loc* blocks, int64_t nblock
   g.vstride = (int64_t)g.p1 * g.p2 * g.p3;
   g.bstride = NV * g.vstride;
   for (int d = 0; d < 3; ++d) g.nrb[d] = m->tree.nrb[d];
+  for (int f = 0; f < 6; ++f) g.bc[f] = cfg->bc[f];
   g.gamma = cfg->gamma;
   m->d_time = (DevTime*)m->dalloc(sizeof(DevTime));
   if (!m->d_time) {
@@ -818,7 +841,7 @@ int pkh_regrid(pkh_mesh* m) {
         for (int dx = -1; dx <= 1 && ok; ++dx) {
           if (!dx && !dy && !dz) continue;
           int64_t q[3] = {p[0] + dx, p[1] + dy, p[2] + dz};
-          for (int e = 0; e < 3; ++e) q[e] = wrapl(q[e], t.nbd(L - 1, e));
+          if (!t.inside(L - 1, q[0], q[1], q[2])) continue;  // beyond a wall
           int lc;
           if (t.at(L - 1, q[0], q[1], q[2]) >= 0 || t.coarser(L - 1, q[0], q[1], q[2], &lc) >= 0) continue;
           const int del[3] = {dx, dy, dz};
@@ -859,6 +882,7 @@ int pkh_regrid(pkh_mesh* m) {
   }
   Tree nt;
   std::copy(t.nrb, t.nrb + 3, nt.nrb);
+  std::copy(t.periodic, t.periodic + 3, nt.periodic);
   nt.maxl = t.maxl;
   std::stable_sort(nv.begin(), nv.end(), [&](const NewLeaf& a, const NewLeaf& b) {
     uint64_t ka = t.key(a.loc), kb = t.key(b.loc);
@@ -1046,7 +1070,7 @@ int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
   if (!m || !out || ckpt_every < 1) return fail(PKH_EINVAL, "bad argument");
   *out = nullptr;
   if (m->need_fill || m->ncblocks)
-    return fail(PKH_EINVAL, "the reverse mode supports single-level meshes only");
+    return fail(PKH_EINVAL, "the reverse mode supports single-level periodic meshes only");
   pkh_tape* t = new pkh_tape();
   t->m = m;
   t->K = ckpt_every;
@@ -1316,7 +1340,7 @@ int pkh_batch_create(pkh_mesh* const* meshes, int32_t n, pkh_batch** out) {
     }
     if (m->need_fill || m->ncblocks) {
       delete b;
-      return fail(PKH_EINVAL, "batches hold single-level meshes");
+      return fail(PKH_EINVAL, "batches hold single-level periodic meshes");
     }
   }
   std::vector<StageLaunch> pred(n), corr(n);

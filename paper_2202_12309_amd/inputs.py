@@ -207,6 +207,23 @@ def uniform_state(leaves, n, rho=1.0, v=(0.0, 0.0, 0.0), p=1.0, gamma=5.0 / 3.0)
     return U
 
 
+def smooth_flow(leaves, n, nrb, gamma=5.0 / 3.0, xmin=(0, 0, 0), xmax=(1, 1, 1)):
+    """A smooth flow with no symmetry, from the cell-centre coordinates (any
+    levels): density 1 +- 0.4, pressure 1 +- 0.25, speeds up to about 0.6,
+    not periodic across the domain (a test flow for walls)."""
+    U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    tp = 2.0 * np.pi
+    for b, lf in enumerate(leaves):
+        x, y, z = cell_centers(lf, n, nrb, xmin, xmax)
+        rho = 1.0 + 0.3 * np.sin(tp * (x + 0.13)) * np.cos(tp * (y - 0.2)) + 0.1 * np.cos(tp * z)
+        vx = 0.2 + 0.3 * np.cos(tp * (x + y))
+        vy = 0.3 * np.sin(tp * (x - z))
+        vz = 0.25 * np.cos(tp * (y + 0.3 * x))
+        p = 1.0 + 0.25 * np.sin(tp * (y + z + 0.1 * x))
+        U[b] = _to_conserved(rho, vx, vy, vz, p, gamma)
+    return U
+
+
 def _smoothed_field(N, seed, field, sigma=4.0, trunc=12):
     """Unit-variance, zero-mean periodic field: keyed white noise convolved
     with a separable Gaussian (sigma cells, truncated at +-trunc cells)."""

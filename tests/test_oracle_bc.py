@@ -23,21 +23,8 @@ def _conserved(rho, vx, vy, vz, p):
                      p / (G - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)])
 
 
-def _flow(m, shift=0.0):
-    """A smooth flow with no symmetry, evaluated at the cell centres of every
-    leaf of m (any levels)."""
-    U = np.empty(m.shape())
-    tp = 2.0 * np.pi
-    for b in range(m.nleaves):
-        x, y, z = m.cell_centers(b)
-        x = x + shift
-        rho = 1.0 + 0.3 * np.sin(tp * (x + 0.13)) * np.cos(tp * (y - 0.2)) + 0.1 * np.cos(tp * z)
-        vx = 0.2 + 0.3 * np.cos(tp * (x + y))
-        vy = 0.3 * np.sin(tp * (x - z))
-        vz = 0.25 * np.cos(tp * (y + 0.3 * x))
-        p = 1.0 + 0.25 * np.sin(tp * (y + z + 0.1 * x))
-        U[b] = _conserved(rho, vx, vy, vz, p)
-    return U
+def _flow(m):
+    return inputs.smooth_flow(m.leaves(), m.n, m.nrb, xmin=m.xmin, xmax=m.xmax)
 
 
 def test_extended_formulation_equals_roll_when_periodic():
