@@ -24,7 +24,7 @@ N = 256
 # sources of the stage kernels: the committed traffic counters are used only
 # while these are unchanged
 STAGE_SRCS = [os.path.join(ROOT, "paper_2202_12309_amd", "csrc", f)
-              for f in ("pkh_stage.hip", "pkh_device.h", "pkh_physics.h")]
+              for f in ("pkh_stage.hip", "pkh_device.h", "pkh_physics.h", "pkh_internal.h")]
 
 
 def stage_source_sha():
@@ -215,6 +215,49 @@ def amr_leg(cycles=200, regrid_every=10):
             "leaves_start": leaves0, "leaves_after_each_regrid": counts, "sim_time": t}
 
 
+def kh_leg(cycles=3000, regrid_every=10):
+    """Kelvin-Helmholtz shear layers with dynamic refinement: 64^3 root in
+    blocks of 16^3, up to level 2 (256^3 at the finest), seed amplitude 0.1.
+    The mesh is first adapted twice to the initial state by the device
+    density-jump indicator (refine above 0.02, derefine below 0.005); then
+    every 10 cycles the indicator sets the flags and the mesh is regridded.
+    Zone-cycles count the leaf cells of every cycle; the time includes the
+    indicator and the regrids."""
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+    blk, nrb = 16, (4, 4, 4)
+    n = (blk,) * 3
+    mesh = Mesh((64,) * 3, n, inputs.uniform_leaves(nrb), max_level=2)
+    for _ in range(2):
+        mesh.upload(inputs.kelvin_helmholtz(mesh.leaves(), n, nrb, amp=0.1))
+        mesh.flag_density_jump(0.02, 0.005)
+        mesh.regrid()
+    mesh.upload(inputs.kelvin_helmholtz(mesh.leaves(), n, nrb, amp=0.1))
+    mesh.sync()
+    leaves0 = mesh.nleaves
+    counts = []
+    zc = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(cycles // regrid_every):
+        zc += mesh.nleaves * blk ** 3 * regrid_every
+        mesh.step(regrid_every)
+        mesh.flag_density_jump(0.02, 0.005)  # waits for the cycles
+        mesh.regrid()
+        counts.append(mesh.nleaves)
+    mesh.sync()
+    el = time.perf_counter() - t0
+    t, dt, cyc = mesh.time()
+    mesh.close()
+    return {"workload": "Kelvin-Helmholtz, 64^3 root in 16^3 blocks, max level 2, seed 0.1, "
+                        "regrid every 10 cycles (density-jump flags 0.02 / 0.005)",
+            "cycles": cyc, "zone_cycles": zc, "seconds": round(el, 4),
+            "zone_cycles_per_s": zc / el, "leaves_start": leaves0,
+            "leaves_min": min(counts), "leaves_max": max(counts), "leaves_end": counts[-1],
+            "sim_time": t}
+
+
 def deep_amr_leg(cycles=10):
     """The paper's multilevel mesh: 256^3 root grid in blocks of 32^3, a
     centred cube of side 0.4 refined to level 3 (296, 1216, 1352 and 21952
@@ -343,6 +386,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-kh", action="store_true")
     ap.add_argument("--no-deep-amr", action="store_true",
                     help="skip the paper's four-level mesh (813M zones, ~130 GB of HBM)")
     ap.add_argument("--no-main", action="store_true",
@@ -374,7 +418,8 @@ def main():
                "config": {"workload": "main 256^3 leg skipped"}, "roofline": None}
     else:
         out = main_leg(args)
-    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None, "deep_amr": None})
+    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None, "kh_amr": None,
+                "deep_amr": None})
     if not args.no_adjoint:
         adj = adjoint_ratio()
         out["adjoint"] = adj
@@ -384,6 +429,9 @@ def main():
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batch"] = batch_leg()
+    if not args.no_kh:
+        torch.cuda.empty_cache()
+        out["kh_amr"] = kh_leg()
     if not args.no_deep_amr:
         torch.cuda.empty_cache()
         out["deep_amr"] = deep_amr_leg()

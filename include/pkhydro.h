@@ -179,16 +179,22 @@ int pkh_set_time(pkh_mesh *mesh, double t, int64_t cycle);
    +1 refine (Sec. 2.1, Sec. 3.8). Applied by pkh_regrid. */
 int pkh_set_refinement_flags(pkh_mesh *mesh, const int8_t *flags, int64_t n);
 
-/* Device refinement indicator (the paper leaves the criterion to the
-   application; Sec. 2.1, Sec. 3.8). Per leaf, eta = the largest
-   |P(i+e_d) - P(i-e_d)| / (P(i+e_d) + P(i-e_d)) over active cells i and
-   directions d (neighbour cells across a block face as for the stencil);
-   evaluated without
-   FMA contraction and with correctly rounded division. Sets the mesh's flags
-   to +1 where eta > refine_above, -1 where eta < derefine_below, else 0 (as
-   pkh_set_refinement_flags would) and, when non-NULL, copies them to
-   flags_out[n leaves] and eta to eta_out[n leaves] (host arrays, caller
-   owned). PKH_EINVAL if derefine_below > refine_above. Synchronises. */
+/* Device refinement indicators (the paper leaves the criterion to the
+   application; Sec. 2.1, Sec. 3.8). Per leaf, eta = the largest relative
+   jump |q(i+e_d) - q(i-e_d)| / (q(i+e_d) + q(i-e_d)) over active cells i
+   and directions d (neighbour cells across a block face as for the
+   stencil) of q = pressure (PKH_JUMP_PRESSURE: shocks, blasts) or density
+   (PKH_JUMP_DENSITY: contact and shear layers, where pressure is smooth);
+   evaluated without FMA contraction and with correctly rounded division.
+   Sets the mesh's flags to +1 where eta > refine_above, -1 where eta <
+   derefine_below, else 0 (as pkh_set_refinement_flags would) and, when
+   non-NULL, copies them to flags_out[n leaves] and eta to eta_out[n leaves]
+   (host arrays, caller owned). PKH_EINVAL for an unknown quantity or if
+   derefine_below > refine_above. Synchronises. */
+enum { PKH_JUMP_PRESSURE = 0, PKH_JUMP_DENSITY = 1 };
+int pkh_flag_jump(pkh_mesh *mesh, int32_t quantity, double refine_above, double derefine_below,
+                  int8_t *flags_out, double *eta_out);
+/* pkh_flag_jump with PKH_JUMP_PRESSURE. */
 int pkh_flag_pressure_jump(pkh_mesh *mesh, double refine_above, double derefine_below,
                            int8_t *flags_out, double *eta_out);
 

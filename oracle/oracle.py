@@ -201,27 +201,37 @@ class OracleMesh:
         if rc != 0:
             raise OracleError(f"orc_regrid failed with {rc}")
 
-    def pressure_jump(self):
-        """Refinement indicator per leaf (the paper leaves the criterion to
-        the application): the largest |P(i+e_d) - P(i-e_d)| / (P(i+e_d) +
-        P(i-e_d)) over active cells i and directions d, on the ghost-filled
-        block. Plain numpy, no FMA, IEEE division."""
+    def _jump(self, quantity):
         n1, n2, n3 = self.n
         g1 = self.gamma - 1.0
         eta = np.zeros(self.nleaves)
         for b in range(self.nleaves):
             u = self.padded(b)
-            ke = 0.5 * ((u[1] * u[1] + u[2] * u[2]) + u[3] * u[3]) / u[0]
-            p = g1 * (u[4] - ke)
+            if quantity == "pressure":
+                ke = 0.5 * ((u[1] * u[1] + u[2] * u[2]) + u[3] * u[3]) / u[0]
+                q = g1 * (u[4] - ke)
+            else:
+                q = u[0]
             a = slice(2, -2)
             jumps = []
             for lo, hi in (((a, a, slice(1, n1 + 1)), (a, a, slice(3, n1 + 3))),
                            ((a, slice(1, n2 + 1), a), (a, slice(3, n2 + 3), a)),
                            ((slice(1, n3 + 1), a, a), (slice(3, n3 + 3), a, a))):
-                pm, pp = p[lo], p[hi]
-                jumps.append((np.abs(pp - pm) / (pp + pm)).max())
+                qm, qp = q[lo], q[hi]
+                jumps.append((np.abs(qp - qm) / (qp + qm)).max())
             eta[b] = max(jumps)
         return eta
+
+    def pressure_jump(self):
+        """Refinement indicator per leaf (the paper leaves the criterion to
+        the application): the largest |P(i+e_d) - P(i-e_d)| / (P(i+e_d) +
+        P(i-e_d)) over active cells i and directions d, on the ghost-filled
+        block. Plain numpy, no FMA, IEEE division."""
+        return self._jump("pressure")
+
+    def density_jump(self):
+        """The same indicator on the density (contact and shear layers)."""
+        return self._jump("density")
 
     def cell_centers(self, b):
         """Cell-centre coordinates (x, y, z) of leaf b, each [n3][n2][n1]."""

@@ -65,6 +65,8 @@ _SIGS = {
     "pkh_regrid": (C.c_int, [C.c_void_p]),
     "pkh_flag_pressure_jump": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(C.c_int8),
                                          C.POINTER(C.c_double)]),
+    "pkh_flag_jump": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_int8),
+                                C.POINTER(C.c_double)]),
     "pkh_conserved_totals": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pkh_sync": (C.c_int, [C.c_void_p]),
     "pkh_kernel_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
@@ -142,6 +144,8 @@ def _as_locs(leaves):
 
 # Boundary kinds per face (pkh_config.bc: x-, x+, y-, y+, z-, z+).
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+# Quantities of the jump refinement indicator.
+JUMP_PRESSURE, JUMP_DENSITY = 0, 1
 
 
 class Mesh:
@@ -316,16 +320,23 @@ class Mesh:
         f = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
         _check(lib().pkh_set_refinement_flags(self._h, f.ctypes.data_as(C.POINTER(C.c_int8)), len(f)))
 
-    def flag_pressure_jump(self, refine_above, derefine_below):
-        """Set the flags from the device pressure-jump indicator; returns
-        (flags int8[nleaves], eta float64[nleaves]) in storage order."""
+    def flag_jump(self, quantity, refine_above, derefine_below):
+        """Set the flags from the device jump indicator of quantity
+        (JUMP_PRESSURE or JUMP_DENSITY); returns (flags int8[nleaves], eta
+        float64[nleaves]) in storage order."""
         n = self.nleaves
         f = np.zeros(n, dtype=np.int8)
         eta = np.zeros(n, dtype=np.float64)
-        _check(lib().pkh_flag_pressure_jump(self._h, float(refine_above), float(derefine_below),
-                                            f.ctypes.data_as(C.POINTER(C.c_int8)),
-                                            eta.ctypes.data_as(C.POINTER(C.c_double))))
+        _check(lib().pkh_flag_jump(self._h, int(quantity), float(refine_above), float(derefine_below),
+                                   f.ctypes.data_as(C.POINTER(C.c_int8)),
+                                   eta.ctypes.data_as(C.POINTER(C.c_double))))
         return f, eta
+
+    def flag_pressure_jump(self, refine_above, derefine_below):
+        return self.flag_jump(JUMP_PRESSURE, refine_above, derefine_below)
+
+    def flag_density_jump(self, refine_above, derefine_below):
+        return self.flag_jump(JUMP_DENSITY, refine_above, derefine_below)
 
     def regrid(self, flags=None):
         if flags is not None:

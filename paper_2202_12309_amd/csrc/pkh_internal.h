@@ -125,7 +125,7 @@ hipError_t launch_totals(double* partial, double* out, const double* u, const Bl
                          int32_t nblocks, const Geom& g, hipStream_t s);
 // Pressure-jump indicator per leaf into eta[nblocks] (ghost-filled u).
 hipError_t launch_eta(double* eta, const double* u, const int32_t* nbr, int32_t nblocks, const Geom& g,
-                      hipStream_t s);
+                      int32_t quantity, hipStream_t s);
 // Regrid: new leaf r takes kind[r] (0 copy, 1 child of a refined leaf,
 // 2 merged parent) from old leaf src[r].
 hipError_t launch_regrid_data(double* unew, const BlockInfo* bnew, const int32_t* kind,

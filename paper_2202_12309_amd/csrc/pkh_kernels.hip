@@ -690,11 +690,12 @@ hipError_t launch_totals(double* partial, double* out, const double* u, const Bl
 }
 
 // ---------------------------------------------------------------------------
-// Pressure-jump refinement indicator: per leaf, the largest relative jump
-// |P(i+e_d) - P(i-e_d)| / (P(i+e_d) + P(i-e_d)) over active cells and
-// directions, on the ghost-filled state. Evaluated without contraction and
-// with correctly rounded division, so a threshold test on it decides the
-// same way as the plain expression evaluated on a CPU.
+// Jump refinement indicator: per leaf, the largest relative jump
+// |q(i+e_d) - q(i-e_d)| / (q(i+e_d) + q(i-e_d)) over active cells and
+// directions, on the ghost-filled state, of q = pressure (quantity 0) or
+// density (quantity 1). Evaluated without contraction and with correctly
+// rounded division, so a threshold test on it decides the same way as the
+// plain expression evaluated on a CPU.
 // ---------------------------------------------------------------------------
 
 __device__ double pressure_nc(const double* c, int64_t vs, double gm1) {
@@ -704,7 +705,8 @@ __device__ double pressure_nc(const double* c, int64_t vs, double gm1) {
   return gm1 * (e - ke);
 }
 
-__global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, const int32_t* nbr, Geom g) {
+__global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, const int32_t* nbr, Geom g,
+                                                  int quantity) {
 #pragma clang fp contract(off)
   __shared__ double sRed[4];
   const int b = blockIdx.x;
@@ -720,8 +722,8 @@ __global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, 
       const int im = i - (d == 0), jm = j - (d == 1), km = k - (d == 2);
       const double* cp = u + nb_index(g, nbr, b, ip, jp, kp);
       const double* cm = u + nb_index(g, nbr, b, im, jm, km);
-      const double pp = pressure_nc(cp, g.vstride, gm1);
-      const double pm = pressure_nc(cm, g.vstride, gm1);
+      const double pp = quantity ? cp[0] : pressure_nc(cp, g.vstride, gm1);
+      const double pm = quantity ? cm[0] : pressure_nc(cm, g.vstride, gm1);
       mx = fmax(mx, fabs(pp - pm) / (pp + pm));
     }
   }
@@ -733,8 +735,8 @@ __global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, 
 }
 
 hipError_t launch_eta(double* eta, const double* u, const int32_t* nbr, int32_t nblocks, const Geom& g,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(eta_kernel, dim3(nblocks), dim3(256), 0, s, eta, u, nbr, g);
+                      int32_t quantity, hipStream_t s) {
+  hipLaunchKernelGGL(eta_kernel, dim3(nblocks), dim3(256), 0, s, eta, u, nbr, g, (int)quantity);
   return hipGetLastError();
 }
 

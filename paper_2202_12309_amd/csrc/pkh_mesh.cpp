@@ -774,27 +774,34 @@ int pkh_set_refinement_flags(pkh_mesh* m, const int8_t* flags, int64_t n) {
   return PKH_OK;
 }
 
-int pkh_flag_pressure_jump(pkh_mesh* m, double refine_above, double derefine_below, int8_t* flags_out,
-                           double* eta_out) {
+int pkh_flag_jump(pkh_mesh* m, int32_t quantity, double refine_above, double derefine_below, int8_t* flags_out,
+                  double* eta_out) {
   if (!m) return fail(PKH_EINVAL, "null mesh");
+  if (quantity != PKH_JUMP_PRESSURE && quantity != PKH_JUMP_DENSITY)
+    return fail(PKH_EINVAL, "quantity must be PKH_JUMP_PRESSURE or PKH_JUMP_DENSITY");
   if (!(derefine_below <= refine_above)) return fail(PKH_EINVAL, "derefine threshold above refine threshold");
   int rc;
   if (!m->ghosts_valid && (rc = do_exchange(m))) return rc;
   if ((rc = ensure_partials(m))) return rc;
   const int64_t nb = m->nb();
   std::vector<double> eta(nb);
-  HIPCHK(launch_eta(m->d_partial, m->A, m->d_nbr, (int32_t)nb, m->g, m->stream));
+  HIPCHK(launch_eta(m->d_partial, m->A, m->d_nbr, (int32_t)nb, m->g, quantity, m->stream));
   HIPCHK(hipMemcpyAsync(eta.data(), m->d_partial, nb * sizeof(double), hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
   if ((rc = check_err(m))) return rc;
   m->flags.assign(nb, 0);
   for (int64_t b = 0; b < nb; ++b) {
-    if (!(eta[b] == eta[b])) return fail(PKH_EPHYS, "non-finite pressure jump in leaf %lld", (long long)b);
+    if (!(eta[b] == eta[b])) return fail(PKH_EPHYS, "non-finite jump indicator in leaf %lld", (long long)b);
     m->flags[b] = eta[b] > refine_above ? 1 : (eta[b] < derefine_below ? -1 : 0);
   }
   if (flags_out) std::copy(m->flags.begin(), m->flags.end(), flags_out);
   if (eta_out) std::copy(eta.begin(), eta.end(), eta_out);
   return PKH_OK;
+}
+
+int pkh_flag_pressure_jump(pkh_mesh* m, double refine_above, double derefine_below, int8_t* flags_out,
+                           double* eta_out) {
+  return pkh_flag_jump(m, PKH_JUMP_PRESSURE, refine_above, derefine_below, flags_out, eta_out);
 }
 
 int pkh_regrid(pkh_mesh* m) {

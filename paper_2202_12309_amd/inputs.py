@@ -224,6 +224,27 @@ def smooth_flow(leaves, n, nrb, gamma=5.0 / 3.0, xmin=(0, 0, 0), xmax=(1, 1, 1))
     return U
 
 
+def kelvin_helmholtz(leaves, n, nrb, seed=8, gamma=5.0 / 3.0, drho=1.0, u0=0.5, width=0.05,
+                     amp=0.01, sigma=0.2, noise=1e-3, p0=2.5):
+    """Two smoothed shear layers at y = 1/4 and 3/4 in a periodic unit box:
+    density 1 outside and 1 + drho between them, x velocity -u0 outside and
+    +u0 between them (tanh profiles of the given width), a single-mode y
+    velocity seed amp sin(2 pi x) localised on the layers (Gaussian of width
+    sigma), uniform pressure p0, and keyed white noise of size noise on the
+    z velocity so the flow leaves the plane."""
+    U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    tp = 2.0 * np.pi
+    for b, lf in enumerate(leaves):
+        x, y, z = cell_centers(lf, n, nrb)
+        prof = np.tanh((y - 0.25) / width) - np.tanh((y - 0.75) / width)
+        rho = 1.0 + 0.5 * drho * prof
+        vx = u0 * (prof - 1.0)
+        vy = amp * np.sin(tp * x) * (np.exp(-((y - 0.25) / sigma) ** 2) + np.exp(-((y - 0.75) / sigma) ** 2))
+        vz = noise * normals(seed, 3, global_index(lf, n, nrb)) if noise else 0.0 * x
+        U[b] = _to_conserved(rho, vx, vy, vz, np.full_like(x, p0), gamma)
+    return U
+
+
 def _smoothed_field(N, seed, field, sigma=4.0, trunc=12):
     """Unit-variance, zero-mean periodic field: keyed white noise convolved
     with a separable Gaussian (sigma cells, truncated at +-trunc cells)."""

@@ -315,6 +315,47 @@ def test_pressure_jump_step_and_flags():
     assert np.all(flags == 1)
 
 
+def _density_state(m, rfun, p=1.3):
+    """Uniform pressure at rest with density rfun(x, y, z) at the cell centres."""
+    U = np.zeros(m.shape())
+    for b in range(m.nleaves):
+        x, y, z = m.cell_centers(b)
+        U[b, 0] = rfun(x, y, z)
+        U[b, 4] = p / (m.gamma - 1.0)
+    return U
+
+
+def test_density_jump_pins():
+    """The density indicator: zero on a uniform density (pressure jumps do
+    not enter), s dy / (a + s y) at the lowest cell of each leaf on a linear
+    density a + s y (two levels, away from the periodic seam), and exactly
+    |r2 - r1| / (r2 + r1) at a density step across a level-0 face."""
+    m = _amr_mesh()
+    U = _density_state(m, lambda x, y, z: 0.8 + 0 * x)
+    U[:, 4] *= np.where(np.arange(m.nleaves) % 2 == 0, 1.0, 3.0)[:, None, None, None]
+    m.set_state(U)
+    assert np.all(m.density_jump() == 0.0)
+    assert m.pressure_jump().max() > 0.1
+    a, s = 1.5, 0.6
+    m.set_state(_density_state(m, lambda x, y, z: a + s * y))
+    eta = m.density_jump()
+    checked = 0
+    for b, (lev, lx, ly, lz) in enumerate(m.leaves()):
+        ny = NRB4[1] << lev
+        if ly == 0 or ly == ny - 1:
+            continue
+        dy = 1.0 / (NRB4[1] * N8[1] * (1 << lev))
+        want = s * dy / (a + s * (ly * N8[1] + 0.5) * dy)
+        assert abs(eta[b] - want) <= 1e-13 * want, (b, eta[b], want)
+        checked += 1
+    assert checked > 40
+    r1, r2 = 1.0, 2.0
+    nrb = (2, 4, 2)
+    m = OracleMesh(N8, nrb, inputs.uniform_leaves(nrb), xmax=(1.0, 2.0, 1.0))
+    m.set_state(_density_state(m, lambda x, y, z: np.where(y < 1.0, r1, r2)))
+    assert np.all(m.density_jump() == (r2 - r1) / (r2 + r1))
+
+
 def test_paper_multilevel_mesh_block_counts():
     """The leaf generator reproduces the paper's multilevel mesh (the cube
     centred in the box, 2:1 balance over face, edge and corner neighbours)."""
