@@ -258,6 +258,36 @@ def kh_leg(cycles=3000, regrid_every=10):
             "sim_time": t}
 
 
+def packs_leg(cycles=20, warmup=3):
+    """The paper's MeshBlockPack knob on the 256^3 turbulent box: each stage
+    launched once per pack of contiguous leaves (packs = 1 is one launch
+    over all leaves), for blocks of 32^3 (512 leaves) and 16^3 (4096
+    leaves). Zone-cycles/s per pack count, HIP events on the mesh stream."""
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+    out = {"workload": "256^3 turbulent box (seed 2), 20 cycles per point"}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for blk, packs in ((32, (1, 2, 4, 8, 16, 64, 512)), (16, (1, 4, 16, 64, 256, 1024, 4096))):
+        n = (blk,) * 3
+        nrb = (N // blk,) * 3
+        mesh = Mesh((N,) * 3, n, inputs.uniform_leaves(nrb))
+        mesh.upload(inputs.turbulent_box(mesh.leaves(), n, nrb, seed=2))
+        res = {}
+        for P in packs:
+            mesh.set_tuning(0, P)
+            mesh.step(warmup)
+            torch.cuda.synchronize()
+            ev0.record(mesh.stream)
+            mesh.step(cycles)
+            ev1.record(mesh.stream)
+            ev1.synchronize()
+            res[str(P)] = N ** 3 * cycles / (ev0.elapsed_time(ev1) / 1e3)
+        out[f"block_{blk}"] = res
+        mesh.close()
+    return out
+
+
 def deep_amr_leg(cycles=10):
     """The paper's multilevel mesh: 256^3 root grid in blocks of 32^3, a
     centred cube of side 0.4 refined to level 3 (296, 1216, 1352 and 21952
@@ -387,6 +417,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--no-kh", action="store_true")
+    ap.add_argument("--packs-sweep", action="store_true",
+                    help="also sweep the number of stage launches per stage (MeshBlockPacks)")
     ap.add_argument("--no-deep-amr", action="store_true",
                     help="skip the paper's four-level mesh (813M zones, ~130 GB of HBM)")
     ap.add_argument("--no-main", action="store_true",
@@ -418,7 +450,7 @@ def main():
                "config": {"workload": "main 256^3 leg skipped"}, "roofline": None}
     else:
         out = main_leg(args)
-    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None, "kh_amr": None,
+    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None, "packs_sweep": None, "kh_amr": None,
                 "deep_amr": None})
     if not args.no_adjoint:
         adj = adjoint_ratio()
@@ -429,6 +461,9 @@ def main():
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batch"] = batch_leg()
+    if args.packs_sweep:
+        torch.cuda.empty_cache()
+        out["packs_sweep"] = packs_leg()
     if not args.no_kh:
         torch.cuda.empty_cache()
         out["kh_amr"] = kh_leg()

@@ -269,11 +269,19 @@ int pkh_batch_autotune(pkh_batch *batch, int32_t trial_cycles, int32_t *tile_row
 /* Launch tuning of the stage kernels (set by the caller or an autotuner).
    tile_rows: rows of cells per workgroup tile (0 = default). Compiled
    choices: n1 = 8: 8; n1 = 16: 8, 16, 4; n1 = 32: 8, 4, 16; n1 = 64: 4, 2.
-   It must divide nblock[1]. The results do not depend on it (each face
-   flux is computed by the same arithmetic whatever the tile). */
+   It must divide nblock[1].
+   packs: launches per stage (0 or 1: one launch over every leaf). With
+   packs = P > 1 the leaves (in storage order) are cut into P contiguous
+   ranges of nearly equal count and each stage is launched once per range,
+   in order: the paper's number of MeshBlockPacks (Sec. 3.6, Sec. 5.1). At
+   most the leaf count.
+   The results depend on neither (each face flux is computed by the same
+   arithmetic whatever the tile or pack, and the CFL reduction is an
+   order-free maximum). */
 typedef struct {
   int32_t tile_rows;
-  int32_t reserved[3];
+  int32_t packs;
+  int32_t reserved[2];
 } pkh_tuning;
 int pkh_set_tuning(pkh_mesh *mesh, const pkh_tuning *tuning);
 int pkh_get_tuning(const pkh_mesh *mesh, pkh_tuning *tuning);

@@ -36,7 +36,7 @@ class Config(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("tile_rows", C.c_int32), ("reserved", C.c_int32 * 3)]
+    _fields_ = [("tile_rows", C.c_int32), ("packs", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class Loc(C.Structure):
@@ -281,9 +281,10 @@ class Mesh:
         _check(lib().pkh_conserved_totals(self._h, out))
         return np.array(out[:])
 
-    def set_tuning(self, tile_rows=0):
+    def set_tuning(self, tile_rows=0, packs=1):
         t = Tuning()
         t.tile_rows = int(tile_rows)
+        t.packs = int(packs)
         _check(lib().pkh_set_tuning(self._h, C.byref(t)))
 
     def autotune(self, trial_cycles=3):
@@ -296,7 +297,7 @@ class Mesh:
     def tuning(self):
         t = Tuning()
         _check(lib().pkh_get_tuning(self._h, C.byref(t)))
-        return {"tile_rows": t.tile_rows}
+        return {"tile_rows": t.tile_rows, "packs": t.packs}
 
     KT_PREDICTOR, KT_CORRECTOR, KT_FILL, KT_FLUXCORR, KT_ADJOINT = 1, 2, 4, 8, 16
 

@@ -73,7 +73,8 @@ struct StageLaunch {
   const double* ubase;
   double* uout;
   const BlockInfo* blocks;
-  int32_t nblocks;
+  int32_t nblocks;    // leaves this launch covers: b0 .. b0 + nblocks - 1
+  int32_t b0;
   Geom g;
   DevTime* tm;
   double beta;
@@ -82,8 +83,9 @@ struct StageLaunch {
   double* fbuf;       // face buffers (may be null on single-level meshes)
   // Same-level neighbour of each leaf per direction, [leaf][27] with index
   // (dz+1)*9 + (dy+1)*3 + (dx+1), -1 where the neighbour is not a same-level
-  // leaf. The stage kernel writes every updated cell that a same-level
-  // neighbour needs as a ghost straight into that neighbour's ghost zone.
+  // leaf. The stage kernel reads halo cells beyond a block face from the
+  // neighbour's active cells through it (from the leaf's own ghost zone
+  // where it is -1).
   const int32_t* nbr;
   int32_t tj;         // rows per tile (0: default)
 };

@@ -207,6 +207,7 @@ struct pkh_mesh {
   std::vector<int8_t> flags;
   bool ghosts_valid = false;
   int32_t tj = 0;
+  int32_t packs = 1;  // stage launches per stage (contiguous leaf ranges)
   // kernel timing: event pairs around launches of the selected kinds
   uint32_t kt_mask = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -479,6 +480,17 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
   s.fbuf = m->d_fbuf;
   s.nbr = m->d_nbr;
   s.tj = m->tj;
+  // one launch per pack: leaves [p nb / P, (p+1) nb / P)
+  const int32_t P = std::max(1, std::min(m->packs, nb));
+  auto launch_packs = [&](StageLaunch st) -> hipError_t {
+    for (int32_t p = 0; p < P; ++p) {
+      st.b0 = (int32_t)((int64_t)p * nb / P);
+      st.nblocks = (int32_t)((int64_t)(p + 1) * nb / P) - st.b0;
+      const hipError_t e = launch_stage(st, m->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   // predictor: U* = U^n - dt/2 D(U^n)
   s.uin = m->A;
   s.ubase = m->A;
@@ -488,7 +500,7 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
   s.do_dt = 0;
   {
     KTimer kt(m, 0, capturing);
-    HIPCHK(launch_stage(s, m->stream));
+    HIPCHK(launch_packs(s));
   }
   if (m->ncblocks) {
     KTimer kt(m, 3, capturing);
@@ -509,7 +521,7 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
   s.do_dt = 1;
   {
     KTimer kt(m, 1, capturing);
-    HIPCHK(launch_stage(s, m->stream));
+    HIPCHK(launch_packs(s));
   }
   if (m->ncblocks) {
     KTimer kt(m, 3, capturing);
@@ -954,8 +966,11 @@ int pkh_set_tuning(pkh_mesh* m, const pkh_tuning* t) {
   if (stage_tile_rows(m->g.n1, m->g.n2, t->tile_rows) < 0)
     return fail(PKH_EINVAL, "tile_rows %d not available for blocks of %d x %d", t->tile_rows, m->g.n1,
                 m->g.n2);
-  if (t->tile_rows != m->tj) drop_graph(m);
+  if (t->packs < 0) return fail(PKH_EINVAL, "packs must be >= 0");
+  const int32_t packs = std::max<int32_t>(1, t->packs);
+  if (t->tile_rows != m->tj || packs != m->packs) drop_graph(m);
   m->tj = t->tile_rows;
+  m->packs = packs;
   return PKH_OK;
 }
 
@@ -963,6 +978,7 @@ int pkh_get_tuning(const pkh_mesh* m, pkh_tuning* t) {
   if (!m || !t) return fail(PKH_EINVAL, "null argument");
   *t = pkh_tuning{};
   t->tile_rows = stage_tile_rows(m->g.n1, m->g.n2, m->tj, m->nb());
+  t->packs = m->packs;
   return PKH_OK;
 }
 
@@ -1513,6 +1529,7 @@ int pkh_autotune(pkh_mesh* m, int32_t trial_cycles, pkh_tuning* out) {
   if (out) {
     *out = pkh_tuning{};
     out->tile_rows = best;
+    out->packs = m->packs;
   }
   return PKH_OK;
 }

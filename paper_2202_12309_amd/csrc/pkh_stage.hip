@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAV
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   const int blk = wg / ntj;
   if (blk >= a.nblocks) return;
-  stage_tile<RECON, N1, TJ>(a, blk, (wg - blk * ntj) * TJ, wg);
+  stage_tile<RECON, N1, TJ>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg);
 }
 
 // Grouped launch: the tiles of many independent meshes (same block width

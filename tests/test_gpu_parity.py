@@ -274,3 +274,29 @@ def test_amr_regrid_parity():
     gm.step(3)
     om.step(3)
     assert np.all(rel_err(gm.download(), om.state(), G) <= 1e-12)
+
+
+def test_packs_do_not_change_results():
+    """One stage launch per pack of contiguous leaves (the paper's
+    MeshBlockPacks) gives bitwise the result of one launch over every leaf,
+    on a two-level mesh with flux correction and level-jump fills, and
+    packs beyond the leaf count are clamped to one leaf per pack."""
+    print_case("packs 1 / 3 / 7 / leaf count, two-level blast 64^3 root in 16^3 blocks, 5 cycles")
+    from paper_2202_12309_amd.binding import Mesh, PkhError
+    n, nrb = (16, 16, 16), (4, 4, 4)
+    lv = inputs.sphere_refined_leaves(nrb, radius=0.3)
+    outs = []
+    for P in (1, 3, 7, 100000):
+        gm = Mesh((64, 64, 64), n, lv, max_level=1)
+        gm.set_tuning(0, P)
+        assert gm.tuning()["packs"] == P
+        gm.upload(inputs.blast(gm.leaves(), n, nrb))
+        gm.step(5)
+        outs.append(gm.download())
+        gm.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    gm = Mesh((64, 64, 64), n, lv, max_level=1)
+    with pytest.raises(PkhError):
+        gm.set_tuning(0, -1)
+    gm.close()
