@@ -288,6 +288,46 @@ def packs_leg(cycles=20, warmup=3):
     return out
 
 
+def remote_leg(cycles=20, warmup=3):
+    """The multi-GPU data path on one GPU: the 256^3 turbulent box in 512
+    blocks of 32^3 cut into P contiguous Morton parts; same-level faces
+    between parts are packed, moved as one device copy per (sender,
+    receiver) pair and unpacked after each stage. Zone-cycles/s, the
+    exchange time per cycle and the bytes one exchange moves per cycle."""
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+    blk = 32
+    n = (blk,) * 3
+    nrb = (N // blk,) * 3
+    mesh = Mesh((N,) * 3, n, inputs.uniform_leaves(nrb))
+    mesh.upload(inputs.turbulent_box(mesh.leaves(), n, nrb, seed=2))
+    out = {"workload": "256^3 turbulent box (seed 2), 512 blocks of 32^3, 20 cycles per point"}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for P in (1, 2, 8, 64, 512):
+        mesh.set_partition(P)
+        info = mesh.partition()
+        mesh.step(warmup)
+        torch.cuda.synchronize()
+        ev0.record(mesh.stream)
+        mesh.step(cycles)
+        ev1.record(mesh.stream)
+        ev1.synchronize()
+        zcs = N ** 3 * cycles / (ev0.elapsed_time(ev1) / 1e3)
+        mesh.kernel_timing(Mesh.KT_REMOTE)
+        mesh.step(cycles)
+        kt = mesh.kernel_times()["remote"]
+        mesh.kernel_timing(0)
+        # two stages per cycle, 2 layers x 32^2 cells x 40 B per remote face
+        mbytes = 2 * info["remote_faces"] * 2 * blk * blk * 40
+        out[str(P)] = {"zone_cycles_per_s": zcs, "remote_faces": info["remote_faces"],
+                       "messages_per_stage": info["messages"],
+                       "exchange_ms_per_cycle": round(kt[0] / cycles, 4),
+                       "message_bytes_per_cycle": mbytes}
+    mesh.close()
+    return out
+
+
 def deep_amr_leg(cycles=10):
     """The paper's multilevel mesh: 256^3 root grid in blocks of 32^3, a
     centred cube of side 0.4 refined to level 3 (296, 1216, 1352 and 21952
@@ -417,6 +457,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--no-kh", action="store_true")
+    ap.add_argument("--remote-split", action="store_true",
+                    help="also time the pack / transfer / unpack path of a virtual partition")
     ap.add_argument("--packs-sweep", action="store_true",
                     help="also sweep the number of stage launches per stage (MeshBlockPacks)")
     ap.add_argument("--no-deep-amr", action="store_true",
@@ -461,6 +503,9 @@ def main():
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batch"] = batch_leg()
+    if args.remote_split:
+        torch.cuda.empty_cache()
+        out["remote_split"] = remote_leg()
     if args.packs_sweep:
         torch.cuda.empty_cache()
         out["packs_sweep"] = packs_leg()

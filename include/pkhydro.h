@@ -266,6 +266,24 @@ int pkh_batch_step(pkh_batch *batch, int32_t n_cycles, uint32_t mode);
    NULL. Synchronises. */
 int pkh_batch_autotune(pkh_batch *batch, int32_t trial_cycles, int32_t *tile_rows);
 
+/* Virtual partition for the multi-GPU data path on one GPU (Sec. 3.7: the
+   communication buffers of faces whose neighbour lives on another rank).
+   The leaves in storage order are cut into nparts contiguous ranges of
+   nearly equal count (the Morton distribution of Sec. 2.1). A same-level
+   face between two parts is remote: after each stage (and its flux
+   correction) the sender's two cell layers next to every remote face are
+   packed into a buffer grouped by (sender part, receiver part), each
+   group moves as one device copy (the stand-in for the peer transfer), and
+   an unpack kernel writes them into the receiver's ghost layers, which the
+   stage kernels then read. Faces inside a part keep the direct reads.
+   Results are bitwise those of nparts = 1. nparts in [1, number of leaves];
+   the partition survives regrids (recut over the new leaves). A
+   partitioned mesh takes no tape or batch (PKH_EINVAL). Synchronises. */
+int pkh_set_partition(pkh_mesh *mesh, int32_t nparts);
+/* Current parts, remote faces and (sender, receiver) messages per stage;
+   any pointer may be NULL. */
+int pkh_get_partition(const pkh_mesh *mesh, int32_t *nparts, int32_t *nremote, int32_t *nmessages);
+
 /* Launch tuning of the stage kernels (set by the caller or an autotuner).
    tile_rows: rows of cells per workgroup tile (0 = default). Compiled
    choices: n1 = 8: 8; n1 = 16: 8, 16, 4; n1 = 32: 8, 4, 16; n1 = 64: 4, 2.
@@ -300,13 +318,15 @@ enum {
   PKH_KT_CORRECTOR = 2u, /* stage-2 kernel (with the fused CFL reduction) */
   PKH_KT_FILL = 4u,      /* ghost fill kernel (faces across level jumps) */
   PKH_KT_FLUXCORR = 8u,  /* fine-coarse flux correction kernel */
-  PKH_KT_ADJOINT = 16u   /* reverse sweep of one stage (pkh_adjoint) */
+  PKH_KT_ADJOINT = 16u,  /* reverse sweep of one stage (pkh_adjoint) */
+  PKH_KT_REMOTE = 32u,   /* pack, transfer and unpack of remote faces */
+  PKH_KT_KINDS = 6
 };
 int pkh_kernel_timing(pkh_mesh *mesh, uint32_t kinds);
 /* Per kind index (0 predictor, 1 corrector, 2 fill, 3 flux correction,
-   4 adjoint stage): summed bracketed duration in milliseconds and the
-   number of launches since the mask was set. ms[5], count[5].
-   Synchronises. */
+   4 adjoint stage, 5 remote faces): summed bracketed duration in
+   milliseconds and the number of bracketed launches since the mask was
+   set. ms[PKH_KT_KINDS], count[PKH_KT_KINDS]. Synchronises. */
 int pkh_kernel_times(pkh_mesh *mesh, double *ms, int64_t *count);
 
 /* Wait for the handle's stream and report any latched PKH_EPHYS. */

@@ -73,6 +73,9 @@ _SIGS = {
     "pkh_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
     "pkh_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
     "pkh_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "pkh_set_partition": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pkh_get_partition": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]),
     "pkh_last_error": (C.c_char_p, []),
     "pkh_tape_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "pkh_tape_destroy": (C.c_int, [C.c_void_p]),
@@ -299,7 +302,7 @@ class Mesh:
         _check(lib().pkh_get_tuning(self._h, C.byref(t)))
         return {"tile_rows": t.tile_rows, "packs": t.packs}
 
-    KT_PREDICTOR, KT_CORRECTOR, KT_FILL, KT_FLUXCORR, KT_ADJOINT = 1, 2, 4, 8, 16
+    KT_PREDICTOR, KT_CORRECTOR, KT_FILL, KT_FLUXCORR, KT_ADJOINT, KT_REMOTE = 1, 2, 4, 8, 16, 32
 
     def kernel_timing(self, kinds):
         _check(lib().pkh_kernel_timing(self._h, int(kinds)))
@@ -307,11 +310,21 @@ class Mesh:
     def kernel_times(self):
         """{kind: (total ms, launches)} for predictor, corrector, fill,
         fluxcorr and adjoint (one reverse stage)."""
-        ms = (C.c_double * 5)()
-        cnt = (C.c_int64 * 5)()
+        ms = (C.c_double * 6)()
+        cnt = (C.c_int64 * 6)()
         _check(lib().pkh_kernel_times(self._h, ms, cnt))
-        names = ("predictor", "corrector", "fill", "fluxcorr", "adjoint")
-        return {names[k]: (ms[k], cnt[k]) for k in range(5)}
+        names = ("predictor", "corrector", "fill", "fluxcorr", "adjoint", "remote")
+        return {names[k]: (ms[k], cnt[k]) for k in range(6)}
+
+    def set_partition(self, nparts):
+        """Cut the leaves into nparts contiguous ranges whose shared
+        same-level faces go through pack / transfer / unpack."""
+        _check(lib().pkh_set_partition(self._h, int(nparts)))
+
+    def partition(self):
+        p, r, g = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().pkh_get_partition(self._h, C.byref(p), C.byref(r), C.byref(g)))
+        return {"nparts": p.value, "remote_faces": r.value, "messages": g.value}
 
     # -- reverse mode ------------------------------------------------------------
     def tape(self, ckpt_every):

@@ -91,6 +91,20 @@ struct StageLaunch {
 };
 
 hipError_t launch_stage(const StageLaunch& a, hipStream_t s);
+
+// A same-level face between leaves of different parts of a partitioned mesh:
+// the receiving leaf, its face slot, the sending leaf. Its two ghost layers
+// travel through a buffer slot of 2 * 5 * (largest face area) doubles.
+struct RemoteFace {
+  int32_t recv, face, send, pad;
+};
+// Copy the sending leaves' two cell layers next to each remote face into
+// buf[rec * slot ...], layout [var][layer][t2][t1].
+hipError_t launch_remote_pack(const double* u, const RemoteFace* rf, int32_t nrf, const Geom& g, double* buf,
+                              int64_t slot, hipStream_t s);
+// Write buf[rec * slot ...] into the receiving leaves' ghost layers.
+hipError_t launch_remote_unpack(double* u, const RemoteFace* rf, int32_t nrf, const Geom& g, const double* buf,
+                                int64_t slot, hipStream_t s);
 // One work item of a grouped stage launch over many meshes.
 struct GroupItem {
   int32_t inst, blk, j0, pad;

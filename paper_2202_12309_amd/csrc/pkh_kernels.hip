@@ -383,6 +383,74 @@ hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Remote faces of a partitioned mesh (the buffers of Sec. 3.7 for faces
+// whose neighbour lives in another part): pack the sender's two cell layers
+// next to the face, and after the transfer unpack them into the receiver's
+// ghost layers. One thread per (layer, face cell), all five variables.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) remote_pack_kernel(const double* __restrict__ u, Geom g,
+                                                          const RemoteFace* __restrict__ rf,
+                                                          double* __restrict__ buf, int64_t slot) {
+  const RemoteFace r = rf[blockIdx.y];
+  const int d = r.face >> 1, hi = r.face & 1;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const int area = n[t1] * n[t2];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 2 * area) return;
+  const int s = q / area, rr = q - s * area;
+  int c[3];
+  c[t1] = rr % n[t1];
+  c[t2] = rr / n[t1];
+  // the receiver's ghost layer n + s (high face) or s - 2 (low face) is the
+  // sender's cell layer s or n - 2 + s
+  c[d] = hi ? s : n[d] - NG + s;
+  const double* src = u + (int64_t)r.send * g.bstride + pad_index(g, c[0], c[1], c[2]);
+  double* dst = buf + (int64_t)blockIdx.y * slot + q;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dst[(int64_t)v * 2 * area] = src[v * g.vstride];
+}
+
+__global__ void __launch_bounds__(256) remote_unpack_kernel(double* __restrict__ u, Geom g,
+                                                            const RemoteFace* __restrict__ rf,
+                                                            const double* __restrict__ buf, int64_t slot) {
+  const RemoteFace r = rf[blockIdx.y];
+  const int d = r.face >> 1, hi = r.face & 1;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const int area = n[t1] * n[t2];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 2 * area) return;
+  const int s = q / area, rr = q - s * area;
+  int c[3];
+  c[t1] = rr % n[t1];
+  c[t2] = rr / n[t1];
+  c[d] = hi ? n[d] + s : s - NG;
+  double* dst = u + (int64_t)r.recv * g.bstride + pad_index(g, c[0], c[1], c[2]);
+  const double* src = buf + (int64_t)blockIdx.y * slot + q;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dst[v * g.vstride] = src[(int64_t)v * 2 * area];
+}
+
+hipError_t launch_remote_pack(const double* u, const RemoteFace* rf, int32_t nrf, const Geom& g, double* buf,
+                              int64_t slot, hipStream_t s) {
+  if (nrf <= 0) return hipSuccess;
+  const int area = std::max(std::max(g.n1 * g.n2, g.n1 * g.n3), g.n2 * g.n3);
+  hipLaunchKernelGGL(remote_pack_kernel, dim3((2 * area + 255) / 256, nrf), dim3(256), 0, s, u, g, rf, buf, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_remote_unpack(double* u, const RemoteFace* rf, int32_t nrf, const Geom& g, const double* buf,
+                                int64_t slot, hipStream_t s) {
+  if (nrf <= 0) return hipSuccess;
+  const int area = std::max(std::max(g.n1 * g.n2, g.n1 * g.n3), g.n2 * g.n3);
+  hipLaunchKernelGGL(remote_unpack_kernel, dim3((2 * area + 255) / 256, nrf), dim3(256), 0, s, u, g, rf, buf,
+                     slot);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                        const LevelMaps& maps, DevTime* tm, int32_t skip_same, hipStream_t s) {
   const int ngc = 4 * g.p1 * g.p2 + 4 * g.n3 * g.p1 + 4 * g.n3 * g.n2;

@@ -200,6 +200,15 @@ struct pkh_mesh {
   bool need_fill = false;     // some ghost region has a neighbour at another level
   int32_t* d_jf = nullptr;    // (leaf, face) pairs whose face neighbour is on another level
   int32_t njf = 0;
+  // virtual partition into contiguous leaf ranges: same-level faces between
+  // parts go through pack / transfer / unpack instead of direct reads
+  int32_t nparts = 1;
+  RemoteFace* d_rf = nullptr;
+  int32_t nrf = 0;
+  double* d_send = nullptr;
+  double* d_recv = nullptr;
+  int64_t rf_slot = 0;                            // doubles per remote face
+  std::vector<std::array<int64_t, 2>> msgs;       // per (sender part, receiver part): first record, count
   double* d_partial = nullptr;
   double* d_tot = nullptr;
   size_t partial_cap = 0;
@@ -246,25 +255,39 @@ void drop_graph(pkh_mesh* m) {
   m->g_valid = false;
 }
 
-void free_tables(pkh_mesh* m) {
-  m->dfree(m->d_blocks);
-  m->dfree(m->d_map);
+// The tables one cycle uses besides the block list and level maps (rebuilt
+// on every regrid and partition change).
+void free_cycle_tables(pkh_mesh* m) {
   m->dfree(m->d_fbuf);
   m->dfree(m->d_ff);
   m->dfree(m->d_ff_first);
   m->dfree(m->d_cblocks);
   m->dfree(m->d_jf);
   m->dfree(m->d_nbr);
-  m->d_nbr = nullptr;
-  m->d_blocks = nullptr;
-  m->d_map = nullptr;
+  m->dfree(m->d_rf);
+  m->dfree(m->d_send);
+  m->dfree(m->d_recv);
   m->d_fbuf = nullptr;
   m->d_ff = nullptr;
   m->d_ff_first = nullptr;
   m->d_cblocks = nullptr;
   m->d_jf = nullptr;
+  m->d_nbr = nullptr;
+  m->d_rf = nullptr;
+  m->d_send = nullptr;
+  m->d_recv = nullptr;
   m->njf = 0;
   m->ncblocks = 0;
+  m->nrf = 0;
+  m->msgs.clear();
+}
+
+void free_tables(pkh_mesh* m) {
+  m->dfree(m->d_blocks);
+  m->dfree(m->d_map);
+  m->d_blocks = nullptr;
+  m->d_map = nullptr;
+  free_cycle_tables(m);
 }
 
 template <class T>
@@ -377,6 +400,31 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
         jf.push_back(f | kind << 3);
       }
   }
+  // remote faces of a partitioned mesh: a same-level face neighbour in another
+  // part is read from the ghost zone, which pack / transfer / unpack fill
+  std::vector<RemoteFace> rf;
+  std::vector<std::array<int64_t, 2>> msgs;
+  const int32_t P = dmap == &m->d_map ? std::max(1, std::min<int32_t>(m->nparts, (int32_t)nb)) : 1;
+  if (P > 1) {
+    std::vector<int32_t> part_of(nb);  // part p holds leaves [p nb / P, (p+1) nb / P)
+    for (int32_t p = 0; p < P; ++p)
+      for (int64_t b = (int64_t)p * nb / P; b < (int64_t)(p + 1) * nb / P; ++b) part_of[b] = p;
+    auto part = [&](int64_t b) { return part_of[b]; };
+    std::vector<std::vector<RemoteFace>> by_pair((size_t)P * P);
+    static const int slot[6] = {12, 14, 10, 16, 4, 22};
+    for (int64_t b = 0; b < nb; ++b)
+      for (int f = 0; f < 6; ++f) {
+        const int32_t s = nbr[b * 27 + slot[f]];
+        if (s >= 0 && part(s) != part(b)) by_pair[(size_t)part(s) * P + part(b)].push_back({(int32_t)b, f, s, 0});
+      }
+    for (const auto& v : by_pair) {
+      if (v.empty()) continue;
+      msgs.push_back({(int64_t)rf.size(), (int64_t)v.size()});
+      rf.insert(rf.end(), v.begin(), v.end());
+    }
+    for (const RemoteFace& r : rf) nbr[(int64_t)r.recv * 27 + slot[r.face]] = -1;
+    if (!rf.empty()) need_fill = true;
+  }
   // level maps
   std::vector<int32_t> flat;
   for (int L = 0; L <= t.maxl; ++L) {
@@ -403,6 +451,16 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
     m->need_fill = need_fill;
     m->njf = (int32_t)(jf.size() / 2);
     if (m->njf && (rc = upload_vec(m, &m->d_jf, jf))) return rc;
+    m->nrf = (int32_t)rf.size();
+    m->msgs = msgs;
+    m->rf_slot = 2 * (int64_t)NV * std::max({m->g.n1 * m->g.n2, m->g.n1 * m->g.n3, m->g.n2 * m->g.n3});
+    if (m->nrf) {
+      if ((rc = upload_vec(m, &m->d_rf, rf))) return rc;
+      const size_t bytes = (size_t)m->nrf * m->rf_slot * sizeof(double);
+      m->d_send = (double*)m->dalloc(bytes);
+      m->d_recv = (double*)m->dalloc(bytes);
+      if (!m->d_send || !m->d_recv) return fail(PKH_ENOMEM, "remote-face buffer allocation failed");
+    }
   }
   // the host vectors above are sources of asynchronous copies
   HIPCHK(hipStreamSynchronize(m->stream));
@@ -469,8 +527,23 @@ struct KTimer {
   }
 };
 
+// Ghost layers of the remote faces of state u: pack, one transfer per
+// (sender part, receiver part) message, unpack. On one GPU the transfer is a
+// device copy; across GPUs it would be the peer send / receive.
+int exchange_remote(pkh_mesh* m, double* u, bool capturing) {
+  if (!m->nrf) return PKH_OK;
+  KTimer kt(m, 5, capturing);
+  HIPCHK(launch_remote_pack(u, m->d_rf, m->nrf, m->g, m->d_send, m->rf_slot, m->stream));
+  for (const auto& msg : m->msgs)
+    HIPCHK(hipMemcpyAsync(m->d_recv + msg[0] * m->rf_slot, m->d_send + msg[0] * m->rf_slot,
+                          (size_t)msg[1] * m->rf_slot * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
+  HIPCHK(launch_remote_unpack(u, m->d_rf, m->nrf, m->g, m->d_recv, m->rf_slot, m->stream));
+  return PKH_OK;
+}
+
 // One cycle's kernels (the clock BEGIN of the cycle has been enqueued).
 int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = false) {
+  int rc;
   const int32_t nb = (int32_t)m->nb();
   StageLaunch s{};
   s.blocks = m->d_blocks;
@@ -508,6 +581,7 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
                                m->ncblocks, m->g, m->d_time, 0.5, 0, m->d_fbuf, m->d_nbr,
                                m->stream));
   }
+  if ((rc = exchange_remote(m, m->B, capturing))) return rc;
   if (m->njf) {  // ghost faces across level jumps (same-level halos are read directly)
     KTimer kt(m, 2, capturing);
     HIPCHK(launch_fill_faces(m->B, m->d_blocks, m->g, m->maps, m->d_time, m->d_jf, m->njf, m->stream));
@@ -529,6 +603,7 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
                                m->ncblocks, m->g, m->d_time, 1.0, 1, m->d_fbuf, m->d_nbr,
                                m->stream));
   }
+  if ((rc = exchange_remote(m, m->A, capturing))) return rc;
   if (m->njf) {
     KTimer kt(m, 2, capturing);
     HIPCHK(launch_fill_faces(m->A, m->d_blocks, m->g, m->maps, m->d_time, m->d_jf, m->njf, m->stream));
@@ -924,16 +999,7 @@ int pkh_regrid(pkh_mesh* m) {
   LevelMaps old_maps = m->maps;
   m->d_blocks = nullptr;
   m->d_map = nullptr;
-  m->dfree(m->d_fbuf);
-  m->dfree(m->d_ff);
-  m->dfree(m->d_ff_first);
-  m->dfree(m->d_cblocks);
-  m->dfree(m->d_nbr);
-  m->d_fbuf = nullptr;
-  m->d_ff = nullptr;
-  m->d_ff_first = nullptr;
-  m->d_cblocks = nullptr;
-  m->d_nbr = nullptr;
+  free_cycle_tables(m);
   m->tree = std::move(nt);
   int32_t *d_kind = nullptr, *d_src = nullptr;
   if ((rc = build_tables(m, m->h_blocks, &m->d_map, m->maps)) || (rc = alloc_state(m)) ||
@@ -974,6 +1040,31 @@ int pkh_set_tuning(pkh_mesh* m, const pkh_tuning* t) {
   return PKH_OK;
 }
 
+int pkh_set_partition(pkh_mesh* m, int32_t nparts) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  if (nparts < 1 || nparts > m->nb()) return fail(PKH_EINVAL, "nparts must be in [1, %lld]", (long long)m->nb());
+  if (nparts == m->nparts) return PKH_OK;
+  HIPCHK(hipStreamSynchronize(m->stream));  // queued work may use the tables
+  drop_graph(m);
+  m->nparts = nparts;
+  free_tables(m);
+  int rc;
+  if ((rc = build_tables(m, m->h_blocks, &m->d_map, m->maps))) return rc;
+  // ghost layers of faces that just became remote were never written by the
+  // direct-read path: fill them from the current state
+  if ((rc = exchange_remote(m, m->A, false))) return rc;
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return PKH_OK;
+}
+
+int pkh_get_partition(const pkh_mesh* m, int32_t* nparts, int32_t* nremote, int32_t* nmessages) {
+  if (!m) return fail(PKH_EINVAL, "null mesh");
+  if (nparts) *nparts = m->nparts;
+  if (nremote) *nremote = m->nrf;
+  if (nmessages) *nmessages = (int32_t)m->msgs.size();
+  return PKH_OK;
+}
+
 int pkh_get_tuning(const pkh_mesh* m, pkh_tuning* t) {
   if (!m || !t) return fail(PKH_EINVAL, "null argument");
   *t = pkh_tuning{};
@@ -985,7 +1076,7 @@ int pkh_get_tuning(const pkh_mesh* m, pkh_tuning* t) {
 int pkh_kernel_timing(pkh_mesh* m, uint32_t kinds) {
   if (!m) return fail(PKH_EINVAL, "null mesh");
   HIPCHK(hipStreamSynchronize(m->stream));
-  m->kt_mask = kinds & 31u;
+  m->kt_mask = kinds & 63u;
   m->kt_rec.clear();
   m->ev_used = 0;
   return PKH_OK;
@@ -994,7 +1085,7 @@ int pkh_kernel_timing(pkh_mesh* m, uint32_t kinds) {
 int pkh_kernel_times(pkh_mesh* m, double* ms, int64_t* count) {
   if (!m || !ms || !count) return fail(PKH_EINVAL, "null argument");
   HIPCHK(hipStreamSynchronize(m->stream));
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < PKH_KT_KINDS; ++k) {
     ms[k] = 0.0;
     count[k] = 0;
   }
