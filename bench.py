@@ -328,6 +328,56 @@ def remote_leg(cycles=20, warmup=3):
     return out
 
 
+def fp32_leg(steps=100, warmup=10, blk=32):
+    """The 256^3 cycle with the state stored in FP32 (FP64 arithmetic, each
+    stage rounding its output once): zone-cycles/s, stage-kernel times, the
+    algorithmic bytes (20 B per cell and state: corrector h*20 + 40, cycle
+    40 h + 60) and the distance from the FP64-stored run after the same
+    cycles."""
+    import numpy as np
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _helpers import rel_err  # per-variable error scales (no method arithmetic)
+    n = (blk,) * 3
+    nrb = (N // blk,) * 3
+    lv = inputs.uniform_leaves(nrb)
+    U0 = inputs.turbulent_box(lv, n, nrb, seed=2).astype(np.float32).astype(np.float64)
+    res = {}
+    for fp32 in (True, False):
+        mesh = Mesh((N,) * 3, n, lv, fp32_state=fp32)
+        mesh.upload(U0)
+        mesh.step(warmup)
+        mesh.sync()
+        mesh.kernel_timing(Mesh.KT_PREDICTOR | Mesh.KT_CORRECTOR)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(mesh.stream)
+        mesh.step(steps)
+        ev1.record(mesh.stream)
+        ev1.synchronize()
+        kt = mesh.kernel_times()
+        res[fp32] = (ev0.elapsed_time(ev1) / steps, kt, mesh.download())
+        mesh.close()
+    ms, kt, U32 = res[True]
+    h = 1.0 + 12.0 / blk
+    b_corr, b_cycle = h * 20.0 + 40.0, 40.0 * h + 60.0
+    corr_ms = kt["corrector"][0] / max(kt["corrector"][1], 1)
+    zcs = N ** 3 / (ms / 1e3)
+    return {"workload": f"hydro 256^3, 512 blocks of 32^3, FP32 state storage, FP64 arithmetic, "
+                        f"{warmup} + {steps} cycles",
+            "zone_cycles_per_s": zcs, "ms_per_step": round(ms, 4),
+            "kernel_avg_ms": {"predictor": round(kt["predictor"][0] / max(kt["predictor"][1], 1), 4),
+                              "corrector": round(corr_ms, 4)},
+            "bytes_per_zone_cycle": b_cycle,
+            "hbm_frac_cycle": round(zcs * b_cycle / (HBM_PEAK_GBS * 1e9), 4),
+            "corrector_hbm_frac": round(b_corr * N ** 3 / (corr_ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4),
+            "fp64_ms_per_step": round(res[False][0], 4),
+            "speedup_vs_fp64_storage": round(res[False][0] / ms, 3),
+            "rel_err_vs_fp64_storage": [float(x) for x in rel_err(U32, res[False][2], 5.0 / 3.0)]}
+
+
 def deep_amr_leg(cycles=10):
     """The paper's multilevel mesh: 256^3 root grid in blocks of 32^3, a
     centred cube of side 0.4 refined to level 3 (296, 1216, 1352 and 21952
@@ -457,6 +507,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--no-kh", action="store_true")
+    ap.add_argument("--fp32-storage", action="store_true",
+                    help="also run the 256^3 cycle with the state stored in FP32")
     ap.add_argument("--remote-split", action="store_true",
                     help="also time the pack / transfer / unpack path of a virtual partition")
     ap.add_argument("--packs-sweep", action="store_true",
@@ -503,6 +555,9 @@ def main():
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batch"] = batch_leg()
+    if args.fp32_storage:
+        torch.cuda.empty_cache()
+        out["fp32_storage"] = fp32_leg()
     if args.remote_split:
         torch.cuda.empty_cache()
         out["remote_split"] = remote_leg()

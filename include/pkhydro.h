@@ -68,7 +68,16 @@ enum { PKH_BC_PERIODIC = 0, PKH_BC_OUTFLOW = 1, PKH_BC_REFLECT = 2 };
 enum { PKH_RECON_DC = 0, PKH_RECON_PLM = 1 };
 enum { PKH_LIMITER_MC = 0 };
 /* pkh_config.flags */
-enum { PKH_FLAG_GRAPH = 1u /* replay captured cycles with hipGraphs */ };
+enum {
+  PKH_FLAG_GRAPH = 1u,     /* replay captured cycles with hipGraphs */
+  /* Store the state in FP32 (half the bytes): every stage widens its inputs
+     to FP64, computes in FP64 and rounds its output once to the nearest
+     float when storing it; the CFL and total reductions run in FP64 on the
+     stored values. Single-level periodic meshes with nblock[0] of 16 or 32;
+     no tape, batch, partition or refinement indicator. Upload rounds the
+     FP64 input to float, download widens. */
+  PKH_FLAG_FP32_STATE = 2u
+};
 
 /* Mesh configuration.
  *   nroot[d]   level-0 cells along d; a multiple of nblock[d].

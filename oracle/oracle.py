@@ -33,6 +33,7 @@ def lib():
         L.orc_nleaves.restype = C.c_int64
         L.orc_leaves.argtypes = [C.c_void_p, _I32]
         L.orc_set_state.argtypes = [C.c_void_p, _D]
+        L.orc_set_fp32.argtypes = [C.c_void_p, C.c_int32]
         L.orc_get_state.argtypes = [C.c_void_p, _D]
         L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_int64]
         L.orc_error.argtypes = [C.c_void_p]
@@ -105,7 +106,7 @@ class OracleMesh:
 
     def __init__(self, nblock, nroot_blocks, leaves, gamma=5.0 / 3.0, cfl=0.3,
                  xmin=(0.0, 0.0, 0.0), xmax=(1.0, 1.0, 1.0), max_level=0, stage1_recon=0,
-                 bc=(BC_PERIODIC,) * 6):
+                 bc=(BC_PERIODIC,) * 6, fp32_state=False):
         n = np.array(nblock, dtype=np.int32)
         nrb = np.array(nroot_blocks, dtype=np.int32)
         locs = np.ascontiguousarray(np.array(leaves, dtype=np.int32).reshape(-1, 4))
@@ -128,6 +129,8 @@ class OracleMesh:
         self.xmax = tuple(xmx)
         self.max_level = max_level
         self.bc = tuple(int(x) for x in bca)
+        if fp32_state:
+            lib().orc_set_fp32(h, 1)
 
     def __del__(self):
         h = getattr(self, "_h", None)

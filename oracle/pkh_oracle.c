@@ -24,6 +24,9 @@
  *     correction.
  *   - Sec. 3.8: periodic derefinement, tree rebuilt on (de)refinement.
  *   - Sec. 3.10: global reductions (the CFL timestep, conserved totals).
+ *   - Optional FP32 storage of the state: each stage computes in FP64 from
+ *     the stored values and rounds its output once to the nearest binary32
+ *     value (the state set by the caller is rounded the same way).
  *   - Boundaries of the domain, per face: periodic, outflow (zero-gradient:
  *     a ghost cell takes the value of the nearest cell inside) or
  *     reflecting (a ghost cell takes the value of its mirror image across
@@ -58,6 +61,7 @@ typedef struct {
   double gamma, cfl;
   int recon1;        /* stage-1 reconstruction: 0 donor cell, 1 PLM */
   int bc[6];         /* per face x-, x+, y-, y+, z-, z+: ORC_BC_* */
+  int fp32;          /* state stored in binary32 (rounded after each stage) */
   int64_t nl;        /* number of leaves */
   int32_t *loc;      /* [nl][4]: level, lx, ly, lz */
   double *U;         /* [nl][5][n3][n2][n1], conserved, active cells */
@@ -485,6 +489,7 @@ static int stage(orc_mesh *m, const double *Uin, const double *Ubase, double *Uo
             div += (Fz[fidx(m, 2, v, i, j, k + 1)] - Fz[fidx(m, 2, v, i, j, k)]) / dz;
             int64_t o = (((b * NV + v) * n3 + k) * n2 + j) * n1 + i;
             Uout[o] = Ubase[o] - coef * div;
+            if (m->fp32) Uout[o] = (double)(float)Uout[o];
           }
   }
   for (int64_t q = 0; q < m->nl * 3; ++q) free(F[q]);
@@ -670,6 +675,16 @@ void orc_leaves(void *h, int32_t *out) {
 void orc_set_state(void *h, const double *U) {
   orc_mesh *m = (orc_mesh *)h;
   memcpy(m->U, U, sizeof(double) * (size_t)(m->nl * NV * ncell(m)));
+  if (m->fp32)
+    for (int64_t q = 0; q < m->nl * NV * ncell(m); ++q) m->U[q] = (double)(float)m->U[q];
+}
+
+/* Store the state in binary32 from now on (rounds the current state). */
+void orc_set_fp32(void *h, int32_t on) {
+  orc_mesh *m = (orc_mesh *)h;
+  m->fp32 = on ? 1 : 0;
+  if (m->fp32)
+    for (int64_t q = 0; q < m->nl * NV * ncell(m); ++q) m->U[q] = (double)(float)m->U[q];
 }
 void orc_get_state(void *h, double *U) {
   orc_mesh *m = (orc_mesh *)h;

@@ -18,6 +18,7 @@ PKH_OK = 0
 _CODES = {-1: "PKH_EINVAL", -2: "PKH_ETILING", -3: "PKH_EBALANCE", -4: "PKH_ENOMEM",
           -5: "PKH_EHIP", -6: "PKH_EPHYS", -7: "PKH_ESTATE"}
 PKH_FLAG_GRAPH = 1
+PKH_FLAG_FP32_STATE = 2
 
 
 class PkhError(RuntimeError):
@@ -162,7 +163,7 @@ class Mesh:
 
     def __init__(self, nroot, nblock, leaves, gamma=5.0 / 3.0, cfl=0.3, xmin=(0.0, 0.0, 0.0),
                  xmax=(1.0, 1.0, 1.0), max_level=0, stage1_recon=0, graph=False, device=0,
-                 stream=None, torch_alloc=True, bc=(0,) * 6):
+                 stream=None, torch_alloc=True, bc=(0,) * 6, fp32_state=False):
         import torch
         self.torch = torch
         self.device = device
@@ -186,7 +187,7 @@ class Mesh:
         cfg.stage1_recon = int(stage1_recon)
         cfg.limiter = 0
         cfg.regrid_every = 0
-        cfg.flags = PKH_FLAG_GRAPH if graph else 0
+        cfg.flags = (PKH_FLAG_GRAPH if graph else 0) | (PKH_FLAG_FP32_STATE if fp32_state else 0)
         self.cfg = cfg
         self.n = tuple(int(x) for x in nblock)
         self._alloc = _TorchAllocator(device) if torch_alloc else None

@@ -69,9 +69,12 @@ struct FineFace {
 
 // ---- launch wrappers (defined in pkh_kernels.hip) ----
 struct StageLaunch {
-  const double* uin;
-  const double* ubase;
-  double* uout;
+  // state arrays: double, or float when fp32 is set (storage precision;
+  // the arithmetic is FP64 either way)
+  const void* uin;
+  const void* ubase;
+  void* uout;
+  int32_t fp32;
   const BlockInfo* blocks;
   int32_t nblocks;    // leaves this launch covers: b0 .. b0 + nblocks - 1
   int32_t b0;
@@ -132,12 +135,18 @@ hipError_t launch_flux_correct(double* u, const BlockInfo* blocks, const FineFac
                                const double* fbuf, const int32_t* nbr, hipStream_t s);
 hipError_t launch_dt(const double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                      DevTime* tm, hipStream_t s);
+hipError_t launch_dt(const float* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                     DevTime* tm, hipStream_t s);
 hipError_t launch_clock(DevTime* tm, int32_t mode, double t_end, hipStream_t s);
-hipError_t launch_scatter(double* u, const double* src, int32_t nblocks, const Geom& g,
-                          hipStream_t s);
-hipError_t launch_gather(double* dst, const double* u, int32_t nblocks, const Geom& g,
-                         hipStream_t s);
+// Upload (double -> stored type), download (stored type -> double), totals;
+// the float forms serve meshes whose state is stored in FP32.
+hipError_t launch_scatter(double* u, const double* src, int32_t nblocks, const Geom& g, hipStream_t s);
+hipError_t launch_scatter(float* u, const double* src, int32_t nblocks, const Geom& g, hipStream_t s);
+hipError_t launch_gather(double* dst, const double* u, int32_t nblocks, const Geom& g, hipStream_t s);
+hipError_t launch_gather(double* dst, const float* u, int32_t nblocks, const Geom& g, hipStream_t s);
 hipError_t launch_totals(double* partial, double* out, const double* u, const BlockInfo* blocks,
+                         int32_t nblocks, const Geom& g, hipStream_t s);
+hipError_t launch_totals(double* partial, double* out, const float* u, const BlockInfo* blocks,
                          int32_t nblocks, const Geom& g, hipStream_t s);
 // Pressure-jump indicator per leaf into eta[nblocks] (ghost-filled u).
 hipError_t launch_eta(double* eta, const double* u, const int32_t* nbr, int32_t nblocks, const Geom& g,

@@ -587,7 +587,8 @@ hipError_t launch_flux_correct(double* u, const BlockInfo* blocks, const FineFac
 // CFL reduction over the active cells (after exchange / regrid / upload).
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) dt_kernel(const double* u, const BlockInfo* blocks,
+template <typename S>
+__global__ void __launch_bounds__(256) dt_kernel(const S* u, const BlockInfo* blocks,
                                                  int nblocks, Geom g, DevTime* tm) {
   __shared__ double sRed[4];
   const int ncell = g.n1 * g.n2 * g.n3;
@@ -598,7 +599,7 @@ __global__ void __launch_bounds__(256) dt_kernel(const double* u, const BlockInf
   if (q < ncell && b < nblocks) {
     const BlockInfo bi = blocks[b];
     const int i = q % g.n1, j = (q / g.n1) % g.n2, k = q / (g.n1 * g.n2);
-    const double* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
+    const S* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
     double uc[NV], wn[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) uc[v] = cell[v * g.vstride];
@@ -618,12 +619,21 @@ __global__ void __launch_bounds__(256) dt_kernel(const double* u, const BlockInf
   if (bad) atomicOr(&tm->err, 1);
 }
 
-hipError_t launch_dt(const double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
-                     DevTime* tm, hipStream_t s) {
+template <typename S>
+static hipError_t launch_dt_t(const S* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                              DevTime* tm, hipStream_t s) {
   const int ncell = g.n1 * g.n2 * g.n3;
   dim3 grid((ncell + 255) / 256, nblocks);
-  hipLaunchKernelGGL(dt_kernel, grid, dim3(256), 0, s, u, blocks, nblocks, g, tm);
+  hipLaunchKernelGGL(dt_kernel<S>, grid, dim3(256), 0, s, u, blocks, nblocks, g, tm);
   return hipGetLastError();
+}
+hipError_t launch_dt(const double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                     DevTime* tm, hipStream_t s) {
+  return launch_dt_t(u, blocks, nblocks, g, tm, s);
+}
+hipError_t launch_dt(const float* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                     DevTime* tm, hipStream_t s) {
+  return launch_dt_t(u, blocks, nblocks, g, tm, s);
 }
 
 // Device clock: END closes a cycle (t += dt, cycle++, next dt from the
@@ -653,10 +663,12 @@ hipError_t launch_clock(DevTime* tm, int32_t mode, double t_end, hipStream_t s) 
 }
 
 // ---------------------------------------------------------------------------
-// Upload / download between the active-only layout and padded blocks.
+// Upload / download between the active-only FP64 layout and padded blocks
+// (stored as double, or as float: rounded to nearest on upload).
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) scatter_kernel(double* u, const double* src, int64_t total,
+template <typename S>
+__global__ void __launch_bounds__(256) scatter_kernel(S* u, const double* src, int64_t total,
                                                       Geom g) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= total) return;
@@ -666,10 +678,11 @@ __global__ void __launch_bounds__(256) scatter_kernel(double* u, const double* s
   r /= g.n2;
   const int k = r % g.n3;
   r /= g.n3;  // r = block*5 + v
-  u[r * g.vstride + pad_index(g, i, j, k)] = src[q];
+  u[r * g.vstride + pad_index(g, i, j, k)] = static_cast<S>(src[q]);
 }
 
-__global__ void __launch_bounds__(256) gather_kernel(double* dst, const double* u, int64_t total,
+template <typename S>
+__global__ void __launch_bounds__(256) gather_kernel(double* dst, const S* u, int64_t total,
                                                      Geom g) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= total) return;
@@ -682,20 +695,32 @@ __global__ void __launch_bounds__(256) gather_kernel(double* dst, const double* 
   dst[q] = u[r * g.vstride + pad_index(g, i, j, k)];
 }
 
-hipError_t launch_scatter(double* u, const double* src, int32_t nblocks, const Geom& g,
-                          hipStream_t s) {
+template <typename S>
+static hipError_t launch_scatter_t(S* u, const double* src, int32_t nblocks, const Geom& g, hipStream_t s) {
   const int64_t total = (int64_t)nblocks * NV * g.n1 * g.n2 * g.n3;
-  hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, u, src,
+  hipLaunchKernelGGL(scatter_kernel<S>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, u, src,
                      total, g);
   return hipGetLastError();
 }
+hipError_t launch_scatter(double* u, const double* src, int32_t nblocks, const Geom& g, hipStream_t s) {
+  return launch_scatter_t(u, src, nblocks, g, s);
+}
+hipError_t launch_scatter(float* u, const double* src, int32_t nblocks, const Geom& g, hipStream_t s) {
+  return launch_scatter_t(u, src, nblocks, g, s);
+}
 
-hipError_t launch_gather(double* dst, const double* u, int32_t nblocks, const Geom& g,
-                         hipStream_t s) {
+template <typename S>
+static hipError_t launch_gather_t(double* dst, const S* u, int32_t nblocks, const Geom& g, hipStream_t s) {
   const int64_t total = (int64_t)nblocks * NV * g.n1 * g.n2 * g.n3;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, dst, u,
+  hipLaunchKernelGGL(gather_kernel<S>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, dst, u,
                      total, g);
   return hipGetLastError();
+}
+hipError_t launch_gather(double* dst, const double* u, int32_t nblocks, const Geom& g, hipStream_t s) {
+  return launch_gather_t(dst, u, nblocks, g, s);
+}
+hipError_t launch_gather(double* dst, const float* u, int32_t nblocks, const Geom& g, hipStream_t s) {
+  return launch_gather_t(dst, u, nblocks, g, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,7 +728,8 @@ hipError_t launch_gather(double* dst, const double* u, int32_t nblocks, const Ge
 // the block partials in a fixed order (bitwise reproducible).
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) block_sum_kernel(double* partial, const double* u,
+template <typename S>
+__global__ void __launch_bounds__(256) block_sum_kernel(double* partial, const S* u,
                                                         const BlockInfo* blocks, Geom g) {
   __shared__ double sh[NV][256];
   const int b = blockIdx.x;
@@ -712,9 +738,9 @@ __global__ void __launch_bounds__(256) block_sum_kernel(double* partial, const d
   double acc[NV] = {0, 0, 0, 0, 0};
   for (int q = threadIdx.x; q < ncell; q += 256) {
     const int i = q % g.n1, j = (q / g.n1) % g.n2, k = q / (g.n1 * g.n2);
-    const double* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
+    const S* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += cell[v * g.vstride];
+    for (int v = 0; v < NV; ++v) acc[v] += static_cast<double>(cell[v * g.vstride]);
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = acc[v];
@@ -750,11 +776,20 @@ __global__ void __launch_bounds__(256) final_sum_kernel(double* out, const doubl
   if (threadIdx.x < NV) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
-hipError_t launch_totals(double* partial, double* out, const double* u, const BlockInfo* blocks,
-                         int32_t nblocks, const Geom& g, hipStream_t s) {
-  hipLaunchKernelGGL(block_sum_kernel, dim3(nblocks), dim3(256), 0, s, partial, u, blocks, g);
+template <typename S>
+static hipError_t launch_totals_t(double* partial, double* out, const S* u, const BlockInfo* blocks,
+                                  int32_t nblocks, const Geom& g, hipStream_t s) {
+  hipLaunchKernelGGL(block_sum_kernel<S>, dim3(nblocks), dim3(256), 0, s, partial, u, blocks, g);
   hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, s, out, partial, nblocks);
   return hipGetLastError();
+}
+hipError_t launch_totals(double* partial, double* out, const double* u, const BlockInfo* blocks,
+                         int32_t nblocks, const Geom& g, hipStream_t s) {
+  return launch_totals_t(partial, out, u, blocks, nblocks, g, s);
+}
+hipError_t launch_totals(double* partial, double* out, const float* u, const BlockInfo* blocks,
+                         int32_t nblocks, const Geom& g, hipStream_t s) {
+  return launch_totals_t(partial, out, u, blocks, nblocks, g, s);
 }
 
 // ---------------------------------------------------------------------------

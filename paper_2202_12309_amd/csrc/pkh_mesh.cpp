@@ -229,7 +229,9 @@ struct pkh_mesh {
   bool g_valid = false;
 
   int64_t nb() const { return (int64_t)tree.leaves.size(); }
-  size_t state_bytes() const { return (size_t)nb() * g.bstride * sizeof(double); }
+  bool fp32 = false;  // state stored in FP32 (single-level periodic meshes)
+  size_t state_bytes() const { return (size_t)nb() * g.bstride * (fp32 ? sizeof(float) : sizeof(double)); }
+  float* Af() const { return reinterpret_cast<float*>(A); }
 
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 8;
@@ -487,9 +489,15 @@ int check_err(pkh_mesh* m) {
 }
 
 int do_exchange(pkh_mesh* m) {
-  HIPCHK(launch_fill(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->maps, m->d_time, 0, m->stream));
+  // an FP32-stored mesh is single-level and periodic: the stage kernels read
+  // every halo cell from a neighbour, so no ghost zone is ever read
+  if (!m->fp32)
+    HIPCHK(launch_fill(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->maps, m->d_time, 0, m->stream));
   HIPCHK(hipMemsetAsync(&m->d_time->smax_bits, 0, sizeof(unsigned long long), m->stream));
-  HIPCHK(launch_dt(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->d_time, m->stream));
+  if (m->fp32)
+    HIPCHK(launch_dt(m->Af(), m->d_blocks, (int32_t)m->nb(), m->g, m->d_time, m->stream));
+  else
+    HIPCHK(launch_dt(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->d_time, m->stream));
   HIPCHK(launch_clock(m->d_time, CLOCK_FROM_SMAX, NAN, m->stream));
   m->ghosts_valid = true;
   return PKH_OK;
@@ -553,6 +561,7 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
   s.fbuf = m->d_fbuf;
   s.nbr = m->d_nbr;
   s.tj = m->tj;
+  s.fp32 = m->fp32;
   // one launch per pack: leaves [p nb / P, (p+1) nb / P)
   const int32_t P = std::max(1, std::min(m->packs, nb));
   auto launch_packs = [&](StageLaunch st) -> hipError_t {
@@ -634,6 +643,12 @@ int check_config(const pkh_config* c) {
     if ((c->bc[f] == PKH_BC_PERIODIC) != (c->bc[f ^ 1] == PKH_BC_PERIODIC))
       return fail(PKH_EINVAL, "a periodic direction must be periodic on both faces");
   }
+  if (c->flags & PKH_FLAG_FP32_STATE) {
+    if (c->max_level != 0) return fail(PKH_EINVAL, "FP32 state storage needs max_level 0");
+    for (int f = 0; f < 6; ++f)
+      if (c->bc[f] != PKH_BC_PERIODIC) return fail(PKH_EINVAL, "FP32 state storage needs periodic boundaries");
+    if (n1 != 16 && n1 != 32) return fail(PKH_EINVAL, "FP32 state storage needs nblock[0] of 16 or 32");
+  }
   if (c->stage1_recon != PKH_RECON_DC && c->stage1_recon != PKH_RECON_PLM)
     return fail(PKH_EINVAL, "stage1_recon must be PKH_RECON_DC or PKH_RECON_PLM");
   if (c->limiter != PKH_LIMITER_MC) return fail(PKH_EINVAL, "only the MC limiter is supported");
@@ -678,6 +693,7 @@ int pkh_mesh_create(const pkh_config* cfg, const pkh_loc* blocks, int64_t nblock
     m->tree.periodic[d] = cfg->bc[2 * d] == PKH_BC_PERIODIC;
   }
   m->tree.maxl = cfg->max_level;
+  m->fp32 = (cfg->flags & PKH_FLAG_FP32_STATE) != 0;
   m->tree.leaves.assign(blocks, blocks + nblocks);
   m->tree.sort_morton();
   if ((rc = m->tree.build())) {
@@ -758,7 +774,10 @@ int pkh_state_upload(pkh_mesh* m, const double* src, int32_t src_on_device) {
     HIPCHK(hipMemcpyAsync(stage, src, bytes, hipMemcpyHostToDevice, m->stream));
     dsrc = stage;
   }
-  HIPCHK(launch_scatter(m->A, dsrc, (int32_t)m->nb(), m->g, m->stream));
+  if (m->fp32)
+    HIPCHK(launch_scatter(m->Af(), dsrc, (int32_t)m->nb(), m->g, m->stream));
+  else
+    HIPCHK(launch_scatter(m->A, dsrc, (int32_t)m->nb(), m->g, m->stream));
   HIPCHK(hipMemsetAsync(&m->d_time->err, 0, sizeof(int), m->stream));
   if (stage) {
     HIPCHK(hipStreamSynchronize(m->stream));
@@ -778,7 +797,10 @@ int pkh_state_download(pkh_mesh* m, double* dst, int32_t dst_on_device) {
     if (!stage) return fail(PKH_ENOMEM, "staging allocation failed");
     ddst = stage;
   }
-  HIPCHK(launch_gather(ddst, m->A, (int32_t)m->nb(), m->g, m->stream));
+  if (m->fp32)
+    HIPCHK(launch_gather(ddst, m->Af(), (int32_t)m->nb(), m->g, m->stream));
+  else
+    HIPCHK(launch_gather(ddst, m->A, (int32_t)m->nb(), m->g, m->stream));
   if (stage) HIPCHK(hipMemcpyAsync(dst, stage, bytes, hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
   if (stage) m->dfree(stage);
@@ -864,6 +886,7 @@ int pkh_set_refinement_flags(pkh_mesh* m, const int8_t* flags, int64_t n) {
 int pkh_flag_jump(pkh_mesh* m, int32_t quantity, double refine_above, double derefine_below, int8_t* flags_out,
                   double* eta_out) {
   if (!m) return fail(PKH_EINVAL, "null mesh");
+  if (m->fp32) return fail(PKH_EINVAL, "refinement indicators need an FP64-stored state");
   if (quantity != PKH_JUMP_PRESSURE && quantity != PKH_JUMP_DENSITY)
     return fail(PKH_EINVAL, "quantity must be PKH_JUMP_PRESSURE or PKH_JUMP_DENSITY");
   if (!(derefine_below <= refine_above)) return fail(PKH_EINVAL, "derefine threshold above refine threshold");
@@ -1021,7 +1044,10 @@ int pkh_regrid(pkh_mesh* m) {
 
 int pkh_conserved_totals(pkh_mesh* m, double out[5]) {
   if (!m || !out) return fail(PKH_EINVAL, "null argument");
-  HIPCHK(launch_totals(m->d_partial, m->d_tot, m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->stream));
+  if (m->fp32)
+    HIPCHK(launch_totals(m->d_partial, m->d_tot, m->Af(), m->d_blocks, (int32_t)m->nb(), m->g, m->stream));
+  else
+    HIPCHK(launch_totals(m->d_partial, m->d_tot, m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->stream));
   HIPCHK(hipMemcpyAsync(out, m->d_tot, NV * sizeof(double), hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
   return check_err(m);
@@ -1029,6 +1055,8 @@ int pkh_conserved_totals(pkh_mesh* m, double out[5]) {
 
 int pkh_set_tuning(pkh_mesh* m, const pkh_tuning* t) {
   if (!m || !t) return fail(PKH_EINVAL, "null argument");
+  if (m->fp32 && t->tile_rows != 0 && t->tile_rows != 8 && !(m->g.n1 == 32 && t->tile_rows == 16))
+    return fail(PKH_EINVAL, "FP32 state storage takes tile_rows 0, 8 or (rows of 32) 16");
   if (stage_tile_rows(m->g.n1, m->g.n2, t->tile_rows) < 0)
     return fail(PKH_EINVAL, "tile_rows %d not available for blocks of %d x %d", t->tile_rows, m->g.n1,
                 m->g.n2);
@@ -1043,6 +1071,7 @@ int pkh_set_tuning(pkh_mesh* m, const pkh_tuning* t) {
 int pkh_set_partition(pkh_mesh* m, int32_t nparts) {
   if (!m) return fail(PKH_EINVAL, "null mesh");
   if (nparts < 1 || nparts > m->nb()) return fail(PKH_EINVAL, "nparts must be in [1, %lld]", (long long)m->nb());
+  if (m->fp32 && nparts > 1) return fail(PKH_EINVAL, "partitions need an FP64-stored state");
   if (nparts == m->nparts) return PKH_OK;
   HIPCHK(hipStreamSynchronize(m->stream));  // queued work may use the tables
   drop_graph(m);
@@ -1183,8 +1212,8 @@ extern "C" {
 int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
   if (!m || !out || ckpt_every < 1) return fail(PKH_EINVAL, "bad argument");
   *out = nullptr;
-  if (m->need_fill || m->ncblocks)
-    return fail(PKH_EINVAL, "the reverse mode supports single-level periodic meshes only");
+  if (m->need_fill || m->ncblocks || m->fp32)
+    return fail(PKH_EINVAL, "the reverse mode supports single-level periodic FP64 meshes only");
   pkh_tape* t = new pkh_tape();
   t->m = m;
   t->K = ckpt_every;
@@ -1452,9 +1481,9 @@ int pkh_batch_create(pkh_mesh* const* meshes, int32_t n, pkh_batch** out) {
       delete b;
       return fail(PKH_EINVAL, "batched meshes must share one stream");
     }
-    if (m->need_fill || m->ncblocks) {
+    if (m->need_fill || m->ncblocks || m->fp32) {
       delete b;
-      return fail(PKH_EINVAL, "batches hold single-level periodic meshes");
+      return fail(PKH_EINVAL, "batches hold single-level periodic FP64 meshes");
     }
   }
   std::vector<StageLaunch> pred(n), corr(n);
@@ -1596,6 +1625,7 @@ int pkh_autotune(pkh_mesh* m, int32_t trial_cycles, pkh_tuning* out) {
   float best_ms = 1e30f;
   for (int tj : kTileChoices) {
     if (stage_tile_rows(m->g.n1, m->g.n2, tj) != tj) continue;
+    if (m->fp32 && tj != 8 && !(m->g.n1 == 32 && tj == 16)) continue;
     m->tj = tj;
     if ((rc = pkh_step(m, 1, INFINITY))) break;
     HIPCHK(hipEventRecord(e0, m->stream));

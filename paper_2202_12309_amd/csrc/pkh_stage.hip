@@ -51,13 +51,17 @@ namespace pkh {
 // stages per-cell HLLE inputs (sqrt(rho), c, h) so no face recomputes them;
 // the corrector stages primitives and reconstructs per face (PLM-MC). A
 // cell is finished once its upper z face is known; its x/y divergence waits
-// in a short register queue. Finished cells a same-level neighbour needs as
-// ghosts are written into that neighbour's ghost zone here.
+// in a short register queue. Halo cells beyond a same-level face are read
+// from the neighbour's active cells.
+//
+// S is the storage type of the state arrays: double, or float for FP32
+// storage (values widened on load, every operation in FP64, the result
+// rounded once when stored; the CFL reduction sees the stored value).
 // ---------------------------------------------------------------------------
 
 // One tile (TJ rows of block blk starting at row j0) of a stage; rot
 // rotates which wave takes the tile's remainder faces.
-template <int RECON, int N1, int TJ>
+template <int RECON, int N1, int TJ, typename S = double>
 __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0, int rot) {
   constexpr int NT = N1 * TJ;
   constexpr int P1 = N1 + 2 * NG;
@@ -94,9 +98,9 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   const double igm1 = 1.0 / gm1;
   const double coef = a.beta * a.tm->dt;
   const int64_t vs = g.vstride;
-  const double* __restrict__ in = a.uin + (int64_t)blk * g.bstride;
-  const double* base = a.ubase + (int64_t)blk * g.bstride;
-  double* out = a.uout + (int64_t)blk * g.bstride;
+  const S* __restrict__ in = static_cast<const S*>(a.uin) + (int64_t)blk * g.bstride;
+  const S* base = static_cast<const S*>(a.ubase) + (int64_t)blk * g.bstride;
+  S* out = static_cast<S*>(a.uout) + (int64_t)blk * g.bstride;
   const int n2 = g.n2, n3 = g.n3;
   const int j = j0 + tj;
   const int fsz = NV * max(max(g.n1 * n2, g.n1 * n3), n2 * n3);  // face slot stride
@@ -224,7 +228,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   if constexpr (PF) {
 #pragma unroll
     for (int sl = 0; sl < PFD; ++sl) {
-      const double* pl = in + pofs(p_first + sl);
+      const S* pl = in + pofs(p_first + sl);
 #pragma unroll
       for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own];
       // the halo is only read on the active planes
@@ -253,7 +257,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 #pragma unroll
         for (int v = 0; v < NV; ++v) u[v] = pu[sl][v];
       } else {
-        const double* pl = in + pofs(p);
+        const S* pl = in + pofs(p);
 #pragma unroll
         for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + own];
       }
@@ -280,7 +284,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       }
       if (p + PFD < p_end) {
         const int64_t po = pofs(p + PFD);
-        const double* pn = in + po;
+        const S* pn = in + po;
 #pragma unroll
         for (int v = 0; v < NV; ++v) pu[sl][v] = pn[v * vs + own];
         const bool act = p + PFD >= 0 && p + PFD < n3;
@@ -351,8 +355,9 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
         for (int v = 0; v < NV; ++v) {
           const double du = dq[0][v] + (fz[v] - fzp[v]) * bi.idx[2];
           const double ub = RECON ? (BPF ? ubn[sl][v] : base[v * vs + o]) : uq[0][v];
-          un[v] = ub - coef * du;
-          out[v * vs + o] = un[v];
+          const S st = static_cast<S>(ub - coef * du);
+          out[v * vs + o] = st;
+          un[v] = static_cast<double>(st);
         }
         if constexpr (BPF) {
           if (k + PFD < n3) {
@@ -478,6 +483,16 @@ __global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAV
   stage_tile<RECON, N1, TJ>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg);
 }
 
+// The same over a state stored in FP32.
+template <int RECON, int N1, int TJ>
+__global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAVES) stage_kernel_f32(StageLaunch a) {
+  const int ntj = a.g.n2 / TJ;
+  const int wg = xcd_order(blockIdx.x, gridDim.x);
+  const int blk = wg / ntj;
+  if (blk >= a.nblocks) return;
+  stage_tile<RECON, N1, TJ, float>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg);
+}
+
 // Grouped launch: the tiles of many independent meshes (same block width
 // and tile) in one grid; items[w] names the mesh, block and first row.
 template <int RECON, int N1, int TJ>
@@ -504,6 +519,15 @@ static hipError_t launch_stage_t(const StageLaunch& a, hipStream_t s) {
   int64_t nwg = (int64_t)a.nblocks * ntj;
   nwg = (nwg + 7) / 8 * 8;
   hipLaunchKernelGGL((stage_kernel<RECON, N1, TJ>), dim3((unsigned)nwg), dim3(N1 * TJ), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int RECON, int N1, int TJ>
+static hipError_t launch_stage_f32_t(const StageLaunch& a, hipStream_t s) {
+  const int ntj = a.g.n2 / TJ;
+  int64_t nwg = (int64_t)a.nblocks * ntj;
+  nwg = (nwg + 7) / 8 * 8;
+  hipLaunchKernelGGL((stage_kernel_f32<RECON, N1, TJ>), dim3((unsigned)nwg), dim3(N1 * TJ), 0, s, a);
   return hipGetLastError();
 }
 
@@ -554,6 +578,18 @@ hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* inst
 
 hipError_t launch_stage(const StageLaunch& a, hipStream_t s) {
   const int tj = stage_tile_rows(a.g.n1, a.g.n2, a.tj, a.nblocks, a.recon);
+  if (a.fp32) {  // FP32 storage: blocks of 16 or 32 cells per row, default tiles
+    switch (a.g.n1 * 100 + tj) {
+      case 1608:
+        return a.recon ? launch_stage_f32_t<1, 16, 8>(a, s) : launch_stage_f32_t<0, 16, 8>(a, s);
+      case 3208:
+        return a.recon ? launch_stage_f32_t<1, 32, 8>(a, s) : launch_stage_f32_t<0, 32, 8>(a, s);
+      case 3216:
+        return a.recon ? launch_stage_f32_t<1, 32, 16>(a, s) : launch_stage_f32_t<0, 32, 16>(a, s);
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   switch (a.g.n1 * 100 + tj) {
     case 808:
       return launch_stage_n<8, 8>(a, s);
