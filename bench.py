@@ -70,6 +70,21 @@ def traffic_from_profile(kernel_sha):
     return rec.get("hbm_bytes_per_launch")
 
 
+def valu_from_profile(kernel_sha):
+    """VALU instructions and issue floor per stage launch from the committed
+    SQ_INSTS_VALU summary, when it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "stage_kernels_256cube_32blocks_valu.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_source_sha256") != kernel_sha:
+        return None
+    return rec
+
+
 def cpu_baseline(blk, cycles=16):
     """The oracle, as it stands, on the same 256^3 workload for a bounded
     number of cycles on this host's cores."""
@@ -463,6 +478,14 @@ def main_leg(args):
                 "traffic": traffic_from_profile(sha),
                 "algorithmic_bytes_per_launch": int(b_corr * cells),
                 "avg_launch_ms": round(corr_ms, 4)}
+        # the second ceiling: FP64 VALU issue (one wave64 instruction holds a
+        # SIMD for 4 cycles) for the instructions the counters saw per launch
+        vr = valu_from_profile(sha)
+        if vr and blk == 32 and args.tile_rows == 0:
+            c = vr["corrector"]
+            roof["valu"] = {"instructions_per_cell": round(c["valu_instructions_per_cell"], 1),
+                            "floor_ms": round(c["valu_floor_ms"], 4),
+                            "frac": round(c["valu_floor_ms"] / corr_ms, 4)}
     out = {
         "metric": METRIC,
         "value": zc,
