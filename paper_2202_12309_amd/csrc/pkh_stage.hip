@@ -130,6 +130,9 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   double uq[UQN][NV];  // predictor: conserved own-cell values awaiting their update
   double dq[QN][NV];  // x/y divergence awaiting the z faces
   double fzp[NV];
+  // corrector: MC z slopes of window cells 1 and 2, each formed once when the
+  // cell above it enters the window
+  double szp[NV], szc[NV];
   bool bad = false;
   double smax = 0.0;
   const int mask = bi.finer_mask;
@@ -145,7 +148,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 #pragma unroll
     for (int v = 0; v < NV; ++v) uq[s][v] = 0.0;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) fzp[v] = 0.0;
+  for (int v = 0; v < NV; ++v) fzp[v] = szp[v] = szc[v] = 0.0;
 
   // stage one cell's inputs into LDS slot c; returns its state
   auto stage_cell = [&](const double u[NV], int c) {
@@ -265,6 +268,16 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 #pragma unroll
       for (int s = 0; s < WN - 1; ++s) w[s] = w[s + 1];
       w[WN - 1] = q;
+      if constexpr (RECON) {
+        const double a1[NV] = {w[1].r, w[1].v0, w[1].v1, w[1].v2, w[1].p};
+        const double a2[NV] = {w[2].r, w[2].v0, w[2].v1, w[2].v2, w[2].p};
+        const double a3[NV] = {w[3].r, w[3].v0, w[3].v1, w[3].v2, w[3].p};
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          szp[v] = szc[v];
+          szc[v] = mc_slope(a2[v] - a1[v], a3[v] - a2[v]);
+        }
+      }
       if constexpr (!RECON) {
 #pragma unroll
         for (int s = 0; s < UQN - 1; ++s)
@@ -318,15 +331,13 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       FState L, R;
       double fz[NV];
       if constexpr (RECON) {
-        const double c0[NV] = {w[0].r, w[0].v0, w[0].v1, w[0].v2, w[0].p};
         const double c1[NV] = {w[1].r, w[1].v0, w[1].v1, w[1].v2, w[1].p};
         const double c2[NV] = {w[2].r, w[2].v0, w[2].v1, w[2].v2, w[2].p};
-        const double c3[NV] = {w[3].r, w[3].v0, w[3].v1, w[3].v2, w[3].p};
         double wl[NV], wr[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          wl[v] = c1[v] + 0.5 * mc_slope(c1[v] - c0[v], c2[v] - c1[v]);
-          wr[v] = c2[v] - 0.5 * mc_slope(c2[v] - c1[v], c3[v] - c2[v]);
+          wl[v] = c1[v] + 0.5 * szp[v];
+          wr[v] = c2[v] - 0.5 * szc[v];
         }
         L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
         R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
