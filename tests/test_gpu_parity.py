@@ -300,3 +300,28 @@ def test_packs_do_not_change_results():
     with pytest.raises(PkhError):
         gm.set_tuning(0, -1)
     gm.close()
+
+
+def test_full_size_bench_configuration_parity():
+    """The bench workload itself: 256^3 in 512 blocks of 32^3, the default
+    launch tiles (8-row predictor, 16-row corrector), against the oracle
+    element by element after 1, 10 and 100 cycles (about a minute of oracle
+    time on 16 threads); clock and totals too."""
+    print_case("256^3 turbulent box, 512 blocks of 32^3, bench launch configuration, 100 cycles")
+    n, N = (32, 32, 32), 256
+    gm, om, nrb = _pair((N, N, N), n, inputs.uniform_leaves((8, 8, 8)))
+    assert gm.tuning()["tile_rows"] == 16
+    U0 = inputs.turbulent_box(gm.leaves(), n, nrb, seed=2)
+    gm.upload(U0)
+    om.set_state(U0)
+    done = 0
+    for upto, tol in ((1, 1e-12), (10, 1e-11), (100, 1e-9)):
+        gm.step(upto - done)
+        om.step(upto - done)
+        done = upto
+        err = rel_err(gm.download(), om.state(), G)
+        print(f"cycle {upto}: rel err {err}", flush=True)
+        assert np.all(err <= tol), (upto, err)
+    assert abs(gm.time()[0] - om.time()[0]) <= 1e-12 * om.time()[0]
+    To, Ao = om.totals()
+    assert np.all(np.abs(gm.totals() - To) <= 1e-13 * np.maximum(Ao, 1.0))
