@@ -325,3 +325,37 @@ def test_full_size_bench_configuration_parity():
     assert abs(gm.time()[0] - om.time()[0]) <= 1e-12 * om.time()[0]
     To, Ao = om.totals()
     assert np.all(np.abs(gm.totals() - To) <= 1e-13 * np.maximum(Ao, 1.0))
+
+
+@pytest.mark.parametrize("n,nrb,ml", [((32, 16, 8), (4, 2, 2), 0), ((16, 8, 8), (2, 4, 1), 0),
+                                      ((64, 8, 4), (1, 2, 3), 0), ((16, 16, 8), (2, 1, 2), 1)])
+def test_ragged_blocks_and_domains(n, nrb, ml):
+    """Blocks that are not cubes in domains that are not cubes (edges 4 to
+    64 cells, a single block along a direction, an odd number of blocks),
+    and a two-level mesh of flat blocks: against the oracle after 3 cycles."""
+    print_case(f"ragged blocks {n} x {nrb}, max level {ml}, 3 cycles")
+    nroot = tuple(n[d] * nrb[d] for d in range(3))
+    xmax = tuple(float(nroot[d]) / nroot[0] for d in range(3))  # cubic cells
+    lv = inputs.uniform_leaves(nrb)
+    if ml:
+        lv = [l for l in lv.tolist() if l != [0, 0, 0, 0]]
+        lv += [[1, c & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)]
+    gm, om, _ = _pair(nroot, n, lv, max_level=ml, xmax=xmax)
+    U0 = inputs.turbulent_box(gm.leaves(), n, nrb, seed=5) if not ml else \
+        inputs.blast(gm.leaves(), n, nrb, center=(0.3, 0.2, 0.4), r=0.15, xmax=xmax)
+    Ug, Uo = _run_both(gm, om, U0, 3)
+    err = rel_err(Ug, Uo, G)
+    print("rel err", err, flush=True)
+    assert np.all(err <= 1e-12), err
+
+
+def test_zero_cycles_is_a_no_op():
+    print_case("step(0)")
+    n = (16, 16, 16)
+    gm, om, nrb = _pair((32, 32, 32), n, inputs.uniform_leaves((2, 2, 2)))
+    U0 = inputs.turbulent_box(gm.leaves(), n, nrb, seed=7)
+    gm.upload(U0)
+    gm.step(0)
+    assert np.array_equal(gm.download(), U0)
+    t, _, cyc = gm.time()
+    assert t == 0.0 and cyc == 0
