@@ -20,6 +20,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "zone-cycles/s & %HBM peak (256^3 FP64 hydro); adjoint/forward cost ratio"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, a fused multiply-add counted as two
+# Algorithmic FP64 operations (add, multiply, divide, square root) per zone of
+# each stage and of the CFL signal speed, as the method's formulas are written
+# (no contraction, no ghost-cell recomputation): counted by the
+# operation-counting mirror of the oracle's formulas, which a test keeps equal
+# to these numbers.
+ALG_FLOPS = {"predictor": 461, "corrector": 731, "cfl": 21}
 N = 256
 # sources of the stage kernels: the committed traffic counters are used only
 # while these are unchanged
@@ -486,6 +493,12 @@ def main_leg(args):
             roof["valu"] = {"instructions_per_cell": round(c["valu_instructions_per_cell"], 1),
                             "floor_ms": round(c["valu_floor_ms"], 4),
                             "frac": round(c["valu_floor_ms"] / corr_ms, 4)}
+        # the same launch against the FP64 vector peak, counting the
+        # method's own operations (corrector and the fused CFL reduction)
+        fl = (ALG_FLOPS["corrector"] + ALG_FLOPS["cfl"]) * cells / (corr_ms / 1e3) / 1e12
+        roof["alu"] = {"flops_per_zone": ALG_FLOPS["corrector"] + ALG_FLOPS["cfl"],
+                       "achieved": round(fl, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(fl / FP64_PEAK_TFLOPS, 4)}
     out = {
         "metric": METRIC,
         "value": zc,
@@ -506,6 +519,8 @@ def main_leg(args):
                    "tile_rows": mesh.tuning()["tile_rows"]},
         "hbm_frac_cycle": round(zc * b_cycle / (HBM_PEAK_GBS * 1e9), 4),
         "bytes_per_zone_cycle": round(b_cycle, 2),
+        "flops_per_zone_cycle": sum(ALG_FLOPS.values()),
+        "fp64_tflops_cycle": round(zc * sum(ALG_FLOPS.values()) / 1e12, 3),
         "hbm_frac_at_ghost_materialised_bytes": round(zc * ghost_materialised_bytes(blk) / (HBM_PEAK_GBS * 1e9),
                                                       4),
         "kernel_avg_ms": {k: (round(v, 4) if v else None) for k, v in avg.items()},
