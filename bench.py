@@ -568,8 +568,8 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding across GPUs is "
+              "not built (its data path runs on one GPU through pkh_set_partition).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -256,7 +256,7 @@ def test_regrid_conserves_totals():
 
 
 # ---------------------------------------------------------------------------
-# Pressure-jump refinement indicator (the harness's criterion)
+# Pressure-jump refinement indicator (the criterion the tests and the bench use)
 # ---------------------------------------------------------------------------
 
 def _pressure_state(m, pfun):
