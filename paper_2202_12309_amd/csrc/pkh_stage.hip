@@ -30,6 +30,10 @@
 #ifndef PKH_PRED_WAVES
 #define PKH_PRED_WAVES 2
 #endif
+// issue the next plane's loads after the update (1) or right after staging (0)
+#ifndef PKH_PF_LATE
+#define PKH_PF_LATE 1
+#endif
 // planes of inputs kept in flight ahead of the one being computed
 #ifndef PKH_CORR_PFD
 #define PKH_CORR_PFD 1
@@ -207,18 +211,48 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     const int hh = h - 4 * N1, r = hh >> 2, s4 = hh & 3;
     return (r + NG) * P1 + (s4 < 2 ? s4 : P1 - 4 + s4);
   };
-  // offset from this block's cell to the one halo cell h is read from
-  auto hshift = [&](int h) -> int64_t {
-    if (h < 4 * N1) return h < 2 * N1 ? dyl : dyh;
-    return ((h - 4 * N1) & 3) < 2 ? dxl : dxr;
+  // offset from this block's cell to the one halo cell h is read from. The
+  // offsets are captured by value so the per-lane choice is a select: taken
+  // by reference, they live in scratch memory and every halo load waits for
+  // a pointer load first.
+  auto hshift = [dxl, dxr, dyl, dyh](int h) -> int64_t {
+    const int64_t sy = h < 2 * N1 ? dyl : dyh;
+    const int64_t sx = ((h - 4 * N1) & 3) < 2 ? dxl : dxr;
+    return h < 4 * N1 ? sy : sx;
   };
   constexpr int HMAX = PF ? (NHALO + NT - 1) / NT : 1;
+  // this lane's halo cells: LDS slot, and offset of the cell read (slot plus
+  // neighbour shift), formed once since neither changes from plane to plane
+  int hslot[HMAX];
+  int64_t hoff[HMAX];
+#pragma unroll
+  for (int hh = 0; hh < HMAX; ++hh) {
+    const int h = min(tid + hh * NT, NHALO - 1);
+    hslot[hh] = hcell(h);
+    hoff[hh] = hshift(h) + hslot[hh];
+  }
   // ring of PFD planes in flight: plane p is staged from slot (p - p_first)
   // % PFD, which then receives plane p + PFD; the loop below is unrolled by
   // PFD so every slot index is a compile-time constant
   double pu[PFD][NV], ph[PFD][HMAX][NV];  // own and halo cells of planes ahead
   double ubn[PFD][NV];                    // corrector: U^n of the next updates
   const int p_first = -1 - LAG, p_end = n3 + 1 + LAG;
+  // start the loads of plane pn (own cell and halo) into ring slot sl
+  auto prefetch = [&](int sl, int pn) {
+    if (pn >= p_end) return;
+    const S* pl = in + pofs(pn);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own];
+    const bool act = pn >= 0 && pn < n3;
+#pragma unroll
+    for (int hh = 0; hh < HMAX; ++hh) {
+      const int h = tid + hh * NT;
+      if (act && h < NHALO) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ph[sl][hh][v] = pl[hoff[hh] + v * vs];
+      }
+    }
+  };
   if constexpr (BPF) {
     // the update of cell c happens at plane p_first + 2 + 2 LAG + c
 #pragma unroll
@@ -241,7 +275,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
         const int h = tid + hh * NT;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          ph[sl][hh][v] = (act && h < NHALO) ? pl[hshift(h) + v * vs + hcell(h)] : 1.0;
+          ph[sl][hh][v] = (act && h < NHALO) ? pl[hoff[hh] + v * vs] : 1.0;
       }
     }
   }
@@ -292,26 +326,10 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 #pragma unroll
         for (int hh = 0; hh < HMAX; ++hh) {
           const int h = tid + hh * NT;
-          if (h < NHALO) stage_cell(ph[sl][hh], hcell(h));
+          if (h < NHALO) stage_cell(ph[sl][hh], hslot[hh]);
         }
       }
-      if (p + PFD < p_end) {
-        const int64_t po = pofs(p + PFD);
-        const S* pn = in + po;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) pu[sl][v] = pn[v * vs + own];
-        const bool act = p + PFD >= 0 && p + PFD < n3;
-#pragma unroll
-        for (int hh = 0; hh < HMAX; ++hh) {
-          const int h = tid + hh * NT;
-          if (act && h < NHALO) {
-            const int c = hcell(h);
-            const int64_t hs = hshift(h);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) ph[sl][hh][v] = pn[hs + v * vs + c];
-          }
-        }
-      }
+      if (!PKH_PF_LATE) prefetch(sl, p + PFD);
     } else {
       const int64_t po = pofs(p);
       for (int h = tid; h < NHALO && p >= 0 && p < n3; h += NT) {
@@ -393,6 +411,10 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 #pragma unroll
       for (int v = 0; v < NV; ++v) fzp[v] = fz[v];
     }
+    // Loads of plane p + PFD start here, after the update, so the wait of
+    // the update for its U^n values does not also wait for them; they land
+    // while the x and y faces are solved.
+    if constexpr (PF && PKH_PF_LATE) prefetch(sl, p + PFD);
     // --- x and y faces of plane p, divergence into the queue. Each thread
     // solves the lower x and y faces of its cell; the tile's upper x faces
     // (one per row) and upper y faces (one per column) are spread over the
