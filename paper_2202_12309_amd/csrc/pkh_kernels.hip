@@ -518,8 +518,6 @@ __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const Bloc
       ((((bi.finer_mask >> XLO) & 1) && i == 0) || (((bi.finer_mask >> XHI) & 1) && i == g.n1 - 1) ||
        (((bi.finer_mask >> YLO) & 1) && j == 0) || (((bi.finer_mask >> YHI) & 1) && j == g.n2 - 1) ||
        (((bi.finer_mask >> ZLO) & 1) && k == 0) || (((bi.finer_mask >> ZHI) & 1) && k == g.n3 - 1))) {
-    const int n[3] = {g.n1, g.n2, g.n3};
-    const int cc[3] = {i, j, k};
     const int fsz = NV * max(max(g.n1 * g.n2, g.n1 * g.n3), g.n2 * g.n3);
     bool touched = false;
     double* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
@@ -530,20 +528,30 @@ __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const Bloc
     for (int e = ff_first[c]; e < ff_first[c + 1]; ++e) {
       const FineFace rec = ff[e];
       const int d = rec.face >> 1, s = rec.face & 1;
-      if (cc[d] != (s ? n[d] - 1 : 0)) continue;
+      // normal axis d and the two transverse axes in increasing order, as
+      // selects (per-lane indexing of small arrays would put them in
+      // scratch memory)
+      const int cd = d == 0 ? i : (d == 1 ? j : k);
+      const int nd = d == 0 ? g.n1 : (d == 1 ? g.n2 : g.n3);
+      if (cd != (s ? nd - 1 : 0)) continue;
       touched = true;
-      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-      const int a1 = cc[t1], a2 = cc[t2];
-      const int h1 = a1 >= n[t1] / 2, h2 = a2 >= n[t2] / 2;
-      const int fs = rec.fine_slot[h1 + 2 * h2];
-      const int f1 = 2 * a1 - h1 * n[t1], f2 = 2 * a2 - h2 * n[t2];
+      const int a1 = d == 0 ? j : i, m1 = d == 0 ? g.n2 : g.n1;
+      const int a2 = d == 2 ? j : k, m2 = d == 2 ? g.n2 : g.n3;
+      const int h1 = a1 >= m1 / 2, h2 = a2 >= m2 / 2;
+      const int sub = h1 + 2 * h2;
+      const int fs = sub == 0   ? rec.fine_slot[0]
+                     : sub == 1 ? rec.fine_slot[1]
+                     : sub == 2 ? rec.fine_slot[2]
+                                : rec.fine_slot[3];
+      const double idd = d == 0 ? bi.idx[0] : (d == 1 ? bi.idx[1] : bi.idx[2]);
+      const int f1 = 2 * a1 - h1 * m1, f2 = 2 * a2 - h2 * m2;
       const double sg = s ? 1.0 : -1.0;
       for (int v = 0; v < NV; ++v) {
-        const double own = fbuf[(int64_t)rec.own_slot * fsz + ((int64_t)v * n[t2] + a2) * n[t1] + a1];
-        const double* fb = fbuf + (int64_t)fs * fsz + (int64_t)v * n[t2] * n[t1];
-        const double fine = 0.25 * ((fb[f2 * n[t1] + f1] + fb[f2 * n[t1] + f1 + 1]) +
-                                    (fb[(f2 + 1) * n[t1] + f1] + fb[(f2 + 1) * n[t1] + f1 + 1]));
-        uc[v] += sg * coef * (own - fine) * bi.idx[d];
+        const double own = fbuf[(int64_t)rec.own_slot * fsz + ((int64_t)v * m2 + a2) * m1 + a1];
+        const double* fb = fbuf + (int64_t)fs * fsz + (int64_t)v * m2 * m1;
+        const double fine = 0.25 * ((fb[f2 * m1 + f1] + fb[f2 * m1 + f1 + 1]) +
+                                    (fb[(f2 + 1) * m1 + f1] + fb[(f2 + 1) * m1 + f1 + 1]));
+        uc[v] += sg * coef * (own - fine) * idd;
       }
     }
     if (touched) {

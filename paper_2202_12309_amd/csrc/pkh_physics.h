@@ -74,6 +74,17 @@ PKH_HD double mc_slope(double dl, double dr) {
   return s * fmax(m, 0.0);
 }
 
+// Half the MC slope, MC(dl, dr)/2 = s*max(0, min(|dl|, s dr, s (dl+dr)/4)),
+// the offset of a face value from its cell's value. Scaling by powers of two
+// is exact, so this equals 0.5 * mc_slope(dl, dr) bit for bit (outside the
+// subnormal range) with one multiplication less and the sign applied by a
+// bit copy.
+PKH_HD double mc_half(double dl, double dr) {
+  const double s = copysign(1.0, dl);
+  const double m = fmin(fmin(fabs(dl), s * dr), copysign(0.25, dl) * (dl + dr));
+  return copysign(fmax(m, 0.0), dl);
+}
+
 PKH_HD double minmod(double a, double b) {
   const double m = fmin(fabs(a), fabs(b));
   return (a * b > 0.0) ? copysign(m, a) : 0.0;

@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "pkh_device.h"
 
@@ -33,6 +34,10 @@
 // issue the next plane's loads after the update (1) or right after staging (0)
 #ifndef PKH_PF_LATE
 #define PKH_PF_LATE 1
+#endif
+// with PKH_PF_LATE: the halo loads start after the first face solve (1)
+#ifndef PKH_PF_SPLIT
+#define PKH_PF_SPLIT 1
 #endif
 // planes of inputs kept in flight ahead of the one being computed
 #ifndef PKH_CORR_PFD
@@ -134,8 +139,8 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   double uq[UQN][NV];  // predictor: conserved own-cell values awaiting their update
   double dq[QN][NV];  // x/y divergence awaiting the z faces
   double fzp[NV];
-  // corrector: MC z slopes of window cells 1 and 2, each formed once when the
-  // cell above it enters the window
+  // corrector: half MC z slopes of window cells 1 and 2, each formed once
+  // when the cell above it enters the window
   double szp[NV], szc[NV];
   bool bad = false;
   double smax = 0.0;
@@ -186,8 +191,8 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       for (int v = 0; v < NV; ++v) {
         const double qm2 = sQ[v][c0 - 2 * st], qm1 = sQ[v][c0 - st], q0 = sQ[v][c0],
                      qp1 = sQ[v][c0 + st];
-        wl[v] = qm1 + 0.5 * mc_slope(qm1 - qm2, q0 - qm1);
-        wr[v] = q0 - 0.5 * mc_slope(q0 - qm1, qp1 - q0);
+        wl[v] = qm1 + mc_half(qm1 - qm2, q0 - qm1);
+        wr[v] = q0 - mc_half(q0 - qm1, qp1 - q0);
       }
       L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
       R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
@@ -197,6 +202,26 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       const int cm = c0 - st;
       L = FState{sQ[0][cm], sQ[1][cm], sQ[2][cm], sQ[3][cm], sQ[4][cm], sQ[5][cm], sQ[6][cm], sQ[7][cm]};
       R = FState{sQ[0][c0], sQ[1][c0], sQ[2][c0], sQ[3][c0], sQ[4][c0], sQ[5][c0], sQ[6][c0], sQ[7][c0]};
+    }
+  };
+
+  // Solve the face of direction D (0: x, 1: y) whose upper cell is LDS slot
+  // c0; its flux goes to LDS slot fo, and to the fine-coarse face buffer at
+  // slot fsl (if >= 0), offset o, when the face borders a finer leaf.
+  auto solve_face = [&](auto dirc, int c0, int fo, int fsl, int64_t o) {
+    constexpr int D = decltype(dirc)::value;
+    FState L, R;
+    double fl[NV];
+    face_states(c0, D == 0 ? 1 : P1, L, R);
+    hlle<D>(L, R, gm1, fl);
+    double* dstf = D == 0 ? &sFx[0][fo] : &sFy[0][fo];
+    constexpr int vstr = D == 0 ? NX : NY;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dstf[v * vstr] = fl[v];
+    if (fsl >= 0) {
+      const int64_t vst = D == 0 ? (int64_t)n3 * n2 : (int64_t)n3 * N1;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fbuf[(int64_t)fsl * fsz + v * vst + o] = fl[v];
     }
   };
 
@@ -237,17 +262,20 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   double pu[PFD][NV], ph[PFD][HMAX][NV];  // own and halo cells of planes ahead
   double ubn[PFD][NV];                    // corrector: U^n of the next updates
   const int p_first = -1 - LAG, p_end = n3 + 1 + LAG;
-  // start the loads of plane pn (own cell and halo) into ring slot sl
-  auto prefetch = [&](int sl, int pn) {
+  // start the loads of plane pn into ring slot sl: the own cell, the halo
+  auto prefetch_own = [&](int sl, int pn) {
     if (pn >= p_end) return;
     const S* pl = in + pofs(pn);
 #pragma unroll
     for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own];
-    const bool act = pn >= 0 && pn < n3;
+  };
+  auto prefetch_halo = [&](int sl, int pn) {
+    if (pn < 0 || pn >= n3) return;  // the halo is only read on the active planes
+    const S* pl = in + pofs(pn);
 #pragma unroll
     for (int hh = 0; hh < HMAX; ++hh) {
       const int h = tid + hh * NT;
-      if (act && h < NHALO) {
+      if (h < NHALO) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) ph[sl][hh][v] = pl[hoff[hh] + v * vs];
       }
@@ -309,7 +337,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           szp[v] = szc[v];
-          szc[v] = mc_slope(a2[v] - a1[v], a3[v] - a2[v]);
+          szc[v] = mc_half(a2[v] - a1[v], a3[v] - a2[v]);
         }
       }
       if constexpr (!RECON) {
@@ -329,7 +357,10 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
           if (h < NHALO) stage_cell(ph[sl][hh], hslot[hh]);
         }
       }
-      if (!PKH_PF_LATE) prefetch(sl, p + PFD);
+      if (!PKH_PF_LATE) {
+        prefetch_own(sl, p + PFD);
+        prefetch_halo(sl, p + PFD);
+      }
     } else {
       const int64_t po = pofs(p);
       for (int h = tid; h < NHALO && p >= 0 && p < n3; h += NT) {
@@ -354,8 +385,8 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
         double wl[NV], wr[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          wl[v] = c1[v] + 0.5 * szp[v];
-          wr[v] = c2[v] - 0.5 * szc[v];
+          wl[v] = c1[v] + szp[v];
+          wr[v] = c2[v] - szc[v];
         }
         L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
         R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
@@ -414,54 +445,43 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     // Loads of plane p + PFD start here, after the update, so the wait of
     // the update for its U^n values does not also wait for them; they land
     // while the x and y faces are solved.
-    if constexpr (PF && PKH_PF_LATE) prefetch(sl, p + PFD);
+    if constexpr (PF && PKH_PF_LATE) {
+      prefetch_own(sl, p + PFD);
+      if (!PKH_PF_SPLIT || p < 0 || p >= n3) prefetch_halo(sl, p + PFD);
+    }
     // --- x and y faces of plane p, divergence into the queue. Each thread
-    // solves the lower x and y faces of its cell; the tile's upper x faces
-    // (one per row) and upper y faces (one per column) are spread over the
-    // first lanes of every wave so that all waves do the same number of
-    // solves between barriers.
+    // solves the lower x and y faces of its cell; the tile's upper x and y
+    // faces are solved by the first lanes of two waves.
     if (p >= 0 && p < n3) {
-      // remainder jobs (the tile's upper x and y faces) go to consecutive
-      // threads starting at one wave, rotated with the plane and the
-      // workgroup so that no SIMD always gets the extra work
-      const int wr = (rot + p + 2) % NWAVE;
-      const int q = (tid - wr * 64 + NT) % NT;
+      // Every face of a direction is solved by one copy of the code (a loop
+      // that is not unrolled, with hlle<0> for x and hlle<1> for y), so a
+      // face shared by two tiles or two blocks gets the same flux bit for bit
+      // on both sides, whichever tile shape is used. Pass 0 solves the lower
+      // face of the own cell; pass 1 the tile's upper x faces (one per row)
+      // on the first lanes of wave wx and its upper y faces (one per column)
+      // on those of the next wave, so the two extra solves land on
+      // different SIMDs; both rotate with the plane and the workgroup so
+      // that no SIMD always gets the extra work.
+      const int wx = (rot + p + 2) % NWAVE;
+      const int wy = (wx + 1) % NWAVE;
+      const int qx = (tid - wx * 64 + NT) % NT, qy = (tid - wy * 64 + NT) % NT;
 #pragma unroll 1
-      for (int slot = 0; slot < 3; ++slot) {
-        // slot 0: lower x face of the own cell; 1: lower y face; 2: upper x
-        // face of row q (q < TJ) or upper y face of column q - TJ
-        if (slot == 2 && q >= TJ + N1) break;
-        const int dir = slot == 0 ? 0 : (slot == 1 ? 1 : (q < TJ ? 0 : 1));
-        const int iy = q - TJ;
-        const int c0 = slot < 2 ? own : (dir == 0 ? (q + NG) * P1 + N1 + NG : (TJ + NG) * P1 + iy + NG);
-        FState L, R;
-        double fl[NV];
-        face_states(c0, dir == 0 ? 1 : P1, L, R);
-        hlle<-1>(L, R, gm1, fl, dir);
-        const int fo = slot < 2 ? (dir == 0 ? tj * (N1 + 1) + ti : tj * N1 + ti)
-                                : (dir == 0 ? q * (N1 + 1) + N1 : TJ * N1 + iy);
-        double* dstf = dir == 0 ? &sFx[0][fo] : &sFy[0][fo];
-        const int vstr = dir == 0 ? NX : NY;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) dstf[v * vstr] = fl[v];
-        // fine-coarse faces: keep this leaf's flux for the correction
-        int fsl = -1;
-        int64_t o = 0, vst = 0;
-        if (dir == 0) {
-          const bool lo = slot == 0 && ti == 0, hi = slot == 2;
-          fsl = lo ? bi.fslot[XLO] : (hi ? bi.fslot[XHI] : -1);
-          o = (int64_t)p * n2 + (slot == 0 ? j : j0 + q);
-          vst = (int64_t)n3 * n2;
-        } else {
-          const bool lo = slot == 1 && j == 0, hi = slot == 2 && j0 + TJ == n2;
-          fsl = lo ? bi.fslot[YLO] : (hi ? bi.fslot[YHI] : -1);
-          o = (int64_t)p * N1 + (slot == 1 ? ti : iy);
-          vst = (int64_t)n3 * N1;
-        }
-        if (fsl >= 0) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) fbuf[(int64_t)fsl * fsz + v * vst + o] = fl[v];
-        }
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1 && qx >= TJ) break;
+        const bool up = pass == 1;
+        solve_face(std::integral_constant<int, 0>{}, up ? (qx + NG) * P1 + N1 + NG : own,
+                   up ? qx * (N1 + 1) + N1 : tj * (N1 + 1) + ti,
+                   up ? bi.fslot[XHI] : (ti == 0 ? bi.fslot[XLO] : -1), (int64_t)p * n2 + (up ? j0 + qx : j));
+      }
+      if constexpr (PF && PKH_PF_LATE && PKH_PF_SPLIT) prefetch_halo(sl, p + PFD);
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1 && qy >= N1) break;
+        const bool up = pass == 1;
+        solve_face(std::integral_constant<int, 1>{}, up ? (TJ + NG) * P1 + qy + NG : own,
+                   up ? TJ * N1 + qy : tj * N1 + ti,
+                   up ? (j0 + TJ == n2 ? bi.fslot[YHI] : -1) : (j == 0 ? bi.fslot[YLO] : -1),
+                   (int64_t)p * N1 + (up ? qy : ti));
       }
       __syncthreads();
 #pragma unroll
