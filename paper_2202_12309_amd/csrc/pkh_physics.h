@@ -55,13 +55,19 @@ PKH_HD double frsq(double x) {
 
 PKH_HD double fsqrt(double x) { return x * frsq(x); }
 
+// The pointwise functions below are written with explicit fused
+// multiply-adds and with contraction off, so that every inlined copy rounds
+// the same way: a kernel may solve the faces of one direction in several
+// places, and a face shared by two tiles must get the same flux from both.
 PKH_HD bool to_prim(const double u[NVAR], double gam, double w[NVAR]) {
+#pragma clang fp contract(off)
   const double ir = frcp(u[0]);
   w[0] = u[0];
   w[1] = u[1] * ir;
   w[2] = u[2] * ir;
   w[3] = u[3] * ir;
-  w[4] = (gam - 1.0) * (u[4] - 0.5 * (u[1] * w[1] + u[2] * w[2] + u[3] * w[3]));
+  const double mv = fma(u[3], w[3], fma(u[2], w[2], u[1] * w[1]));  // M.v = 2 x kinetic energy
+  w[4] = (gam - 1.0) * fma(-0.5, mv, u[4]);
   return (w[0] > 0.0) && (w[4] > 0.0);  // false also for NaN
 }
 
@@ -80,6 +86,7 @@ PKH_HD double mc_slope(double dl, double dr) {
 // subnormal range) with one multiplication less and the sign applied by a
 // bit copy.
 PKH_HD double mc_half(double dl, double dr) {
+#pragma clang fp contract(off)
   const double s = copysign(1.0, dl);
   const double m = fmin(fmin(fabs(dl), s * dr), copysign(0.25, dl) * (dl + dr));
   return copysign(fmax(m, 0.0), dl);
@@ -98,11 +105,13 @@ struct FState {
 
 // Derived quantities of a state from its primitives.
 PKH_HD void complete_state(FState& q, double gam, double igm1) {
+#pragma clang fp contract(off)
   const double is = frsq(q.r);     // 1/sqrt(rho)
   const double ir = is * is;
   q.sr = q.r * is;
   q.c = fsqrt(gam * q.p * ir);
-  const double e = q.p * igm1 + 0.5 * q.r * (q.v0 * q.v0 + q.v1 * q.v1 + q.v2 * q.v2);
+  const double v2 = fma(q.v2, q.v2, fma(q.v1, q.v1, q.v0 * q.v0));
+  const double e = fma(0.5 * q.r, v2, q.p * igm1);
   q.h = (e + q.p) * ir;
 }
 
@@ -113,13 +122,15 @@ PKH_HD void complete_state(FState& q, double gam, double igm1) {
 template <int D>
 PKH_HD void hlle(const FState& L, const FState& R, double gm1, double f[NVAR],
                                      int drt = 0) {
+#pragma clang fp contract(off)
   const int d = D >= 0 ? D : drt;
   const double r = L.sr * frcp(L.sr + R.sr), r1 = 1.0 - r;
-  const double vb0 = r * L.v0 + r1 * R.v0;
-  const double vb1 = r * L.v1 + r1 * R.v1;
-  const double vb2 = r * L.v2 + r1 * R.v2;
-  const double hb = r * L.h + r1 * R.h;
-  const double ab = fsqrt(gm1 * (hb - 0.5 * (vb0 * vb0 + vb1 * vb1 + vb2 * vb2)));
+  const double vb0 = fma(r, L.v0, r1 * R.v0);
+  const double vb1 = fma(r, L.v1, r1 * R.v1);
+  const double vb2 = fma(r, L.v2, r1 * R.v2);
+  const double hb = fma(r, L.h, r1 * R.h);
+  const double kb = fma(vb2, vb2, fma(vb1, vb1, vb0 * vb0));
+  const double ab = fsqrt(gm1 * fma(-0.5, kb, hb));
   const double vbn = d == 0 ? vb0 : (d == 1 ? vb1 : vb2);
   const double ul = d == 0 ? L.v0 : (d == 1 ? L.v1 : L.v2);
   const double ur = d == 0 ? R.v0 : (d == 1 ? R.v1 : R.v2);
@@ -128,20 +139,18 @@ PKH_HD void hlle(const FState& L, const FState& R, double gm1, double f[NVAR],
   const double ib = frcp(bp - bm);
   const double bpm = bp * bm;
   const double ml = L.r * ul, mr = R.r * ur;  // mass fluxes
-  f[0] = (bp * ml - bm * mr + bpm * (R.r - L.r)) * ib;
+  f[0] = fma(bpm, R.r - L.r, fma(bp, ml, -(bm * mr))) * ib;
   const double vl[3] = {L.v0, L.v1, L.v2}, vr[3] = {R.v0, R.v1, R.v2};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double fl = ml * vl[c], fr = mr * vr[c];
-    if (c == d) {
-      fl += L.p;
-      fr += R.p;
-    }
-    f[1 + c] = (bp * fl - bm * fr + bpm * (R.r * vr[c] - L.r * vl[c])) * ib;
+    const double fl = c == d ? fma(ml, vl[c], L.p) : ml * vl[c];
+    const double fr = c == d ? fma(mr, vr[c], R.p) : mr * vr[c];
+    const double du = fma(R.r, vr[c], -(L.r * vl[c]));
+    f[1 + c] = fma(bpm, du, fma(bp, fl, -(bm * fr))) * ib;
   }
   // energy: E = rho h - P, energy flux (E + P) u = m h
   const double el = fma(L.r, L.h, -L.p), er = fma(R.r, R.h, -R.p);
-  f[4] = (bp * ml * L.h - bm * mr * R.h + bpm * (er - el)) * ib;
+  f[4] = fma(bpm, er - el, fma(bp * ml, L.h, -((bm * mr) * R.h))) * ib;
 }
 
 

@@ -449,40 +449,31 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       prefetch_own(sl, p + PFD);
       if (!PKH_PF_SPLIT || p < 0 || p >= n3) prefetch_halo(sl, p + PFD);
     }
-    // --- x and y faces of plane p, divergence into the queue. Each thread
-    // solves the lower x and y faces of its cell; the tile's upper x and y
-    // faces are solved by the first lanes of two waves.
+    // --- x and y faces of plane p, divergence into the queue.
     if (p >= 0 && p < n3) {
-      // Every face of a direction is solved by one copy of the code (a loop
-      // that is not unrolled, with hlle<0> for x and hlle<1> for y), so a
-      // face shared by two tiles or two blocks gets the same flux bit for bit
-      // on both sides, whichever tile shape is used. Pass 0 solves the lower
-      // face of the own cell; pass 1 the tile's upper x faces (one per row)
-      // on the first lanes of wave wx and its upper y faces (one per column)
-      // on those of the next wave, so the two extra solves land on
-      // different SIMDs; both rotate with the plane and the workgroup so
-      // that no SIMD always gets the extra work.
+      // Each thread solves the lower x and y faces of its cell. The tile's
+      // upper x faces (one per row) go to the first lanes of wave wx, its
+      // upper y faces (one per column) to those of the next wave, so the two
+      // extra solves land on different SIMDs; both rotate with the plane and
+      // the workgroup so that no SIMD always gets the extra work. Every face
+      // of a direction is solved with the direction fixed at compile time
+      // and by arithmetic whose rounding does not depend on where it is
+      // inlined, so a face shared by two tiles or two blocks gets the same
+      // flux bit for bit on both sides, whichever tile shape is used.
       const int wx = (rot + p + 2) % NWAVE;
       const int wy = (wx + 1) % NWAVE;
       const int qx = (tid - wx * 64 + NT) % NT, qy = (tid - wy * 64 + NT) % NT;
-#pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1 && qx >= TJ) break;
-        const bool up = pass == 1;
-        solve_face(std::integral_constant<int, 0>{}, up ? (qx + NG) * P1 + N1 + NG : own,
-                   up ? qx * (N1 + 1) + N1 : tj * (N1 + 1) + ti,
-                   up ? bi.fslot[XHI] : (ti == 0 ? bi.fslot[XLO] : -1), (int64_t)p * n2 + (up ? j0 + qx : j));
-      }
+      solve_face(std::integral_constant<int, 0>{}, own, tj * (N1 + 1) + ti, ti == 0 ? bi.fslot[XLO] : -1,
+                 (int64_t)p * n2 + j);
       if constexpr (PF && PKH_PF_LATE && PKH_PF_SPLIT) prefetch_halo(sl, p + PFD);
-#pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1 && qy >= N1) break;
-        const bool up = pass == 1;
-        solve_face(std::integral_constant<int, 1>{}, up ? (TJ + NG) * P1 + qy + NG : own,
-                   up ? TJ * N1 + qy : tj * N1 + ti,
-                   up ? (j0 + TJ == n2 ? bi.fslot[YHI] : -1) : (j == 0 ? bi.fslot[YLO] : -1),
-                   (int64_t)p * N1 + (up ? qy : ti));
-      }
+      solve_face(std::integral_constant<int, 1>{}, own, tj * N1 + ti, j == 0 ? bi.fslot[YLO] : -1,
+                 (int64_t)p * N1 + ti);
+      if (qx < TJ)
+        solve_face(std::integral_constant<int, 0>{}, (qx + NG) * P1 + N1 + NG, qx * (N1 + 1) + N1,
+                   bi.fslot[XHI], (int64_t)p * n2 + j0 + qx);
+      if (qy < N1)
+        solve_face(std::integral_constant<int, 1>{}, (TJ + NG) * P1 + qy + NG, TJ * N1 + qy,
+                   j0 + TJ == n2 ? bi.fslot[YHI] : -1, (int64_t)p * N1 + qy);
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < QN - 1; ++s)
