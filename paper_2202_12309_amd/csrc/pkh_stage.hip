@@ -205,21 +205,25 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     }
   };
 
-  // Solve the face of direction D (0: x, 1: y) whose upper cell is LDS slot
-  // c0; its flux goes to LDS slot fo, and to the fine-coarse face buffer at
-  // slot fsl (if >= 0), offset o, when the face borders a finer leaf.
-  auto solve_face = [&](auto dirc, int c0, int fo, int fsl, int64_t o) {
+  // Solve the face of direction D (0: x, 1: y; D < 0: the run-time
+  // direction dir, one instruction stream for lanes of both) whose upper
+  // cell is LDS slot c0; its flux goes to LDS slot fo, and to the
+  // fine-coarse face buffer at slot fsl (if >= 0), offset o, when the face
+  // borders a finer leaf. The arithmetic does not depend on D: the
+  // pointwise physics rounds the same in every inlined copy.
+  auto solve_face = [&](auto dirc, int dir, int c0, int fo, int fsl, int64_t o) {
     constexpr int D = decltype(dirc)::value;
+    const int d = D >= 0 ? D : dir;
     FState L, R;
     double fl[NV];
-    face_states(c0, D == 0 ? 1 : P1, L, R);
-    hlle<D>(L, R, gm1, fl);
-    double* dstf = D == 0 ? &sFx[0][fo] : &sFy[0][fo];
-    constexpr int vstr = D == 0 ? NX : NY;
+    face_states(c0, d == 0 ? 1 : P1, L, R);
+    hlle<D>(L, R, gm1, fl, d);
+    double* dstf = d == 0 ? &sFx[0][fo] : &sFy[0][fo];
+    const int vstr = d == 0 ? NX : NY;
 #pragma unroll
     for (int v = 0; v < NV; ++v) dstf[v * vstr] = fl[v];
     if (fsl >= 0) {
-      const int64_t vst = D == 0 ? (int64_t)n3 * n2 : (int64_t)n3 * N1;
+      const int64_t vst = d == 0 ? (int64_t)n3 * n2 : (int64_t)n3 * N1;
 #pragma unroll
       for (int v = 0; v < NV; ++v) fbuf[(int64_t)fsl * fsz + v * vst + o] = fl[v];
     }
@@ -452,28 +456,26 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     // --- x and y faces of plane p, divergence into the queue.
     if (p >= 0 && p < n3) {
       // Each thread solves the lower x and y faces of its cell. The tile's
-      // upper x faces (one per row) go to the first lanes of wave wx, its
-      // upper y faces (one per column) to those of the next wave, so the two
-      // extra solves land on different SIMDs; both rotate with the plane and
-      // the workgroup so that no SIMD always gets the extra work. Every face
-      // of a direction is solved with the direction fixed at compile time
-      // and by arithmetic whose rounding does not depend on where it is
-      // inlined, so a face shared by two tiles or two blocks gets the same
-      // flux bit for bit on both sides, whichever tile shape is used.
-      const int wx = (rot + p + 2) % NWAVE;
-      const int wy = (wx + 1) % NWAVE;
-      const int qx = (tid - wx * 64 + NT) % NT, qy = (tid - wy * 64 + NT) % NT;
-      solve_face(std::integral_constant<int, 0>{}, own, tj * (N1 + 1) + ti, ti == 0 ? bi.fslot[XLO] : -1,
+      // upper x faces (one per row) and upper y faces (one per column) go to
+      // consecutive lanes starting at one wave, rotated with the plane and
+      // the workgroup so that no SIMD always gets the extra work. A face
+      // shared by two tiles or two blocks gets the same flux bit for bit on
+      // both sides, whichever tile shape is used.
+      const int wr = (rot + p + 2) % NWAVE;
+      const int q = (tid - wr * 64 + NT) % NT;
+      solve_face(std::integral_constant<int, 0>{}, 0, own, tj * (N1 + 1) + ti, ti == 0 ? bi.fslot[XLO] : -1,
                  (int64_t)p * n2 + j);
       if constexpr (PF && PKH_PF_LATE && PKH_PF_SPLIT) prefetch_halo(sl, p + PFD);
-      solve_face(std::integral_constant<int, 1>{}, own, tj * N1 + ti, j == 0 ? bi.fslot[YLO] : -1,
+      solve_face(std::integral_constant<int, 1>{}, 1, own, tj * N1 + ti, j == 0 ? bi.fslot[YLO] : -1,
                  (int64_t)p * N1 + ti);
-      if (qx < TJ)
-        solve_face(std::integral_constant<int, 0>{}, (qx + NG) * P1 + N1 + NG, qx * (N1 + 1) + N1,
-                   bi.fslot[XHI], (int64_t)p * n2 + j0 + qx);
-      if (qy < N1)
-        solve_face(std::integral_constant<int, 1>{}, (TJ + NG) * P1 + qy + NG, TJ * N1 + qy,
-                   j0 + TJ == n2 ? bi.fslot[YHI] : -1, (int64_t)p * N1 + qy);
+      if (q < TJ + N1) {
+        const bool xf = q < TJ;
+        const int iy = q - TJ;
+        solve_face(std::integral_constant<int, -1>{}, xf ? 0 : 1,
+                   xf ? (q + NG) * P1 + N1 + NG : (TJ + NG) * P1 + iy + NG, xf ? q * (N1 + 1) + N1 : TJ * N1 + iy,
+                   xf ? bi.fslot[XHI] : (j0 + TJ == n2 ? bi.fslot[YHI] : -1),
+                   xf ? (int64_t)p * n2 + j0 + q : (int64_t)p * N1 + iy);
+      }
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < QN - 1; ++s)
