@@ -117,10 +117,10 @@ struct GroupItem {
 hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
                               const GroupItem* items, int nitems, hipStream_t s);
 // Rows per workgroup tile actually used for a block of n1 x n2 cells and a
-// requested value (0: default, which for n1 = 32 depends on the stage,
-// recon, and on the blocks of the launch, nblocks; 0 there means many); -1
-// if no compiled variant fits.
-int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0, int recon = 1);
+// requested value (0: default, which for n1 = 16 and 32 depends on the
+// blocks of the launch, nblocks; 0 there means unknown); -1 if no compiled
+// variant fits.
+int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0);
 // Ghost face regions of the (leaf, face) pairs jf[2 njf] (faces whose
 // neighbour is on another level).
 hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,

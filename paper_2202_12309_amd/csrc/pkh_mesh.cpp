@@ -1055,8 +1055,8 @@ int pkh_conserved_totals(pkh_mesh* m, double out[5]) {
 
 int pkh_set_tuning(pkh_mesh* m, const pkh_tuning* t) {
   if (!m || !t) return fail(PKH_EINVAL, "null argument");
-  if (m->fp32 && t->tile_rows != 0 && t->tile_rows != 8 && !(m->g.n1 == 32 && t->tile_rows == 16))
-    return fail(PKH_EINVAL, "FP32 state storage takes tile_rows 0, 8 or (rows of 32) 16");
+  if (m->fp32 && t->tile_rows != 0 && t->tile_rows != 8 && t->tile_rows != 16)
+    return fail(PKH_EINVAL, "FP32 state storage takes tile_rows 0, 8 or 16");
   if (stage_tile_rows(m->g.n1, m->g.n2, t->tile_rows) < 0)
     return fail(PKH_EINVAL, "tile_rows %d not available for blocks of %d x %d", t->tile_rows, m->g.n1,
                 m->g.n2);

@@ -304,7 +304,7 @@ def test_packs_do_not_change_results():
 
 def test_full_size_bench_configuration_parity():
     """The bench workload itself: 256^3 in 512 blocks of 32^3, the default
-    launch tiles (8-row predictor, 16-row corrector), against the oracle
+    launch tiles (16 rows for both stages), against the oracle
     element by element after 1, 10 and 100 cycles (about a minute of oracle
     time on 16 threads); clock and totals too."""
     print_case("256^3 turbulent box, 512 blocks of 32^3, bench launch configuration, 100 cycles")
