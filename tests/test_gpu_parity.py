@@ -302,6 +302,40 @@ def test_packs_do_not_change_results():
     gm.close()
 
 
+@pytest.mark.parametrize("case", ["uniform32", "two_level16", "fp32_16"])
+def test_tile_rows_do_not_change_results(case):
+    """Every compiled tile shape gives bitwise the same state: a face shared
+    by two tiles (or two blocks) is solved by the lower-face job of one and
+    the upper-face job of the other, and both must round identically. Covers
+    32^3 blocks (turbulent box), a two-level blast in 16^3 blocks (fine-coarse
+    face fluxes written from both jobs, flux correction) and FP32 storage."""
+    print_case(f"tile rows 4 / 8 / 16, {case}, 6 cycles")
+    from paper_2202_12309_amd.binding import Mesh
+    if case == "uniform32":
+        n, nrb, N, lv, ml = (32, 32, 32), (2, 2, 2), 64, inputs.uniform_leaves((2, 2, 2)), 0
+    elif case == "two_level16":
+        n, nrb, N, ml = (16, 16, 16), (4, 4, 4), 64, 1
+        lv = inputs.sphere_refined_leaves(nrb, radius=0.3)
+    else:
+        n, nrb, N, lv, ml = (16, 16, 16), (2, 2, 2), 32, inputs.uniform_leaves((2, 2, 2)), 0
+    fp32 = case == "fp32_16"
+    outs = []
+    for tj in ((8, 16) if fp32 else (4, 8, 16)):
+        gm = Mesh((N, N, N), n, lv, max_level=ml, fp32_state=fp32)
+        gm.set_tuning(tj)
+        assert gm.tuning()["tile_rows"] == tj
+        if case == "two_level16":
+            gm.upload(inputs.blast(gm.leaves(), n, nrb))
+        else:
+            gm.upload(inputs.turbulent_box(gm.leaves(), n, nrb, seed=2))
+        gm.step(6)
+        outs.append((gm.download(), gm.time()))
+        gm.close()
+    for U, t in outs[1:]:
+        assert np.array_equal(U, outs[0][0])
+        assert t == outs[0][1]
+
+
 def test_full_size_bench_configuration_parity():
     """The bench workload itself: 256^3 in 512 blocks of 32^3, the default
     launch tiles (16 rows for both stages), against the oracle
