@@ -30,6 +30,8 @@ void pkhc_prim_rev(const double* u, double gam, const double* gw, double* gu) { 
 
 double pkhc_mc(double dl, double dr) { return mc_slope(dl, dr); }
 
+double pkhc_mc_half(double dl, double dr) { return mc_half(dl, dr); }
+
 // HLLE flux from primitive face states; d = 0, 1, 2.
 void pkhc_hlle(const double* wl, const double* wr, int d, double gam, double* f) {
   const double igm1 = 1.0 / (gam - 1.0);

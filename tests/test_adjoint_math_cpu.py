@@ -30,6 +30,10 @@ def L():
     lib.pkhc_face_plm_rev.argtypes = [D, C.c_int, C.c_double, D, D]
     lib.pkhc_prim.argtypes = [D, C.c_double, D]
     lib.pkhc_prim_rev.argtypes = [D, C.c_double, D, D]
+    lib.pkhc_mc.argtypes = [C.c_double, C.c_double]
+    lib.pkhc_mc.restype = C.c_double
+    lib.pkhc_mc_half.argtypes = [C.c_double, C.c_double]
+    lib.pkhc_mc_half.restype = C.c_double
     return lib
 
 
@@ -123,3 +127,21 @@ def test_prim_adjoint_matches_fd(L):
         gu = np.zeros(5)
         L.pkhc_prim_rev(p(u), g, p(gw), p(gu))
         assert np.allclose(gu, J.T @ gw, rtol=1e-6, atol=1e-8)
+
+
+def test_half_mc_slope_is_half_the_mc_slope(L):
+    """The stage kernels offset face values by the half slope mc_half; it
+    must equal 0.5 * MC bit for bit (scaling by powers of two is exact) on
+    the limiter's hand cases, both signs, extrema, ties between the three
+    candidates and random pairs over many magnitudes."""
+    hand = [((1.0, 1.0), 0.5), ((1.0, 3.0), 1.0), ((1.0, 0.2), 0.2), ((1.0, -1.0), 0.0),
+            ((0.0, 2.0), 0.0), ((-1.0, -3.0), -1.0), ((2.0, 0.0), 0.0)]
+    for (dl, dr), want in hand:
+        assert L.pkhc_mc_half(dl, dr) == want, (dl, dr)
+    rng = np.random.default_rng(7)
+    dl = rng.standard_normal(20000) * 10.0 ** rng.integers(-12, 6, 20000)
+    dr = rng.standard_normal(20000) * 10.0 ** rng.integers(-12, 6, 20000)
+    ties = [(1.0, 1.0 / 3.0), (3.0, 1.0), (1.0, 7.0 / 3.0), (-2.0, -2.0 / 3.0)]
+    for a, b in list(zip(dl, dr)) + ties:
+        h, f = L.pkhc_mc_half(a, b), L.pkhc_mc(a, b)
+        assert np.float64(h).tobytes() == np.float64(0.5 * f).tobytes() or (h == 0.0 and f == 0.0), (a, b)
