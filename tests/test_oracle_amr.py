@@ -370,3 +370,155 @@ def test_paper_multilevel_mesh_block_counts():
     # a valid, 2:1-balanced tiling the oracle accepts (with blocks of 8^3)
     m = OracleMesh((8, 8, 8), nrb, lv, max_level=g["max_level"])
     assert m.nleaves == len(lv)
+
+
+# ---------------------------------------------------------------------------
+# Regrid: the data of new children (prolongation of the composite field at
+# the parent's level) pinned by closed forms.
+# ---------------------------------------------------------------------------
+
+_COEF = np.array([[2.0, 0.7, -0.4, 0.3],   # per variable: a + b x + c y + d z
+                  [0.3, -0.2, 0.5, 0.1],
+                  [-0.1, 0.4, 0.2, -0.6],
+                  [0.2, 0.1, -0.3, 0.45],
+                  [5.0, 1.1, 0.9, -0.8]])
+
+
+def _linear_state(m, lv, nrb):
+    U = np.empty(m.shape())
+    for k, lf in enumerate(lv):
+        x, y, z = inputs.cell_centers(lf, N8, nrb)
+        for v in range(5):
+            a, b, c, d = _COEF[v]
+            U[k, v] = a + b * x + c * y + d * z
+    return U
+
+
+def _away_from_seam(lf, nrb):
+    """Mask [n3][n2][n1] of the cells of a new child whose parent cell and
+    the parent's two neighbours along every axis lie inside the periodic
+    domain without wrapping (the linear field has its seam at 0 = 1)."""
+    lev = int(lf[0])
+    masks = []
+    for d in range(3):
+        Nc = nrb[d] * N8[d] << (lev - 1)
+        J = int(lf[1 + d]) * N8[d] + np.arange(N8[d])
+        I = J >> 1
+        masks.append((I >= 1) & (I <= Nc - 2))
+    mz, my, mx = np.meshgrid(masks[2], masks[1], masks[0], indexing="ij")
+    return mz & my & mx
+
+
+def _check_children(m, new_leaves, nrb, want_fn):
+    U = m.state()
+    lv = m.leaves()
+    idx = {tuple(int(v) for v in l): k for k, l in enumerate(lv)}
+    checked = 0
+    for lf in new_leaves:
+        k = idx[tuple(lf)]
+        ok = _away_from_seam(lf, nrb)
+        want = want_fn(lf)
+        err = np.abs(U[k][:, ok] - want[:, ok]).max()
+        assert err <= 1e-13 * np.abs(want).max(), (lf, err)
+        checked += int(ok.sum())
+    return checked
+
+
+def test_regrid_children_reproduce_linear_field():
+    """Refining every leaf of a field linear in x, y and z: each child cell
+    takes the field's value at its own centre (the minmod slopes of a linear
+    field are its differences, and a fine centre sits a quarter coarse cell
+    from its parent's centre along each axis). A flipped slope sign, a slope
+    along the wrong axis or a half-cell offset all fail this."""
+    nrb = (4, 4, 4)
+    m = OracleMesh(N8, nrb, inputs.uniform_leaves(nrb), max_level=1)
+    m.set_state(_linear_state(m, m.leaves(), nrb))
+    m.regrid(np.ones(m.nleaves, dtype=np.int8))
+    assert m.nleaves == 512
+    new = [tuple(int(v) for v in l) for l in m.leaves()]
+
+    def want(lf):
+        x, y, z = inputs.cell_centers(lf, N8, nrb)
+        return np.stack([a + b * x + c * y + d * z for a, b, c, d in _COEF])
+    assert _check_children(m, new, nrb, want) > 100000
+
+
+def test_regrid_children_next_to_other_levels():
+    """Two-level mesh, linear field sampled at every leaf's cell centres. A
+    coarse leaf beside the refined region is split (the slope stencils of
+    its outer parent cells reach into finer leaves: composite value =
+    restriction) and a fine leaf inside the refined region is split to level
+    2 (stencils in other level-1 leaves): every child cell equals the field
+    at its centre."""
+    m = _amr_mesh(max_level=2)
+    lv = m.leaves()
+    m.set_state(_linear_state(m, lv, NRB4))
+    flags = np.zeros(len(lv), dtype=np.int8)
+    tgt = {(0, 0, 1, 1): None, (1, 3, 3, 3): None}
+    for k, l in enumerate(lv):
+        if tuple(int(v) for v in l) in tgt:
+            flags[k] = 1
+    assert flags.sum() == 2
+    m.regrid(flags)
+    new = [(1, 2 * 0 + (c & 1), 2 * 1 + ((c >> 1) & 1), 2 * 1 + ((c >> 2) & 1)) for c in range(8)]
+    new += [(2, 6 + (c & 1), 6 + ((c >> 1) & 1), 6 + ((c >> 2) & 1)) for c in range(8)]
+    have = {tuple(int(v) for v in l) for l in m.leaves()}
+    assert set(new) <= have and m.nleaves == len(lv) + 14
+
+    def want(lf):
+        x, y, z = inputs.cell_centers(lf, N8, NRB4)
+        return np.stack([a + b * x + c * y + d * z for a, b, c, d in _COEF])
+    # the children of (0,0,1,1) at its +x face take slopes from the composite
+    # value in the refined root block (1,1,1): they are among those checked
+    assert _check_children(m, new, NRB4, want) > 3000
+
+
+def test_regrid_children_minmod_slopes():
+    """The slopes are minmod-limited one-sided differences of the parent
+    level. On f = 1 + x^2 (refine all, coarse width h, parent centre xc > h)
+    minmod takes the smaller difference 2 xc h - h^2, so a child is
+    c0 + s (2 xc h - h^2) / 4 with s = -1 / +1 for the lower / upper child
+    (a central slope would give s xc h / 2). At an asymmetric kink
+    f = 1 + 2 (x - xk) for x > xk, 1 + (xk - x) below, with xk a parent
+    centre, the one-sided differences have opposite signs: both children of
+    that parent keep its value."""
+    nrb = (4, 1, 1)
+    h = 1.0 / (nrb[0] * N8[0])
+
+    def run(fx):
+        m = OracleMesh(N8, nrb, inputs.uniform_leaves(nrb), max_level=1)
+        U = np.zeros(m.shape())
+        for k, lf in enumerate(m.leaves()):
+            x, _, _ = inputs.cell_centers(lf, N8, nrb)
+            U[k] = fx(x)[None]
+        m.set_state(U)
+        m.regrid(np.ones(m.nleaves, dtype=np.int8))
+        xs, vals = [], []
+        for k, lf in enumerate(m.leaves()):
+            if lf[2] or lf[3]:
+                continue  # one row of leaves along x
+            x, _, _ = inputs.cell_centers(lf, N8, nrb)
+            xs.append(x[0, 0])
+            vals.append(m.state()[k, :, 0, 0])
+        x = np.concatenate(xs)
+        v = np.concatenate(vals, axis=1)
+        o = np.argsort(x)
+        return x[o], v[:, o]
+
+    x, v = run(lambda x: 1.0 + x * x)
+    I = np.floor(x / h).astype(int)
+    xc = (I + 0.5) * h
+    s = np.where(x > xc, 1.0, -1.0)
+    sel = (I >= 1) & (I <= nrb[0] * N8[0] - 2)
+    want = 1.0 + xc * xc + s * (2 * xc * h - h * h) / 4
+    assert np.abs(v[:, sel] - want[sel]).max() <= 1e-14
+    xk = 13.5 * h
+
+    def kink(x):
+        return 1.0 + np.where(x > xk, 2.0 * (x - xk), xk - x)
+    x, v = run(kink)
+    I = np.floor(x / h).astype(int)
+    at = I == 13
+    assert at.sum() == 2 and np.all(v[:, at] == 1.0)
+    near = (I >= 1) & (I <= nrb[0] * N8[0] - 2) & ~at & (np.abs(I - 13) > 0)
+    assert np.abs(v[:, near] - kink(x[near])).max() <= 1e-14
