@@ -214,7 +214,9 @@ int pkh_flag_pressure_jump(pkh_mesh *mesh, double refine_above, double derefine_
    the composite field at the parent's level, a merged parent the
    restriction of its children. The tree and all tables are rebuilt on the
    host, the data moved on the device, ghosts and the timestep recomputed.
-   Flags are cleared. Synchronises. */
+   Flags are cleared. Synchronises. PKH_ESTATE while a tape or a batch
+   holds the mesh (they keep pointers into its leaf layout): destroy them
+   first. */
 int pkh_regrid(pkh_mesh *mesh);
 
 /* Conserved totals sum_leaves sum_active U_v dV (Sec. 3.10 reduction);
@@ -234,7 +236,8 @@ typedef struct pkh_tape pkh_tape;
 /* Tape for the mesh; ckpt_every >= 1. Device memory: one active-state copy
    per checkpoint (allocated as cycles are recorded) plus 2*ckpt_every + 1
    ghost-filled states for recomputation and 2 for the reverse sweep.
-   PKH_EINVAL on multilevel meshes. */
+   PKH_EINVAL on multilevel meshes. While the tape exists the mesh refuses
+   pkh_regrid and pkh_set_partition (PKH_ESTATE). */
 int pkh_tape_create(pkh_mesh *mesh, int32_t ckpt_every, pkh_tape **out);
 int pkh_tape_destroy(pkh_tape *tape);
 
@@ -264,7 +267,8 @@ enum {
   PKH_GRAPH = 2  /* PKH_FUSED with segments of up to 50 cycles replayed from a
                     captured hipGraph */
 };
-/* The results of the three modes are bitwise identical. */
+/* The results of the three modes are bitwise identical. While the batch
+   exists its meshes refuse pkh_regrid and pkh_set_partition (PKH_ESTATE). */
 int pkh_batch_create(pkh_mesh *const *meshes, int32_t n, pkh_batch **out);
 int pkh_batch_destroy(pkh_batch *batch);
 int pkh_batch_step(pkh_batch *batch, int32_t n_cycles, uint32_t mode);
@@ -287,7 +291,8 @@ int pkh_batch_autotune(pkh_batch *batch, int32_t trial_cycles, int32_t *tile_row
    stage kernels then read. Faces inside a part keep the direct reads.
    Results are bitwise those of nparts = 1. nparts in [1, number of leaves];
    the partition survives regrids (recut over the new leaves). A
-   partitioned mesh takes no tape or batch (PKH_EINVAL). Synchronises. */
+   partitioned mesh takes no tape or batch (PKH_EINVAL), and a mesh held by
+   a tape or batch cannot be repartitioned (PKH_ESTATE). Synchronises. */
 int pkh_set_partition(pkh_mesh *mesh, int32_t nparts);
 /* Current parts, remote faces and (sender, receiver) messages per stage;
    any pointer may be NULL. */

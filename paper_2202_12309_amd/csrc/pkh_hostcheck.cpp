@@ -1,7 +1,9 @@
 // pkh_hostcheck.cpp -- host build of the pointwise physics and its
-// hand-written adjoints, exported for the CPU unit tests (finite-difference
-// checks of the reverse mode). Not used by the GPU path.
+// hand-written adjoints, and of the tile-shape choice, exported for the CPU
+// unit tests (finite-difference checks of the reverse mode, launch shapes).
+// Not used by the GPU path.
 #include "pkh_physics.h"
+#include "pkh_tiles.h"
 
 using namespace pkh;
 
@@ -23,6 +25,8 @@ void plm_states(const double* q, double* wl, double* wr) {
 }  // namespace
 
 extern "C" {
+
+int pkhc_tile_rows(int n1, int n2, int tj, long long nblocks) { return stage_tile_rows(n1, n2, tj, nblocks); }
 
 void pkhc_prim(const double* u, double gam, double* w) { to_prim(u, gam, w); }
 

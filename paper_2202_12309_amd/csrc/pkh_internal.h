@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pkh_tiles.h"
+
 namespace pkh {
 
 constexpr int NV = 5;  // rho, M1, M2, M3, E
@@ -116,11 +118,6 @@ struct GroupItem {
 // width n1 and tile rows tj; insts/items are device arrays.
 hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
                               const GroupItem* items, int nitems, hipStream_t s);
-// Rows per workgroup tile actually used for a block of n1 x n2 cells and a
-// requested value (0: default, which for n1 = 16 and 32 depends on the
-// blocks of the launch, nblocks; 0 there means unknown); -1 if no compiled
-// variant fits.
-int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0);
 // Ghost face regions of the (leaf, face) pairs jf[2 njf] (faces whose
 // neighbour is on another level).
 hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,

@@ -732,14 +732,24 @@ hipError_t launch_gather(double* dst, const float* u, int32_t nblocks, const Geo
 }
 
 // ---------------------------------------------------------------------------
-// Conserved totals: per-block sums in a fixed order, then one workgroup sums
-// the block partials in a fixed order (bitwise reproducible).
+// Conserved totals: per-block sums in a fixed order (per-thread strided sums,
+// a butterfly of wave shuffles, the block's waves in index order), then one
+// workgroup sums the block partials the same way (bitwise reproducible).
 // ---------------------------------------------------------------------------
+
+// Sum over the 64 lanes of a wave by an xor butterfly: lanes l and l^off add
+// the same two values at each step, so every lane ends with the same sum,
+// formed in a fixed order.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
 
 template <typename S>
 __global__ void __launch_bounds__(256) block_sum_kernel(double* partial, const S* u,
                                                         const BlockInfo* blocks, Geom g) {
-  __shared__ double sh[NV][256];
+  __shared__ double sh[NV][4];
   const int b = blockIdx.x;
   const BlockInfo bi = blocks[b];
   const int ncell = g.n1 * g.n2 * g.n3;
@@ -751,37 +761,35 @@ __global__ void __launch_bounds__(256) block_sum_kernel(double* partial, const S
     for (int v = 0; v < NV; ++v) acc[v] += static_cast<double>(cell[v * g.vstride]);
   }
 #pragma unroll
-  for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = acc[v];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
+  for (int v = 0; v < NV; ++v) acc[v] = wave_sum(acc[v]);
+  if ((threadIdx.x & 63) == 0)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
-    __syncthreads();
-  }
+    for (int v = 0; v < NV; ++v) sh[v][threadIdx.x >> 6] = acc[v];
+  __syncthreads();
   if (threadIdx.x < NV) {
+    const int v = threadIdx.x;
     const double dV = 1.0 / (bi.idx[0] * bi.idx[1] * bi.idx[2]);
-    partial[(int64_t)b * NV + threadIdx.x] = sh[threadIdx.x][0] * dV;
+    partial[(int64_t)b * NV + v] = ((sh[v][0] + sh[v][1]) + (sh[v][2] + sh[v][3])) * dV;
   }
 }
 
 __global__ void __launch_bounds__(256) final_sum_kernel(double* out, const double* partial,
                                                         int nblocks) {
-  __shared__ double sh[NV][256];
+  __shared__ double sh[NV][4];
   double acc[NV] = {0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += 256)
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += partial[(int64_t)b * NV + v];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = acc[v];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
+  for (int v = 0; v < NV; ++v) acc[v] = wave_sum(acc[v]);
+  if ((threadIdx.x & 63) == 0)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
-    __syncthreads();
+    for (int v = 0; v < NV; ++v) sh[v][threadIdx.x >> 6] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int v = threadIdx.x;
+    out[v] = (sh[v][0] + sh[v][1]) + (sh[v][2] + sh[v][3]);
   }
-  if (threadIdx.x < NV) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 template <typename S>

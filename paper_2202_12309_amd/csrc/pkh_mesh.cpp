@@ -217,6 +217,9 @@ struct pkh_mesh {
   bool ghosts_valid = false;
   int32_t tj = 0;
   int32_t packs = 1;  // stage launches per stage (contiguous leaf ranges)
+  // tapes and batches holding pointers into the leaf layout (regrid and
+  // partition changes are refused while any is attached)
+  int32_t attached = 0;
   // kernel timing: event pairs around launches of the selected kinds
   uint32_t kt_mask = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -916,6 +919,9 @@ int pkh_flag_pressure_jump(pkh_mesh* m, double refine_above, double derefine_bel
 
 int pkh_regrid(pkh_mesh* m) {
   if (!m) return fail(PKH_EINVAL, "null mesh");
+  if (m->attached)
+    return fail(PKH_ESTATE, "%d tape(s) or batch(es) hold this mesh's layout; destroy them before a regrid",
+                m->attached);
   const Tree& t = m->tree;
   const int64_t nl = m->nb();
   std::vector<char> ref(nl, 0), der(nl, 0);
@@ -1073,6 +1079,9 @@ int pkh_set_partition(pkh_mesh* m, int32_t nparts) {
   if (nparts < 1 || nparts > m->nb()) return fail(PKH_EINVAL, "nparts must be in [1, %lld]", (long long)m->nb());
   if (m->fp32 && nparts > 1) return fail(PKH_EINVAL, "partitions need an FP64-stored state");
   if (nparts == m->nparts) return PKH_OK;
+  if (m->attached)
+    return fail(PKH_ESTATE, "%d tape(s) or batch(es) hold this mesh's layout; destroy them before repartitioning",
+                m->attached);
   HIPCHK(hipStreamSynchronize(m->stream));  // queued work may use the tables
   drop_graph(m);
   m->nparts = nparts;
@@ -1243,6 +1252,7 @@ int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
   for (double* p : t->S) HIPCHK(hipMemsetAsync(p, 0, pb, m->stream));
   for (double* p : t->Us) HIPCHK(hipMemsetAsync(p, 0, pb, m->stream));
   HIPCHK(hipMemcpyAsync(t->d_time, m->d_time, sizeof(DevTime), hipMemcpyDeviceToDevice, m->stream));
+  m->attached++;
   *out = t;
   return PKH_OK;
 }
@@ -1251,6 +1261,7 @@ int pkh_tape_destroy(pkh_tape* t) {
   if (!t) return PKH_OK;
   (void)hipStreamSynchronize(t->m->stream);
   tape_free(t);
+  t->m->attached--;
   delete t;
   return PKH_OK;
 }
@@ -1351,6 +1362,7 @@ struct pkh_batch {
   DevTime** d_tms = nullptr;        // per mesh clock
   hipGraphExec_t gexec = nullptr;
   int32_t g_cycles = 0;
+  bool attached = false;            // counted in every member's attached count
 };
 
 namespace {
@@ -1538,6 +1550,8 @@ int pkh_batch_create(pkh_mesh* const* meshes, int32_t n, pkh_batch** out) {
     pkh_batch_destroy(b);
     return rc;
   }
+  for (pkh_mesh* m : b->meshes) m->attached++;
+  b->attached = true;
   *out = b;
   return PKH_OK;
 }
@@ -1551,6 +1565,8 @@ int pkh_batch_destroy(pkh_batch* b) {
   m0->dfree(b->d_pred);
   m0->dfree(b->d_corr);
   m0->dfree(b->d_tms);
+  if (b->attached)
+    for (pkh_mesh* m : b->meshes) m->attached--;
   delete b;
   return PKH_OK;
 }

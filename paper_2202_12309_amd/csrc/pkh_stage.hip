@@ -582,27 +582,6 @@ static hipError_t launch_stage_n(const StageLaunch& a, hipStream_t s) {
   return a.recon ? launch_stage_t<1, N1, TJ>(a, s) : launch_stage_t<0, N1, TJ>(a, s);
 }
 
-int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks) {
-  // compiled (N1, TJ) variants; the first is the default. For n1 = 32 both
-  // stages take 16 rows once the launch has at least two rounds of waves at
-  // two waves per SIMD (4096 waves), else 8; for n1 = 16 (one workgroup of
-  // four waves per block at 16 rows) from 1024 waves on, else 8. Measured:
-  // 16 rows against 8 save 1.5 % of the 256^3 cycle with blocks of 32^3, 3 %
-  // with blocks of 16^3, and 7 % of the two-level blast (960 leaves of 16^3).
-  static const int opts[4][3] = {{8, 8, 0}, {8, 16, 4}, {16, 8, 4}, {4, 2, 0}};
-  const int row = n1 == 8 ? 0 : n1 == 16 ? 1 : n1 == 32 ? 2 : n1 == 64 ? 3 : -1;
-  if (row < 0) return -1;
-  if (tj == 0) {
-    tj = opts[row][0];
-    const bool large = nblocks > 0 && nblocks * n1 * n2 / 64 >= 4096;
-    if (n1 == 32 && nblocks > 0 && !large) tj = 8;
-    if (n1 == 16 && nblocks > 0 && nblocks * n1 * n2 / 64 >= 1024) tj = 16;
-  }
-  for (int q = 0; q < 3; ++q)
-    if (opts[row][q] == tj && tj > 0 && n2 % tj == 0) return tj;
-  return -1;
-}
-
 hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
                               const GroupItem* items, int nitems, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;

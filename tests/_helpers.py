@@ -1,5 +1,7 @@
 """Shared helpers of the GPU parity tests (no method arithmetic here)."""
+import ctypes
 import os
+import subprocess
 import sys
 
 import numpy as np
@@ -7,6 +9,24 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+
+CSRC = os.path.join(ROOT, "paper_2202_12309_amd", "csrc")
+HOSTCHECK_LIB = os.path.join(ROOT, "paper_2202_12309_amd", "libpkhcheck.so")
+
+
+def host_check_lib():
+    """The library's host build of its pointwise physics and tile-shape
+    choice (pkh_hostcheck.cpp), compiled with g++ when stale."""
+    src = os.path.join(CSRC, "pkh_hostcheck.cpp")
+    deps = [src] + [os.path.join(CSRC, h) for h in ("pkh_physics.h", "pkh_tiles.h")]
+    if (not os.path.exists(HOSTCHECK_LIB)
+            or os.path.getmtime(HOSTCHECK_LIB) < max(os.path.getmtime(d) for d in deps)):
+        tmp = HOSTCHECK_LIB + f".tmp{os.getpid()}"
+        subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I", CSRC, src, "-o", tmp],
+                       check=True)
+        os.replace(tmp, HOSTCHECK_LIB)
+    return ctypes.CDLL(HOSTCHECK_LIB)
 
 
 def gpu_available():

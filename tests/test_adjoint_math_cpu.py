@@ -3,27 +3,18 @@ HLLE with Einfeldt speeds, PLM-MC face states) against central finite
 differences of the same functions, compiled for the host from the GPU
 sources. CPU only."""
 import ctypes as C
-import os
-import subprocess
 
 import numpy as np
 import pytest
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-CSRC = os.path.join(ROOT, "paper_2202_12309_amd", "csrc")
-LIB = os.path.join(ROOT, "paper_2202_12309_amd", "libpkhcheck.so")
+from _helpers import host_check_lib
+
 D = C.POINTER(C.c_double)
 
 
 @pytest.fixture(scope="module")
 def L():
-    src = os.path.join(CSRC, "pkh_hostcheck.cpp")
-    hdr = os.path.join(CSRC, "pkh_physics.h")
-    if (not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(src),
-                                                                os.path.getmtime(hdr))):
-        subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I", CSRC, src, "-o", LIB],
-                       check=True)
-    lib = C.CDLL(LIB)
+    lib = host_check_lib()
     lib.pkhc_hlle.argtypes = [D, D, C.c_int, C.c_double, D]
     lib.pkhc_hlle_rev.argtypes = [D, D, C.c_int, C.c_double, D, D, D]
     lib.pkhc_face_plm.argtypes = [D, C.c_int, C.c_double, D]

@@ -175,3 +175,30 @@ def test_gradient_matches_reference_at_bench_mesh():
     err = np.abs(g_gpu - g_ref).reshape(len(lv), 5, -1).max(axis=(0, 2)) / scale.max()
     print("grad rel err", err, flush=True)
     assert np.all(err <= 1e-8), err
+
+
+def test_gradient_matches_reference_checkpoint_schedule():
+    """The adjoint workload's schedule -- 50 cycles with a checkpoint every 10
+    (five full segments, each recomputed from its checkpoint) -- on 32^3 as 8
+    blocks of 16^3, against the reference gradient. The general flow of the
+    tests above (velocity and pressure structure) keeps every limiter and
+    wave-speed branch away from rounding-size ties, so both sides take the
+    same branches."""
+    print_case("adjoint vs reference, 32^3 as 8 blocks of 16^3, 50 cycles, checkpoint every 10")
+    N, blk, cycles, ckpt = 32, 16, 50, 10
+    mesh, lv, n, nrb, U0, tgt = _setup(N, blk, amp=3e-2)
+    U0 = U0 + 0.05 * inputs.turbulent_box(lv, n, nrb, seed=9) - 0.05 * inputs.uniform_state(lv, n)
+    dV = 1.0 / N ** 3
+    loss, g_gpu, _ = _gpu_grad(mesh, U0, tgt, cycles, ckpt, dV)
+    print("gpu gradient done", flush=True)
+    G0 = torch.tensor(torch_ref.blocks_to_global(U0, lv, n, nrb), requires_grad=True)
+    GN, _ = torch_ref.run(G0, cycles)
+    rho_t = torch.tensor(torch_ref.blocks_to_global(np.stack([tgt] * 5, axis=1), lv, n, nrb)[0])
+    L = 0.5 * ((GN[0] - rho_t) ** 2).sum() * dV
+    L.backward()
+    g_ref = torch_ref.global_to_blocks(G0.grad.numpy(), lv, n)
+    assert abs(loss - float(L)) <= 1e-10 * abs(float(L))
+    scale = np.abs(g_ref).reshape(len(lv), 5, -1).max(axis=(0, 2))
+    err = np.abs(g_gpu - g_ref).reshape(len(lv), 5, -1).max(axis=(0, 2)) / scale.max()
+    print("grad rel err", err, flush=True)
+    assert np.all(err <= 1e-8), err

@@ -47,27 +47,37 @@ def test_pressure_jump_indicator_matches_oracle():
 
 
 def _regrid_loop(gm, om, segments, every):
+    counts = []
     for s in range(segments):
         gm.step(every)
         om.step(every)
         c = (s + 1) * every
+        tol = min(1e-11 * c, 1e-9)
         err = rel_err(gm.download(), om.state(), G)
         print(f"cycle {c}: leaves {gm.nleaves}, rel err {err}", flush=True)
-        assert np.all(err <= 1e-11 * c), (c, err)
+        assert np.all(err <= tol), (c, err)
         To, Ao = om.totals()
         assert np.all(np.abs(gm.totals() - To) <= 1e-13 * np.maximum(Ao, 1.0))
         flags = _flags(om.pressure_jump())
         gm.regrid(flags)
         om.regrid(flags)
         assert np.array_equal(gm.leaves(), om.leaves())
-        assert np.all(rel_err(gm.download(), om.state(), G) <= 1e-11 * c)
+        assert np.all(rel_err(gm.download(), om.state(), G) <= tol)
+        counts.append(gm.nleaves)
+    return counts
 
 
 def test_two_level_blast_regrid_parity_full_size():
-    print_case("two-level blast, 128^3 root, 960 leaves, 30 cycles, regrid every 10")
+    """The two-level blast at full size and length: 128^3 root in 16^3
+    blocks, 960 leaves at the start, 200 cycles with a regrid every 10 (20
+    regrids) by the oracle's pressure-jump flags applied to both sides:
+    within 1e-11 per cycle of the oracle (at most 1e-9), identical leaves
+    after every regrid, totals to 1e-13."""
+    print_case("two-level blast, 128^3 root, 960 leaves, 200 cycles, regrid every 10")
     gm, om = _blast_pair((8, 8, 8))
     assert gm.nleaves == 960
-    _regrid_loop(gm, om, 3, 10)
+    counts = _regrid_loop(gm, om, 20, 10)
+    assert len(set(counts)) > 1  # the mesh follows the blast
 
 
 def test_two_level_blast_regrid_parity_100_cycles():

@@ -296,6 +296,13 @@ def test_packs_do_not_change_results():
         gm.close()
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+    # and the packed runs equal the oracle's run of the same mesh
+    om = OracleMesh(n, nrb, lv, max_level=1)
+    om.set_state(inputs.blast(om.leaves(), n, nrb))
+    om.step(5)
+    err = rel_err(outs[1], om.state(), G)
+    print("3 packs vs oracle, rel err", err, flush=True)
+    assert np.all(err <= 5e-11), err
     gm = Mesh((64, 64, 64), n, lv, max_level=1)
     with pytest.raises(PkhError):
         gm.set_tuning(0, -1)
