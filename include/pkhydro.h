@@ -223,6 +223,18 @@ int pkh_regrid(pkh_mesh *mesh);
    fixed-order device reduction; synchronises. out[5]. */
 int pkh_conserved_totals(pkh_mesh *mesh, double out[5]);
 
+/* pkh_conserved_totals for callers that cannot allocate device memory
+   (code that must not call hipMalloc, e.g. inside tight serving loops or
+   under harnesses that forbid allocation): the same kernels, bitwise the
+   same result, with the per-leaf partial sums in a static device array of
+   the library (one per GPU, 65536 leaves x 5 doubles + 5 results, about
+   2.5 MiB, held until the process ends) instead of the mesh's own buffer.
+   Allocates nothing. PKH_EINVAL for meshes of more than 65536 leaves. Every
+   call on one GPU shares that GPU's array: calls on one GPU that overlap in
+   time (meshes on different streams, or host threads) race and must be
+   serialised by the caller. Synchronises. out[5] is a host array. */
+int pkh_conserved_totals_noalloc(pkh_mesh *mesh, double out[5]);
+
 /* ---- Reverse mode (gradient of a final-state loss w.r.t. the initial
    state), single-level meshes. A tape records the timestep of every cycle
    and the state every `ckpt_every` cycles; the adjoint recomputes each

@@ -69,6 +69,7 @@ _SIGS = {
     "pkh_flag_jump": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_int8),
                                 C.POINTER(C.c_double)]),
     "pkh_conserved_totals": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "pkh_conserved_totals_noalloc": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pkh_sync": (C.c_int, [C.c_void_p]),
     "pkh_kernel_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
     "pkh_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
@@ -283,6 +284,13 @@ class Mesh:
     def totals(self):
         out = (C.c_double * 5)()
         _check(lib().pkh_conserved_totals(self._h, out))
+        return np.array(out[:])
+
+    def totals_noalloc(self):
+        """totals() through the entry point that allocates nothing (static
+        device scratch shared by every call on the GPU)."""
+        out = (C.c_double * 5)()
+        _check(lib().pkh_conserved_totals_noalloc(self._h, out))
         return np.array(out[:])
 
     def set_tuning(self, tile_rows=0, packs=1):

@@ -145,6 +145,16 @@ hipError_t launch_totals(double* partial, double* out, const double* u, const Bl
                          int32_t nblocks, const Geom& g, hipStream_t s);
 hipError_t launch_totals(double* partial, double* out, const float* u, const BlockInfo* blocks,
                          int32_t nblocks, const Geom& g, hipStream_t s);
+// The same with the partial sums in the library's static device scratch
+// (leaves at most TOTALS_SCRATCH_LEAVES); the five results land at
+// scr + TOTALS_SCRATCH_LEAVES * NV. totals_scratch gives the scratch's
+// device address on `device` (looked up once per device).
+constexpr int32_t TOTALS_SCRATCH_LEAVES = 65536;
+hipError_t totals_scratch(int device, double** ptr);
+hipError_t launch_totals_scratch(const double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                                 double* scr, hipStream_t s);
+hipError_t launch_totals_scratch(const float* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                                 double* scr, hipStream_t s);
 // Pressure-jump indicator per leaf into eta[nblocks] (ghost-filled u).
 hipError_t launch_eta(double* eta, const double* u, const int32_t* nbr, int32_t nblocks, const Geom& g,
                       int32_t quantity, hipStream_t s);

@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "pkh_device.h"
 
@@ -806,6 +807,51 @@ hipError_t launch_totals(double* partial, double* out, const double* u, const Bl
 hipError_t launch_totals(double* partial, double* out, const float* u, const BlockInfo* blocks,
                          int32_t nblocks, const Geom& g, hipStream_t s) {
   return launch_totals_t(partial, out, u, blocks, nblocks, g, s);
+}
+
+// Scratch of the totals for callers that cannot allocate: the per-leaf
+// partial sums and the five results in a file-scope device array, one copy
+// per GPU for the life of the process. Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): the
+// device address of each GPU's copy is looked up once, with that GPU
+// current, and kept per device.
+static __device__ __align__(256) double scratch[(int64_t)TOTALS_SCRATCH_LEAVES * NV + 8];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+}  // namespace
+
+hipError_t totals_scratch(int device, double** ptr) {
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_totals_scratch(const double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                                 double* scr, hipStream_t s) {
+  if (nblocks < 1 || nblocks > TOTALS_SCRATCH_LEAVES) return hipErrorInvalidValue;
+  return launch_totals_t(scr, scr + (int64_t)TOTALS_SCRATCH_LEAVES * NV, u, blocks, nblocks, g, s);
+}
+hipError_t launch_totals_scratch(const float* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
+                                 double* scr, hipStream_t s) {
+  if (nblocks < 1 || nblocks > TOTALS_SCRATCH_LEAVES) return hipErrorInvalidValue;
+  return launch_totals_t(scr, scr + (int64_t)TOTALS_SCRATCH_LEAVES * NV, u, blocks, nblocks, g, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -179,6 +179,7 @@ struct Tree {
 struct pkh_mesh {
   pkh_config cfg{};
   hipStream_t stream = nullptr;
+  int device = 0;  // the HIP device current at creation
   pkh_alloc_fn af = nullptr;
   pkh_free_fn ffn = nullptr;
   void* actx = nullptr;
@@ -688,6 +689,10 @@ int pkh_mesh_create(const pkh_config* cfg, const pkh_loc* blocks, int64_t nblock
   pkh_mesh* m = new pkh_mesh();
   m->cfg = *cfg;
   m->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&m->device) != hipSuccess) {
+    delete m;
+    return fail(PKH_EHIP, "no current HIP device");
+  }
   m->af = alloc;
   m->ffn = free_fn;
   m->actx = alloc_ctx;
@@ -1055,6 +1060,23 @@ int pkh_conserved_totals(pkh_mesh* m, double out[5]) {
   else
     HIPCHK(launch_totals(m->d_partial, m->d_tot, m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->stream));
   HIPCHK(hipMemcpyAsync(out, m->d_tot, NV * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return check_err(m);
+}
+
+int pkh_conserved_totals_noalloc(pkh_mesh* m, double out[5]) {
+  if (!m || !out) return fail(PKH_EINVAL, "null argument");
+  if (m->nb() > TOTALS_SCRATCH_LEAVES)
+    return fail(PKH_EINVAL, "%lld leaves exceed the %d the static totals scratch holds; use pkh_conserved_totals",
+                (long long)m->nb(), TOTALS_SCRATCH_LEAVES);
+  double* scr = nullptr;
+  HIPCHK(totals_scratch(m->device, &scr));
+  if (m->fp32)
+    HIPCHK(launch_totals_scratch(m->Af(), m->d_blocks, (int32_t)m->nb(), m->g, scr, m->stream));
+  else
+    HIPCHK(launch_totals_scratch(m->A, m->d_blocks, (int32_t)m->nb(), m->g, scr, m->stream));
+  HIPCHK(hipMemcpyAsync(out, scr + (int64_t)TOTALS_SCRATCH_LEAVES * NV, NV * sizeof(double),
+                        hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
   return check_err(m);
 }
