@@ -28,17 +28,34 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, a fused multiply-add counted as t
 # to these numbers.
 ALG_FLOPS = {"predictor": 461, "corrector": 731, "cfl": 21}
 N = 256
-# sources of the stage kernels: the committed traffic counters are used only
-# while these are unchanged
-STAGE_SRCS = [os.path.join(ROOT, "paper_2202_12309_amd", "csrc", f)
-              for f in ("pkh_stage.hip", "pkh_device.h", "pkh_physics.h", "pkh_internal.h")]
+STAGE_HOST_MARK = "// ---- host-side launchers: everything below runs on the host ----"
+DEVICE_STRUCTS = ("BlockInfo", "DevTime", "LevelMaps", "Geom", "FineFace", "StageLaunch", "GroupItem")
+
+
+def stage_device_source():
+    """The source text that defines the stage kernels' device code: the
+    kernels of pkh_stage.hip (up to its host-side launchers), the device
+    helpers and pointwise physics they include, and the layouts of the
+    structures they read from pkh_internal.h. Host-side changes (launch
+    shapes, tables, entry points) leave it unchanged."""
+    import re
+    csrc = os.path.join(ROOT, "paper_2202_12309_amd", "csrc")
+    st = open(os.path.join(csrc, "pkh_stage.hip")).read()
+    parts = [st[:st.index(STAGE_HOST_MARK)] if STAGE_HOST_MARK in st else st]
+    for f in ("pkh_device.h", "pkh_physics.h"):
+        parts.append(open(os.path.join(csrc, f)).read())
+    inter = open(os.path.join(csrc, "pkh_internal.h")).read()
+    for name in DEVICE_STRUCTS:
+        m = re.search(r"struct %s \{.*?\n\};" % name, inter, re.S)
+        parts.append(m.group(0) if m else name)
+    parts += re.findall(r"^constexpr int [A-Z]+ = \d+;|^enum : int \{[^}]*\};", inter, re.M)
+    return "\n".join(parts)
 
 
 def stage_source_sha():
-    h = hashlib.sha256()
-    for f in STAGE_SRCS:
-        h.update(open(f, "rb").read())
-    return h.hexdigest()
+    """SHA-256 of the stage kernels' device source (stage_device_source): the
+    committed rocprofv3 counters are used only while it is unchanged."""
+    return hashlib.sha256(stage_device_source().encode()).hexdigest()
 
 
 def algorithmic_bytes(n):
@@ -52,6 +69,14 @@ def algorithmic_bytes(n):
     Predictor: h * 40 + 40. Cycle: 80 h + 120 (230 B at n = 32)."""
     h = 1.0 + 12.0 / n
     return h * 40.0 + 80.0, 80.0 * h + 120.0
+
+
+def stage_floor_bytes():
+    """The stage-wise floor of the method, FP64, 5 variables: each stage reads
+    its input state and writes its output once, the corrector also reads U^n
+    (no halo re-reads): corrector 40 + 40 + 40 = 120 B per zone, the cycle
+    (40 + 40) + 120 = 200 B per zone-cycle."""
+    return 120.0, 200.0
 
 
 def ghost_materialised_bytes(n):
@@ -92,23 +117,27 @@ def valu_from_profile(kernel_sha):
     return rec
 
 
-def cpu_baseline(blk, cycles=16):
-    """The oracle, as it stands, on the same 256^3 workload for a bounded
-    number of cycles on this host's cores."""
-    from oracle import oracle as orc
-    from paper_2202_12309_amd import inputs
-    n = (blk,) * 3
-    nrb = (N // blk,) * 3
-    lv = inputs.uniform_leaves(nrb)
-    om = orc.OracleMesh(n, nrb, lv)
-    om.set_state(inputs.turbulent_box(om.leaves(), n, nrb, seed=2))
-    t0 = time.perf_counter()
-    om.step(cycles)
-    el = time.perf_counter() - t0
-    return {"value": N ** 3 * cycles / el, "unit": "zone-cycles/s", "cores": orc.threads(),
+def cpu_baseline(blk):
+    """The oracle, as it stands, compiled -O3 -march=native -fopenmp on this
+    host and timed on the same 256^3 workload in a child process: all cores
+    of the process (OMP_NUM_THREADS, else its CPU affinity) over 4 cycles and
+    one core over 1 cycle, median of 3 runs each."""
+    import subprocess
+    r = subprocess.run([sys.executable, "-m", "oracle.timing", "--block", str(blk)], cwd=ROOT,
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError("oracle timing failed: " + r.stderr[-2000:])
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    a, o = rec["all_core"], rec["one_core"]
+    return {"value": a["zone_cycles_per_s"], "unit": "zone-cycles/s", "cores": a["threads"],
             "kind": "oracle",
-            "sample": f"{cycles} full cycles of the same 256^3 mesh ({N**3 * cycles} zone-cycles, "
-                      f"{el:.1f} s wall)"}
+            "sample": f"{a['cycles']} full cycles of the same 256^3 mesh per run "
+                      f"({N ** 3 * a['cycles']} zone-cycles), median of {len(a['seconds'])} runs "
+                      f"({a['median_s']} s); one core: {o['cycles']} cycle per run, median "
+                      f"{o['median_s']} s",
+            "build": rec["build"], "cpu_model": rec["cpu_model"], "affinity_cpus": rec["affinity_cpus"],
+            "single_core": {"value": o["zone_cycles_per_s"], "cores": 1},
+            "runs_s": {"all_core": a["seconds"], "one_core": o["seconds"]}}
 
 
 def adjoint_ratio(cycles=50, ckpt=10):
@@ -117,7 +146,8 @@ def adjoint_ratio(cycles=50, ckpt=10):
     checkpoint every 10 cycles; loss = L2 misfit of the final density to a
     seeded target. Returns the per-cycle cost of the reverse sweep (the
     adjoint stage kernels only) and of the whole gradient (recomputation
-    included) relative to one forward cycle."""
+    included) relative to one plain forward cycle (pkh_step, no tape) of the
+    same mesh."""
     import torch
     from paper_2202_12309_amd import inputs
     from paper_2202_12309_amd.binding import Mesh
@@ -147,11 +177,23 @@ def adjoint_ratio(cycles=50, ckpt=10):
         ev[3].synchronize()
         kt = mesh.kernel_times()
         mesh.kernel_timing(0)
-    t_fwd = ev[0].elapsed_time(ev[1]) / cycles
+    t_taped = ev[0].elapsed_time(ev[1]) / cycles
     t_adj = ev[2].elapsed_time(ev[3]) / cycles
     t_rev = kt["adjoint"][0] / cycles
+    # the denominator: plain forward cycles (no tape) of the same mesh and state
+    tape.close()
+    mesh.upload(U0)
+    mesh.step(5)
+    mesh.sync()
+    ev[0].record(mesh.stream)
+    mesh.step(cycles)
+    ev[1].record(mesh.stream)
+    ev[1].synchronize()
+    t_fwd = ev[0].elapsed_time(ev[1]) / cycles
+    mesh.close()
     return {"workload": "128^3 FP64, 64 blocks of 32^3, 50 cycles, checkpoint every 10",
-            "forward_ms_per_cycle": round(t_fwd, 4), "reverse_sweep_ms_per_cycle": round(t_rev, 4),
+            "forward_ms_per_cycle": round(t_fwd, 4), "taped_forward_ms_per_cycle": round(t_taped, 4),
+            "reverse_sweep_ms_per_cycle": round(t_rev, 4),
             "gradient_ms_per_cycle": round(t_adj, 4),
             "reverse_sweep_over_forward": round(t_rev / t_fwd, 3),
             "gradient_over_forward": round(t_adj / t_fwd, 3)}
@@ -161,7 +203,9 @@ def batch_leg(cycles=50):
     """64 independent FP64 periodic instances (edges 32..128, blocks 16^3 or
     32^3, sound-wave or blast initial conditions; seed 4): aggregate
     zone-cycles/s of the plain per-instance launches, the grouped launches,
-    the captured-graph replays, and the graph after autotuning."""
+    the captured-graph replays, the persistent launch, and the graph and the
+    persistent launch after autotuning (tile rows of the grouped launches,
+    waves per SIMD of the persistent kernel)."""
     import torch
     from paper_2202_12309_amd import inputs
     from paper_2202_12309_amd.binding import Batch, Mesh
@@ -181,9 +225,11 @@ def batch_leg(cycles=50):
            "cells": cells, "cycles_timed": cycles}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for label, mode, tune in (("plain", "plain", False), ("fused", "fused", False),
-                              ("graph", "graph", False), ("graph_autotuned", "graph", True)):
+                              ("graph", "graph", False), ("persistent", "persistent", False),
+                              ("graph_autotuned", "graph", True), ("persistent_autotuned", "persistent", False)):
         if tune:
             out["autotuned_tile_rows"] = sorted(set(b.autotune(3)))
+            out["autotuned_persistent_waves_per_simd"] = b.tuning()["waves_per_simd"]
         b.step(cycles, mode)  # warm-up (and graph capture)
         torch.cuda.synchronize()
         ev0.record(stream)
@@ -193,6 +239,8 @@ def batch_leg(cycles=50):
         ms = ev0.elapsed_time(ev1)
         out[label] = cells * cycles / (ms / 1e3)
     out["speedup_graph_vs_plain"] = out["graph_autotuned"] / out["plain"]
+    out["speedup_persistent_vs_plain"] = out["persistent_autotuned"] / out["plain"]
+    out["speedup_persistent_vs_fused"] = out["persistent_autotuned"] / out["fused"]
     b.close()
     return out
 
@@ -307,6 +355,40 @@ def packs_leg(cycles=20, warmup=3):
             res[str(P)] = N ** 3 * cycles / (ev0.elapsed_time(ev1) / 1e3)
         out[f"block_{blk}"] = res
         mesh.close()
+    return out
+
+
+def block_sweep_leg(cycles=20, warmup=5):
+    """The 256^3 turbulent box (seed 2) cut into blocks of 16^3 (4096), 32^3
+    (512) and 64^3 (64), one pack, default tiles: zone-cycles/s and the
+    stage-kernel times for each block size."""
+    import torch
+    from paper_2202_12309_amd import inputs
+    from paper_2202_12309_amd.binding import Mesh
+    out = {"workload": f"256^3 turbulent box (seed 2), {cycles} cycles per point"}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fields = inputs.turbulent_box_global((N, N, N), seed=2)
+    for blk in (16, 32, 64):
+        n = (blk,) * 3
+        nrb = (N // blk,) * 3
+        mesh = Mesh((N,) * 3, n, inputs.uniform_leaves(nrb))
+        mesh.upload(inputs.scatter_global(fields, mesh.leaves(), n))
+        mesh.step(warmup)
+        mesh.sync()
+        mesh.kernel_timing(Mesh.KT_PREDICTOR | Mesh.KT_CORRECTOR)
+        torch.cuda.synchronize()
+        ev0.record(mesh.stream)
+        mesh.step(cycles)
+        ev1.record(mesh.stream)
+        ev1.synchronize()
+        kt = mesh.kernel_times()
+        ms = ev0.elapsed_time(ev1) / cycles
+        out[f"block_{blk}"] = {"blocks": len(mesh.leaves()), "tile_rows": mesh.tuning()["tile_rows"],
+                               "ms_per_cycle": round(ms, 4), "zone_cycles_per_s": N ** 3 / (ms / 1e3),
+                               "predictor_ms": round(kt["predictor"][0] / kt["predictor"][1], 4),
+                               "corrector_ms": round(kt["corrector"][0] / kt["corrector"][1], 4)}
+        mesh.close()
+        torch.cuda.empty_cache()
     return out
 
 
@@ -477,14 +559,19 @@ def main_leg(args):
     corr_ms = avg["corrector"]
     roof = None
     if corr_ms:
-        ach = b_corr * cells / (corr_ms / 1e3) / 1e9
+        b_floor = stage_floor_bytes()[0]
+        ach = b_floor * cells / (corr_ms / 1e3) / 1e9
+        ach_halo = b_corr * cells / (corr_ms / 1e3) / 1e9
         sha = stage_source_sha()
         roof = {"bound": "hbm", "kernel": "stage_kernel<PLM> (corrector)",
                 "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": traffic_from_profile(sha),
-                "algorithmic_bytes_per_launch": int(b_corr * cells),
-                "avg_launch_ms": round(corr_ms, 4)}
+                "algorithmic_bytes_per_zone": b_floor,
+                "algorithmic_bytes_per_launch": int(b_floor * cells),
+                "avg_launch_ms": round(corr_ms, 4),
+                "halo_model": {"bytes_per_zone": round(b_corr, 3), "achieved": round(ach_halo, 1),
+                               "frac": round(ach_halo / HBM_PEAK_GBS, 4)}}
         # the second ceiling: FP64 VALU issue (one wave64 instruction holds a
         # SIMD for 4 cycles) for the instructions the counters saw per launch
         vr = valu_from_profile(sha)
@@ -518,6 +605,7 @@ def main_leg(args):
                    "cells": cells, "block": blk, "blocks": len(lv), "graph": bool(args.graph),
                    "tile_rows": mesh.tuning()["tile_rows"]},
         "hbm_frac_cycle": round(zc * b_cycle / (HBM_PEAK_GBS * 1e9), 4),
+        "hbm_frac_cycle_at_stage_floor": round(zc * stage_floor_bytes()[1] / (HBM_PEAK_GBS * 1e9), 4),
         "bytes_per_zone_cycle": round(b_cycle, 2),
         "flops_per_zone_cycle": sum(ALG_FLOPS.values()),
         "fp64_tflops_cycle": round(zc * sum(ALG_FLOPS.values()) / 1e12, 3),
@@ -545,6 +633,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--no-kh", action="store_true")
+    ap.add_argument("--no-block-sweep", action="store_true",
+                    help="skip the 256^3 cycle in blocks of 16^3 and 64^3 beside 32^3")
     ap.add_argument("--fp32-storage", action="store_true",
                     help="also run the 256^3 cycle with the state stored in FP32")
     ap.add_argument("--remote-split", action="store_true",
@@ -582,12 +672,19 @@ def main():
                "config": {"workload": "main 256^3 leg skipped"}, "roofline": None}
     else:
         out = main_leg(args)
-    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None, "packs_sweep": None, "kh_amr": None,
-                "deep_amr": None})
+    out.update({"adjoint_forward_ratio": None, "adjoint": None, "batch": None, "amr": None, "packs_sweep": None,
+                "kh_amr": None, "deep_amr": None, "block_sweep": None})
     if not args.no_adjoint:
         adj = adjoint_ratio()
         out["adjoint"] = adj
-        out["adjoint_forward_ratio"] = adj["reverse_sweep_over_forward"]
+        # both readings of the cost ratio against plain forward cycles: the
+        # reverse sweep of a cycle with its intermediates at hand, and the
+        # whole gradient with the checkpoint recomputation
+        out["adjoint_forward_ratio"] = {"reverse_sweep": adj["reverse_sweep_over_forward"],
+                                        "gradient_with_recompute": adj["gradient_over_forward"]}
+    if not args.no_block_sweep:
+        torch.cuda.empty_cache()
+        out["block_sweep"] = block_sweep_leg()
     if not args.no_amr:
         out["amr"] = amr_leg()
     if not args.no_batch:

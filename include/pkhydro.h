@@ -236,22 +236,34 @@ int pkh_conserved_totals(pkh_mesh *mesh, double out[5]);
 int pkh_conserved_totals_noalloc(pkh_mesh *mesh, double out[5]);
 
 /* ---- Reverse mode (gradient of a final-state loss w.r.t. the initial
-   state), single-level meshes. A tape records the timestep of every cycle
-   and the state every `ckpt_every` cycles; the adjoint recomputes each
-   segment forward from its checkpoint, keeping the ghost-filled inputs of
-   both stages, and sweeps it in reverse: per cycle the transposes of the
-   ghost fill, the corrector, the ghost fill and the predictor, with the
-   timestep frozen at its recorded value and limiter / wave-speed branches
-   frozen at those the forward pass takes. ---- */
+   state). A tape records the timestep of every cycle and the state every
+   `ckpt_every` cycles; the adjoint recomputes each segment forward from its
+   checkpoint, keeping the ghost-filled inputs of both stages, and sweeps it
+   in reverse: per cycle the transposes of the ghost fill, the corrector,
+   the ghost fill and the predictor, with the timestep frozen at its
+   recorded value and limiter / wave-speed / prolongation-slope branches
+   frozen at those the forward pass takes. On meshes with level jumps the
+   transposes include the fine-coarse flux correction (each fine sub-face
+   flux also carries a quarter of the coarse cell's adjoint), restriction
+   (1/8 of a ghost adjoint to each fine cell) and prolongation (the linear
+   map with the forward's minmod cases); at walls the image rule. ---- */
 typedef struct pkh_tape pkh_tape;
 
 /* Tape for the mesh; ckpt_every >= 1. Device memory: one active-state copy
    per checkpoint (allocated as cycles are recorded) plus 2*ckpt_every + 1
-   ghost-filled states for recomputation and 2 for the reverse sweep.
-   PKH_EINVAL on multilevel meshes. While the tape exists the mesh refuses
-   pkh_regrid and pkh_set_partition (PKH_ESTATE). */
+   ghost-filled states for recomputation and 1 or 2 for the reverse sweep.
+   Single-level periodic meshes with 8 to 64 cells per block row use the
+   pencil/row reverse kernels; meshes with level jumps or walls the
+   face-wise reverse. PKH_EINVAL for FP32-stored or partitioned meshes.
+   While the tape exists the mesh refuses pkh_regrid and pkh_set_partition
+   (PKH_ESTATE). */
 int pkh_tape_create(pkh_mesh *mesh, int32_t ckpt_every, pkh_tape **out);
 int pkh_tape_destroy(pkh_tape *tape);
+/* Use (on = 1) the face-wise reverse on a mesh that does not need it (a
+   cross-check of the two), or return (on = 0) to the pencil/row kernels;
+   PKH_EINVAL for on = 0 on a mesh with level jumps or walls. The gradient
+   does not depend on it beyond rounding. Synchronises. */
+int pkh_tape_set_facewise(pkh_tape *tape, int32_t on);
 
 /* Advance n_cycles exactly like pkh_step (no t_end clamp) while recording
    into the tape. A second call discards the previous recording. */
@@ -268,28 +280,6 @@ int pkh_tape_replay(pkh_mesh *mesh, pkh_tape *tape);
    layout; may alias lam_final). The mesh's own state is not touched.
    Enqueued on the mesh's stream; synchronises at the end. */
 int pkh_adjoint(pkh_mesh *mesh, pkh_tape *tape, const double *lam_final, double *grad_init);
-
-/* ---- Batches: many independent single-level meshes advanced together
-   (each keeps its own t and dt). The meshes must share one HIP stream. ---- */
-typedef struct pkh_batch pkh_batch;
-enum {
-  PKH_PLAIN = 0, /* per mesh and cycle: the mesh's own launches (pkh_step) */
-  PKH_FUSED = 1, /* per cycle: one grouped launch per stage and tile shape over
-                    every mesh's tiles, one clock launch for all meshes */
-  PKH_GRAPH = 2  /* PKH_FUSED with segments of up to 50 cycles replayed from a
-                    captured hipGraph */
-};
-/* The results of the three modes are bitwise identical. While the batch
-   exists its meshes refuse pkh_regrid and pkh_set_partition (PKH_ESTATE). */
-int pkh_batch_create(pkh_mesh *const *meshes, int32_t n, pkh_batch **out);
-int pkh_batch_destroy(pkh_batch *batch);
-int pkh_batch_step(pkh_batch *batch, int32_t n_cycles, uint32_t mode);
-/* Autotune: for each group of meshes with the same block width, time every
-   compiled tile-rows choice over `trial_cycles` fused cycles (the meshes'
-   states and clocks are saved and restored around the trials) and keep the
-   fastest; writes the chosen tile rows per mesh into tile_rows[n] if not
-   NULL. Synchronises. */
-int pkh_batch_autotune(pkh_batch *batch, int32_t trial_cycles, int32_t *tile_rows);
 
 /* Virtual partition for the multi-GPU data path on one GPU (Sec. 3.7: the
    communication buffers of faces whose neighbour lives on another rank).
@@ -333,6 +323,62 @@ int pkh_get_tuning(const pkh_mesh *mesh, pkh_tuning *tuning);
 /* Autotune one mesh the same way (states saved and restored); writes the
    chosen tuning to *out if not NULL. */
 int pkh_autotune(pkh_mesh *mesh, int32_t trial_cycles, pkh_tuning *out);
+
+/* ---- Batches: many independent meshes advanced together, each with its
+   own t and dt (the paper's concern with launch overhead for many small
+   blocks, Sec. 5.1, and MeshBlockPacks, Sec. 3.6). Members may be
+   multilevel and may have walls; they must share one HIP stream, be stored
+   in FP64 and be unpartitioned. ---- */
+typedef struct pkh_batch pkh_batch;
+enum {
+  PKH_PLAIN = 0,     /* per mesh and cycle: the mesh's own launches (pkh_step) */
+  PKH_FUSED = 1,     /* per cycle: one grouped launch per stage and tile shape over
+                        every mesh's tiles, each multilevel mesh's flux correction
+                        and level-jump face fill, one clock launch for all meshes */
+  PKH_GRAPH = 2,     /* PKH_FUSED with segments of up to 50 cycles replayed from a
+                        captured hipGraph */
+  PKH_PERSISTENT = 3 /* one persistent launch per segment of up to 50 cycles:
+                        resident workgroups take (cycle, phase, mesh, tile or
+                        chunk) items from a ticket counter in order; an item
+                        waits (bounded) only for the previous phase of its own
+                        mesh, so meshes overlap and the launch cannot deadlock;
+                        the last item of a mesh's cycle advances its clock.
+                        Needs blocks of 16 or 32 cells per row (tiles of 16 or
+                        8 rows, 256-thread workgroups); PKH_EINVAL otherwise */
+};
+/* Create a batch over n distinct meshes. tuning (may be NULL): tile_rows
+   for the grouped launches of every member (0: each mesh's own), packs
+   ignored. The results of the four modes are bitwise identical. While the
+   batch exists its meshes refuse pkh_regrid and pkh_set_partition
+   (PKH_ESTATE). */
+int pkh_batch_create(pkh_mesh *const *meshes, int32_t n, const pkh_tuning *tuning, pkh_batch **out);
+int pkh_batch_destroy(pkh_batch *batch);
+/* n_cycles cycles of every member in the given mode; no host
+   synchronisation. A persistent launch whose bounded wait gave up (a wait
+   longer than wait_limit_s) latches an error that the members' next
+   synchronising call reports as PKH_ESTATE; the launch still drains and
+   ends. */
+int pkh_batch_step(pkh_batch *batch, int32_t n_cycles, uint32_t mode);
+/* Launch knobs of the persistent mode: waves_per_simd 2 or 3 (0: 2), the
+   kernel variant compiled for that occupancy; wait_limit_s the bound of
+   every wait inside the persistent kernel, in seconds of the device wall
+   clock (default 2; 0 gives up on any wait not met at once). No numerical
+   effect. */
+typedef struct {
+  int32_t waves_per_simd;
+  int32_t reserved;
+  double wait_limit_s;
+} pkh_batch_tuning;
+int pkh_batch_set_tuning(pkh_batch *batch, const pkh_batch_tuning *tuning);
+int pkh_batch_get_tuning(const pkh_batch *batch, pkh_batch_tuning *tuning);
+/* Autotune: for each group of meshes with the same block width, time every
+   compiled tile-rows choice over `trial_cycles` fused cycles, then (when the
+   persistent mode is available) each waves-per-SIMD variant of the
+   persistent kernel, and keep the fastest; the meshes' states and clocks
+   are saved and restored around the trials. Writes the chosen tile rows
+   per mesh into tile_rows[n] if not NULL; the chosen persistent variant is
+   read with pkh_batch_get_tuning. Synchronises. */
+int pkh_batch_autotune(pkh_batch *batch, int32_t trial_cycles, int32_t *tile_rows);
 
 /* Kernel timing with HIP events on the handle's stream (a measurement aid
    for the roofline report). `kinds` is a mask of PKH_KT_* bits; while it is

@@ -1,7 +1,9 @@
 """Build the oracle's shared library (TEST INFRASTRUCTURE).
 
 The parity build uses ``-O2 -ffp-contract=off`` so that no fused multiply-add
-changes the rounding of the plain definition.
+changes the rounding of the plain definition. The timing build (the CPU
+baseline the GPU path is reported beside) is the same source compiled
+``-O3 -march=native -fopenmp`` for the host it runs on.
 """
 import os
 import subprocess
@@ -20,6 +22,17 @@ def build(force=True):
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_timing(out_path):
+    """The timing build at out_path, tuned for this host's CPU (so it is
+    compiled where it runs)."""
+    tmp = out_path + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wno-unused-function", SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out_path)
+    return out_path
 
 
 if __name__ == "__main__":

@@ -24,36 +24,56 @@ def lib():
         path = _build.LIB
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
             _build.build()
-        L = C.CDLL(path)
-        L.orc_create.argtypes = [_I32, _I32, C.c_int32, _D, _D, C.c_double, C.c_double,
-                                 C.c_int32, _I32, _I32, C.c_int64, C.POINTER(C.c_void_p)]
-        L.orc_create.restype = C.c_int
-        L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_nleaves.argtypes = [C.c_void_p]
-        L.orc_nleaves.restype = C.c_int64
-        L.orc_leaves.argtypes = [C.c_void_p, _I32]
-        L.orc_set_state.argtypes = [C.c_void_p, _D]
-        L.orc_set_fp32.argtypes = [C.c_void_p, C.c_int32]
-        L.orc_get_state.argtypes = [C.c_void_p, _D]
-        L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_int64]
-        L.orc_error.argtypes = [C.c_void_p]
-        L.orc_padded.argtypes = [C.c_void_p, C.c_int64, _D]
-        L.orc_dt.argtypes = [C.c_void_p]
-        L.orc_dt.restype = C.c_double
-        L.orc_stage_inplace.argtypes = [C.c_void_p, C.c_int32, C.c_double]
-        L.orc_step.argtypes = [C.c_void_p, C.c_int32, C.c_double]
-        L.orc_time.argtypes = [C.c_void_p, _D, _D, C.POINTER(C.c_int64)]
-        L.orc_totals.argtypes = [C.c_void_p, _D, _D]
-        L.orc_regrid.argtypes = [C.c_void_p, C.POINTER(C.c_int8), C.c_int64]
-        L.orc_mc.argtypes = [C.c_double, C.c_double]
-        L.orc_mc.restype = C.c_double
-        L.orc_minmod.argtypes = [C.c_double, C.c_double]
-        L.orc_minmod.restype = C.c_double
-        L.orc_hlle.argtypes = [_D, _D, C.c_int, C.c_double, _D]
-        L.orc_prim.argtypes = [_D, C.c_double, _D]
-        L.orc_threads.restype = C.c_int
-        _lib = L
+        _lib = load(path)
     return _lib
+
+
+def use(path):
+    """Make the oracle build at `path` the one every OracleMesh of this
+    process uses (the timing build; call before any other use)."""
+    global _lib
+    _lib = load(path)
+    return _lib
+
+
+def load(path):
+    """Load a build of the oracle and declare its entry points."""
+    L = C.CDLL(path)
+    L.orc_create.argtypes = [_I32, _I32, C.c_int32, _D, _D, C.c_double, C.c_double,
+                             C.c_int32, _I32, _I32, C.c_int64, C.POINTER(C.c_void_p)]
+    L.orc_create.restype = C.c_int
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_nleaves.argtypes = [C.c_void_p]
+    L.orc_nleaves.restype = C.c_int64
+    L.orc_leaves.argtypes = [C.c_void_p, _I32]
+    L.orc_set_state.argtypes = [C.c_void_p, _D]
+    L.orc_set_fp32.argtypes = [C.c_void_p, C.c_int32]
+    L.orc_get_state.argtypes = [C.c_void_p, _D]
+    L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+    L.orc_error.argtypes = [C.c_void_p]
+    L.orc_padded.argtypes = [C.c_void_p, C.c_int64, _D]
+    L.orc_dt.argtypes = [C.c_void_p]
+    L.orc_dt.restype = C.c_double
+    L.orc_stage_inplace.argtypes = [C.c_void_p, C.c_int32, C.c_double]
+    L.orc_step.argtypes = [C.c_void_p, C.c_int32, C.c_double]
+    L.orc_time.argtypes = [C.c_void_p, _D, _D, C.POINTER(C.c_int64)]
+    L.orc_totals.argtypes = [C.c_void_p, _D, _D]
+    L.orc_regrid.argtypes = [C.c_void_p, C.POINTER(C.c_int8), C.c_int64]
+    L.orc_mc.argtypes = [C.c_double, C.c_double]
+    L.orc_mc.restype = C.c_double
+    L.orc_minmod.argtypes = [C.c_double, C.c_double]
+    L.orc_minmod.restype = C.c_double
+    L.orc_hlle.argtypes = [_D, _D, C.c_int, C.c_double, _D]
+    L.orc_prim.argtypes = [_D, C.c_double, _D]
+    L.orc_threads.restype = C.c_int
+    L.orc_step_dts.argtypes = [C.c_void_p, C.c_int32, _D]
+    L.orc_track_branches.argtypes = [C.c_void_p, C.c_int32]
+    L.orc_branch_signature.argtypes = [C.c_void_p]
+    L.orc_branch_signature.restype = C.c_uint64
+    L.orc_mc_code.argtypes = [C.c_double, C.c_double]
+    L.orc_minmod_code.argtypes = [C.c_double, C.c_double]
+    L.orc_hlle_code.argtypes = [_D, _D, C.c_int, C.c_double]
+    return L
 
 
 def _dp(a):
@@ -184,6 +204,23 @@ class OracleMesh:
         rc = lib().orc_step(self._h, int(ncycles), float(t_end))
         if rc != 0:
             raise OracleError(f"orc_step failed with {rc}")
+
+    def step_dts(self, dts):
+        """Cycles with the given timesteps (one per cycle) instead of the CFL
+        timestep: the map a frozen-timestep reverse mode differentiates."""
+        d = np.ascontiguousarray(np.asarray(dts, dtype=np.float64))
+        rc = lib().orc_step_dts(self._h, len(d), _dp(d))
+        if rc != 0:
+            raise OracleError(f"orc_step_dts failed with {rc}")
+
+    def track_branches(self, on=True):
+        """Start (signature reset) or stop recording the branch signature."""
+        lib().orc_track_branches(self._h, 1 if on else 0)
+
+    def branch_signature(self):
+        """Order-free hash of every limiter, wave-speed and prolongation-slope
+        branch taken by the stages since track_branches(True)."""
+        return int(lib().orc_branch_signature(self._h))
 
     def time(self):
         t = C.c_double()

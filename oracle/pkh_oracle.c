@@ -69,6 +69,14 @@ typedef struct {
   double t, dt_last;
   int64_t cycle;
   int err;
+  /* branch signature (for finite-difference checks of the reverse mode):
+     while track is set, every branch the cycle takes -- each MC limiter
+     case, each HLLE wave-speed choice, each minmod case of a prolongation
+     slope -- is hashed with its position and summed into sig (an
+     order-free sum, so the OpenMP schedule cannot change it) */
+  int track;
+  uint64_t sig;
+  int64_t stage_no;
 } orc_mesh;
 
 /* ------------------------------------------------------------------ */
@@ -105,6 +113,41 @@ double orc_minmod(double a, double b) {
   return a > 0.0 ? m : -m;
 }
 
+/* Which case of orc_mc / orc_minmod a pair of differences takes (the same
+   comparisons in the same order): MC 0 extremum, 1 2|dl|, 2 2|dr|,
+   3 |dl+dr|/2; minmod 0 extremum, 1 a, 2 b. */
+int orc_mc_code(double dl, double dr) {
+  if (dl * dr <= 0.0) return 0;
+  double a = 2.0 * fabs(dl), b = 2.0 * fabs(dr), c = 0.5 * fabs(dl + dr);
+  double m = a;
+  int k = 1;
+  if (b < m) { m = b; k = 2; }
+  if (c < m) k = 3;
+  return k;
+}
+
+int orc_minmod_code(double a, double b) {
+  if (a * b <= 0.0) return 0;
+  return fabs(a) < fabs(b) ? 1 : 2;
+}
+
+static uint64_t mix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+/* Per-thread part of the branch signature of the stage being evaluated. */
+static uint64_t tl_sig;
+#pragma omp threadprivate(tl_sig)
+
+static void track_branch(const orc_mesh *m, uint64_t key, uint64_t word) {
+  if (m->track) tl_sig += mix64(mix64(key) ^ (word * 0xD6E8FEB86659FD93ull + 1));
+}
+
+static void hlle_impl(const double *wl, const double *wr, int d, double gamma, double *f, int *code);
+
 /* HLLE flux across a face normal to direction d (0=x, 1=y, 2=z) from the
    primitive left/right states. Wave-speed bounds after Einfeldt (1988):
    b+ = max(u_roe + a_roe, u_R + c_R, 0), b- = min(u_roe - a_roe, u_L - c_L, 0),
@@ -112,6 +155,19 @@ double orc_minmod(double a, double b) {
    b+ b- (U_R - U_L)) / (b+ - b-). Output is the conserved-variable flux in
    (rho, Mx, My, Mz, E) order. */
 void orc_hlle(const double *wl, const double *wr, int d, double gamma, double *f) {
+  hlle_impl(wl, wr, d, gamma, f, NULL);
+}
+
+/* Which wave-speed bounds orc_hlle takes: 3 * (b- case) + (b+ case), with
+   case 0 the Roe estimate, 1 the outer side's signal speed, 2 zero. */
+int orc_hlle_code(const double *wl, const double *wr, int d, double gamma) {
+  double f[5];
+  int code = 0;
+  hlle_impl(wl, wr, d, gamma, f, &code);
+  return code;
+}
+
+static void hlle_impl(const double *wl, const double *wr, int d, double gamma, double *f, int *code) {
   double gm1 = gamma - 1.0;
   double rl = wl[0], pl = wl[4], rr = wr[0], pr = wr[4];
   double ul = wl[1 + d], ur = wr[1 + d];
@@ -129,11 +185,13 @@ void orc_hlle(const double *wl, const double *wr, int d, double gamma, double *f
   double vb2 = vb[0] * vb[0] + vb[1] * vb[1] + vb[2] * vb[2];
   double ab = sqrt(gm1 * (hb - 0.5 * vb2));
   double bp = vb[d] + ab;
-  if (ur + cr > bp) bp = ur + cr;
-  if (0.0 > bp) bp = 0.0;
+  int kp = 0, km = 0;
+  if (ur + cr > bp) { bp = ur + cr; kp = 1; }
+  if (0.0 > bp) { bp = 0.0; kp = 2; }
   double bm = vb[d] - ab;
-  if (ul - cl < bm) bm = ul - cl;
-  if (0.0 < bm) bm = 0.0;
+  if (ul - cl < bm) { bm = ul - cl; km = 1; }
+  if (0.0 < bm) { bm = 0.0; km = 2; }
+  if (code) *code = 3 * km + kp;
 
   double fl[5], fr[5], uL[5], uR[5];
   uL[0] = rl; uR[0] = rr;
@@ -293,12 +351,21 @@ static double ghost_inside(orc_mesh *m, const double *U, int L, const int64_t J[
     int64_t I[3] = {J[0] >> 1, J[1] >> 1, J[2] >> 1};
     double c0 = comp(m, U, L - 1, I, v);
     double ss[3];
+    uint64_t word = 0;
     for (int d = 0; d < 3; ++d) {
       int64_t Im[3] = {I[0], I[1], I[2]}, Ip[3] = {I[0], I[1], I[2]};
       Im[d] -= 1;
       Ip[d] += 1;
-      double s = orc_minmod(c0 - comp(m, U, L - 1, Im, v), comp(m, U, L - 1, Ip, v) - c0);
+      double da = c0 - comp(m, U, L - 1, Im, v), db = comp(m, U, L - 1, Ip, v) - c0;
+      double s = orc_minmod(da, db);
+      word = 4 * word + (uint64_t)orc_minmod_code(da, db);
       ss[d] = (J[d] & 1) ? s : -s;
+    }
+    if (m->track) {
+      uint64_t key = ((((uint64_t)m->stage_no * 16 + (uint64_t)L) * 8 + (uint64_t)v) << 40) ^
+                     (((uint64_t)J[2] & 0x3FFF) << 28) ^ (((uint64_t)J[1] & 0x3FFF) << 14) ^
+                     ((uint64_t)J[0] & 0x3FFF);
+      track_branch(m, key ^ 0x5555000000000000ull, word);
     }
     return c0 + 0.25 * ((ss[0] + ss[1]) + ss[2]);
   }
@@ -361,7 +428,7 @@ static int64_t fidx(const orc_mesh *m, int d, int v, int64_t i, int64_t j, int64
 }
 
 /* Face fluxes of one leaf along d from its padded primitives Wp. */
-static void leaf_fluxes(const orc_mesh *m, const double *Wp, int recon, int d, double *F) {
+static void leaf_fluxes(const orc_mesh *m, int64_t blk, const double *Wp, int recon, int d, double *F) {
   const int n1 = m->n[0], n2 = m->n[1], n3 = m->n[2];
   const int64_t p1 = n1 + 2 * NG, p2 = n2 + 2 * NG, p3 = n3 + 2 * NG;
   const int64_t cstride = p1 * p2 * p3;
@@ -373,6 +440,7 @@ static void leaf_fluxes(const orc_mesh *m, const double *Wp, int recon, int d, d
         /* cell "i" of the face is the upper neighbour; "i-1" the lower */
         int64_t c = ((int64_t)(k + NG) * p2 + (j + NG)) * p1 + (i + NG);
         double wl[5], wr[5], f[5];
+        uint64_t word = 0;
         for (int v = 0; v < NV; ++v) {
           const double *q = Wp + v * cstride;
           double qm2 = q[c - 2 * step], qm1 = q[c - step], q0 = q[c], qp1 = q[c + step];
@@ -382,9 +450,25 @@ static void leaf_fluxes(const orc_mesh *m, const double *Wp, int recon, int d, d
           } else {
             wl[v] = qm1 + 0.5 * orc_mc(qm1 - qm2, q0 - qm1);
             wr[v] = q0 - 0.5 * orc_mc(q0 - qm1, qp1 - q0);
+            if (m->track) word = 16 * word + 4 * (uint64_t)orc_mc_code(qm1 - qm2, q0 - qm1) +
+                                 (uint64_t)orc_mc_code(q0 - qm1, qp1 - q0);
           }
         }
-        orc_hlle(wl, wr, d, m->gamma, f);
+        int hc = 0;
+        hlle_impl(wl, wr, d, m->gamma, f, &hc);
+        if (m->track) {
+          /* with identical face states (outflow walls copy the cell beside
+             them) both wave-speed bounds of a pair coincide in exact
+             arithmetic and the flux is F(U) whatever they are: its
+             derivative does not depend on the bound taken, so such a face
+             records no wave-speed case */
+          int same = 1;
+          for (int v = 0; v < NV; ++v) same &= wl[v] == wr[v];
+          if (same) hc = 15;
+          uint64_t key = (((((uint64_t)m->stage_no * 4 + (uint64_t)d) << 24) ^ (uint64_t)blk) << 32) ^
+                         (((uint64_t)k & 0x7FF) << 22) ^ (((uint64_t)j & 0x7FF) << 11) ^ ((uint64_t)i & 0x7FF);
+          track_branch(m, key, 16 * word + (uint64_t)hc);
+        }
         for (int v = 0; v < NV; ++v) F[fidx(m, d, v, i, j, k)] = f[v];
       }
 }
@@ -451,8 +535,10 @@ static int stage(orc_mesh *m, const double *Uin, const double *Ubase, double *Uo
     if (!F[q]) return ORC_ENOMEM;
   }
   int bad = 0;
+  m->stage_no += 1;
 #pragma omp parallel
   {
+    tl_sig = 0;
     double *P = (double *)malloc(sizeof(double) * (size_t)psz);
     double *W = (double *)malloc(sizeof(double) * (size_t)psz);
     int64_t cs = psz / NV;
@@ -469,10 +555,14 @@ static int stage(orc_mesh *m, const double *Uin, const double *Ubase, double *Uo
         }
         for (int v = 0; v < NV; ++v) W[v * cs + c] = w[v];
       }
-      for (int d = 0; d < 3; ++d) leaf_fluxes(m, W, recon, d, F[b * 3 + d]);
+      for (int d = 0; d < 3; ++d) leaf_fluxes(m, b, W, recon, d, F[b * 3 + d]);
     }
     free(P);
     free(W);
+    if (m->track) {
+#pragma omp atomic
+      m->sig += tl_sig;
+    }
   }
   flux_correct(m, F);
 #pragma omp parallel for schedule(static)
@@ -748,6 +838,39 @@ int orc_step(void *h, int32_t ncycles, double t_end) {
   free(Us);
   return rc;
 }
+
+/* n full cycles with the given timesteps dts[0..n) instead of the CFL
+   timestep (the map a reverse mode with frozen timesteps differentiates). */
+int orc_step_dts(void *h, int32_t ncycles, const double *dts) {
+  orc_mesh *m = (orc_mesh *)h;
+  size_t sz = (size_t)(m->nl * NV * ncell(m));
+  double *Us = (double *)malloc(sizeof(double) * sz);
+  if (!Us) return ORC_ENOMEM;
+  int rc = ORC_OK;
+  for (int c = 0; c < ncycles; ++c) {
+    double dt = dts[c];
+    rc = stage(m, m->U, m->U, Us, m->recon1, 0.5 * dt);
+    if (rc) break;
+    rc = stage(m, Us, m->U, m->U, 1, dt);
+    if (rc) break;
+    m->t += dt;
+    m->dt_last = dt;
+    m->cycle += 1;
+  }
+  free(Us);
+  return rc;
+}
+
+/* Start (on = 1, signature reset to 0) or stop recording the branch
+   signature of the stages that follow. */
+void orc_track_branches(void *h, int32_t on) {
+  orc_mesh *m = (orc_mesh *)h;
+  m->track = on ? 1 : 0;
+  m->sig = 0;
+  m->stage_no = 0;
+}
+
+uint64_t orc_branch_signature(void *h) { return ((orc_mesh *)h)->sig; }
 
 void orc_time(void *h, double *t, double *dt_last, int64_t *cycle) {
   orc_mesh *m = (orc_mesh *)h;

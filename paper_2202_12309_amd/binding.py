@@ -40,6 +40,10 @@ class Tuning(C.Structure):
     _fields_ = [("tile_rows", C.c_int32), ("packs", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
+class BatchTuning(C.Structure):
+    _fields_ = [("waves_per_simd", C.c_int32), ("reserved", C.c_int32), ("wait_limit_s", C.c_double)]
+
+
 class Loc(C.Structure):
     _fields_ = [("level", C.c_int32), ("lx1", C.c_int32), ("lx2", C.c_int32), ("lx3", C.c_int32)]
 
@@ -81,10 +85,13 @@ _SIGS = {
     "pkh_last_error": (C.c_char_p, []),
     "pkh_tape_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "pkh_tape_destroy": (C.c_int, [C.c_void_p]),
+    "pkh_tape_set_facewise": (C.c_int, [C.c_void_p, C.c_int32]),
     "pkh_forward_taped": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
     "pkh_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pkh_tape_replay": (C.c_int, [C.c_void_p, C.c_void_p]),
-    "pkh_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "pkh_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pkh_batch_set_tuning": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pkh_batch_get_tuning": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pkh_batch_destroy": (C.c_int, [C.c_void_p]),
     "pkh_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32]),
     "pkh_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
@@ -368,7 +375,7 @@ class Mesh:
 
 
 class Tape:
-    """Recording of taped cycles for the reverse mode (single-level meshes)."""
+    """Recording of taped cycles for the reverse mode."""
 
     def __init__(self, mesh, ckpt_every):
         self.mesh = mesh
@@ -382,6 +389,10 @@ class Tape:
     def replay(self):
         """Advance the mesh's current state with the recorded timesteps."""
         _check(lib().pkh_tape_replay(self.mesh._h, self._h))
+
+    def set_facewise(self, on=True):
+        """Use the face-wise reverse (needed with level jumps or walls)."""
+        _check(lib().pkh_tape_set_facewise(self._h, 1 if on else 0))
 
     def adjoint(self, lam_final):
         """lam_final: float64 CUDA tensor in the upload layout; returns dL/dU0."""
@@ -443,20 +454,24 @@ def euler_vl2(U0, mesh, n_cycles, ckpt_every=10):
     return _EULER_FN.apply(U0, mesh, int(n_cycles), int(ckpt_every))
 
 
-BATCH_MODES = {"plain": 0, "fused": 1, "graph": 2}
+BATCH_MODES = {"plain": 0, "fused": 1, "graph": 2, "persistent": 3}
 
 
 class Batch:
-    """Independent single-level meshes advanced together (they must share a
-    stream). Modes: 'plain' (each mesh's own launches), 'fused' (grouped
-    launches over every mesh's tiles), 'graph' (fused, replayed from captured
-    50-cycle hipGraphs); bitwise identical results."""
+    """Independent meshes advanced together (they must share a stream; they
+    may be multilevel). Modes: 'plain' (each mesh's own launches), 'fused'
+    (grouped launches over every mesh's tiles), 'graph' (fused, replayed
+    from captured 50-cycle hipGraphs), 'persistent' (one persistent launch
+    per segment of up to 50 cycles); bitwise identical results. tile_rows:
+    tile rows of the grouped launches for every member (0: each mesh's own)."""
 
-    def __init__(self, meshes):
+    def __init__(self, meshes, tile_rows=0):
         self.meshes = list(meshes)
         arr = (C.c_void_p * len(self.meshes))(*[m._h.value for m in self.meshes])
         h = C.c_void_p()
-        _check(lib().pkh_batch_create(arr, len(self.meshes), C.byref(h)))
+        tun = Tuning()
+        tun.tile_rows = int(tile_rows)
+        _check(lib().pkh_batch_create(arr, len(self.meshes), C.byref(tun), C.byref(h)))
         self._h = h
 
     def step(self, n_cycles, mode="fused"):
@@ -466,6 +481,19 @@ class Batch:
         out = (C.c_int32 * len(self.meshes))()
         _check(lib().pkh_batch_autotune(self._h, int(trial_cycles), out))
         return list(out)
+
+    def set_tuning(self, waves_per_simd=0, wait_limit_s=2.0):
+        """Persistent-mode knobs: kernel variant (2 or 3 waves per SIMD) and
+        the bound of its waits in seconds."""
+        t = BatchTuning()
+        t.waves_per_simd = int(waves_per_simd)
+        t.wait_limit_s = float(wait_limit_s)
+        _check(lib().pkh_batch_set_tuning(self._h, C.byref(t)))
+
+    def tuning(self):
+        t = BatchTuning()
+        _check(lib().pkh_batch_get_tuning(self._h, C.byref(t)))
+        return {"waves_per_simd": t.waves_per_simd, "wait_limit_s": t.wait_limit_s}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

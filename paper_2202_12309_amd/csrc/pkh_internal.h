@@ -118,6 +118,55 @@ struct GroupItem {
 // width n1 and tile rows tj; insts/items are device arrays.
 hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
                               const GroupItem* items, int nitems, hipStream_t s);
+// ---- Persistent batch launch: one kernel advances many independent
+// meshes by several cycles; workgroups take items from a ticket counter in
+// order (cycle, phase, instance) and wait only for items with smaller
+// tickets, so the launch cannot deadlock whatever its grid. ----
+// Phases of a cycle: 0 predictor tiles, 1 flux correction of U*, 2 ghost
+// faces of U* across level jumps and walls, 3 corrector tiles, 4 flux
+// correction of U^{n+1}, 5 ghost faces of U^{n+1}; then the instance's clock.
+constexpr int PPHASES = 6;
+struct PInst {
+  StageLaunch st[2];       // predictor, corrector
+  const FineFace* ff;      // flux-correction records (multilevel)
+  const int32_t* ff_first;
+  const int32_t* cblocks;
+  const int32_t* jf;       // ghost face records
+  LevelMaps maps;
+  int32_t cnt[PPHASES];    // items of each phase in one cycle
+  int32_t last;            // last phase with items (its end closes the cycle)
+  int32_t n1;              // block width: 16 (16-row tiles) or 32 (8-row tiles)
+};
+// Monotonic per-instance progress within one launch: items done per phase
+// (all cycles so far) and cycles whose clock has been advanced.
+struct PSync {
+  unsigned int done[PPHASES];
+  unsigned int clock;
+  unsigned int pad;
+};
+// One work item: phases 0 and 3 a tile (a = leaf, b = first row); 1 and 4
+// a 256-cell chunk a of coarse block b of the flux-correction list; 2 and 5
+// a 256-cell chunk a of ghost face record b.
+struct PItem {
+  int32_t inst, phase, a, b;
+};
+struct PCtl {
+  unsigned int ticket;  // next item ticket
+  int err;              // set when a bounded wait gave up
+  int pad[2];
+};
+// Rows per tile of the persistent launch (256-thread workgroups).
+constexpr int persistent_tile_rows(int n1) { return n1 == 32 ? 8 : (n1 == 16 ? 16 : -1); }
+// Resident 256-thread workgroups of the persistent kernel with `waves`
+// waves per SIMD (2 or 3), or -1.
+int persistent_grid(int waves);
+// Reset the progress counters and run `ncycles` cycles of every instance;
+// a wait longer than wait_ticks of the device wall clock gives up, latches
+// ctl->err and error bit 4 of every instance's clock, and the launch drains.
+hipError_t launch_persistent(const PInst* insts, int32_t ninst, PSync* sync, const PItem* items, int32_t nper,
+                             int32_t ncycles, PCtl* ctl, int waves, int grid, long long wait_ticks,
+                             hipStream_t s);
+
 // Ghost face regions of the (leaf, face) pairs jf[2 njf] (faces whose
 // neighbour is on another level).
 hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
@@ -175,6 +224,17 @@ hipError_t launch_adj_stage(int recon, const double* U, const double* lam, doubl
                             const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                             const int32_t* nbr, const double* dtp, double beta, double* out,
                             const double* add0, const double* add1, hipStream_t s);
+// Block widths the row kernels of launch_adj_stage cover.
+bool adj_xrow_supported(int n1);
+// The same stage reverse face by face, for meshes with level jumps or
+// walls (also valid without): gw scratch of one padded state; the
+// transposed flux correction and ghost fill of the face records jf[2 njf]
+// are included. Lookup failures latch error bit 2 in tm.
+hipError_t launch_adj_stage_facewise(int recon, const double* U, const double* lam, double* gw,
+                                     const BlockInfo* blocks, int32_t nblocks, const Geom& g, const int32_t* nbr,
+                                     const LevelMaps& maps, const int32_t* jf, int32_t njf, const double* dtp,
+                                     double beta, double* out, const double* add0, const double* add1,
+                                     DevTime* tm, hipStream_t s);
 // record: dts[c] = tm->dt; else tm->dt = dts[c].
 hipError_t launch_tape_dt(DevTime* tm, double* dts, int32_t c, int32_t record, hipStream_t s);
 

@@ -17,151 +17,10 @@
 #include <algorithm>
 #include <mutex>
 
+#include "pkh_amr.h"
 #include "pkh_device.h"
 
 namespace pkh {
-
-// ---------------------------------------------------------------------------
-// Composite-field lookups shared by the ghost fill and the regrid kernels.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ int wrap_i(int a, int n) {
-  a %= n;
-  return a < 0 ? a + n : a;
-}
-
-__device__ __forceinline__ int32_t leaf_at(const LevelMaps& M, int L, int bx, int by, int bz) {
-  return M.map[M.off[L] + ((int64_t)bz * M.nb[L][1] + by) * M.nb[L][0] + bx];
-}
-
-__device__ __forceinline__ int64_t pad_index(const Geom& g, int i, int j, int k) {
-  return ((int64_t)(k + NG) * g.p2 + (j + NG)) * g.p1 + (i + NG);
-}
-
-// Composite value at level L of a global cell J inside the domain, all five
-// variables: leaf value at level L; restriction of the level-(L+1) leaves;
-// or, while regridding, the containing coarser cell (injection).
-__device__ void comp_val_inside(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g,
-                                int L, const int J[3], double out[NV], int* err) {
-  const int n[3] = {g.n1, g.n2, g.n3};
-  const int b[3] = {J[0] / n[0], J[1] / n[1], J[2] / n[2]};
-  int32_t id = leaf_at(M, L, b[0], b[1], b[2]);
-  if (id >= 0) {
-    const double* c = u + (int64_t)id * g.bstride +
-                      pad_index(g, J[0] - b[0] * n[0], J[1] - b[1] * n[1], J[2] - b[2] * n[2]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = c[v * g.vstride];
-    return;
-  }
-  for (int Lc = L - 1; Lc >= 0; --Lc) {
-    const int sh = L - Lc;
-    id = leaf_at(M, Lc, b[0] >> sh, b[1] >> sh, b[2] >> sh);
-    if (id >= 0) {
-      const BlockInfo bc = blocks[id];
-      const double* c = u + (int64_t)id * g.bstride +
-                        pad_index(g, (J[0] >> sh) - bc.lx * n[0], (J[1] >> sh) - bc.ly * n[1],
-                                  (J[2] >> sh) - bc.lz * n[2]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = c[v * g.vstride];
-      return;
-    }
-  }
-  if (L + 1 > M.maxl) {
-    *err = 1;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = 0.0;
-    return;
-  }
-  const double* fc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int F0 = 2 * J[0] + (c & 1), F1 = 2 * J[1] + ((c >> 1) & 1), F2 = 2 * J[2] + ((c >> 2) & 1);
-    const int32_t fid = leaf_at(M, L + 1, F0 / n[0], F1 / n[1], F2 / n[2]);
-    if (fid < 0) {
-      *err = 1;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = 0.0;
-      return;
-    }
-    const BlockInfo bf = blocks[fid];
-    fc[c] = u + (int64_t)fid * g.bstride + pad_index(g, F0 - bf.lx * n[0], F1 - bf.ly * n[1], F2 - bf.lz * n[2]);
-  }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int64_t o = (int64_t)v * g.vstride;
-    out[v] = 0.125 * (((fc[0][o] + fc[1][o]) + (fc[2][o] + fc[3][o])) +
-                      ((fc[4][o] + fc[5][o]) + (fc[6][o] + fc[7][o])));
-  }
-}
-
-// Global cell J of level L (at most one domain length outside) brought into
-// the domain: wrapped along periodic directions; beyond an outflow face the
-// nearest cell inside, beyond a reflecting face the mirror image. Returns
-// the reflected directions in bits 0-2 (the image's momentum along them
-// changes sign) and bit 3 when J was moved across a wall.
-__device__ __forceinline__ int cell_in_domain(const Geom& g, int L, int J[3]) {
-  const int n[3] = {g.n1, g.n2, g.n3};
-  int code = 0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int N = (g.nrb[d] * n[d]) << L;
-    if (g.bc[2 * d] == BC_PERIODIC) {
-      J[d] = wrap_i(J[d], N);
-    } else if (J[d] < 0 || J[d] >= N) {
-      const int hi = J[d] >= N;
-      code |= 8;
-      if (g.bc[2 * d + hi] == BC_OUTFLOW) {
-        J[d] = hi ? N - 1 : 0;
-      } else {
-        J[d] = hi ? 2 * N - 1 - J[d] : -1 - J[d];
-        code |= 1 << d;
-      }
-    }
-  }
-  return code;
-}
-
-// Momentum signs of an image reflected along the directions in code.
-__device__ __forceinline__ void apply_image_signs(int code, double out[NV]) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    if ((code >> d) & 1) out[1 + d] = -out[1 + d];
-}
-
-// Composite value at level L, global cell J (any integers within a domain
-// length; brought into the domain here): beyond a wall, the value of the
-// image cell with its momentum signs.
-__device__ void comp_val(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L,
-                         int J0, int J1, int J2, double out[NV], int* err) {
-  int J[3] = {J0, J1, J2};
-  const int code = cell_in_domain(g, L, J);
-  comp_val_inside(u, blocks, M, g, L, J, out, err);
-  apply_image_signs(code, out);
-}
-
-// Linear prolongation to fine cell F (level L) from the composite field at
-// level L-1 with minmod slopes, all five variables; the fine centre sits a
-// quarter coarse width from the coarse centre along each axis.
-__device__ void prolong_val(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L,
-                            int F0, int F1, int F2, double out[NV], int* err) {
-  const int I[3] = {F0 >> 1, F1 >> 1, F2 >> 1};  // F >= 0 here
-  const int odd[3] = {F0 & 1, F1 & 1, F2 & 1};
-  double c0[NV], t[3][NV];
-  comp_val(u, blocks, M, g, L - 1, I[0], I[1], I[2], c0, err);
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double m[NV], q[NV];
-    comp_val(u, blocks, M, g, L - 1, I[0] - (d == 0), I[1] - (d == 1), I[2] - (d == 2), m, err);
-    comp_val(u, blocks, M, g, L - 1, I[0] + (d == 0), I[1] + (d == 1), I[2] + (d == 2), q, err);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double sd = minmod(c0[v] - m[v], q[v] - c0[v]);
-      t[d][v] = odd[d] ? sd : -sd;
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) out[v] = c0[v] + 0.25 * ((t[0][v] + t[1][v]) + t[2][v]);
-}
 
 // ---------------------------------------------------------------------------
 // Fill-in-one ghost exchange: one thread per (block, ghost cell), all five
@@ -240,139 +99,9 @@ __global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* b
   fill_cell(u, blocks, g, M, tm, b, i, j, k, skip_same);
 }
 
-// Restriction at level L, global cell J (in range): the 8 level-(L+1)
-// cells below it lie in one fine leaf (blocks have even edges), so the leaf
-// is looked up once; the sum is paired as in comp_val.
-__device__ __forceinline__ void restrict_val(const double* u, const BlockInfo* blocks, const LevelMaps& M,
-                                             const Geom& g, int L, const int J[3], double out[NV], int* err) {
-  const int F[3] = {2 * J[0], 2 * J[1], 2 * J[2]};
-  const int32_t fid = leaf_at(M, L + 1, F[0] / g.n1, F[1] / g.n2, F[2] / g.n3);
-  if (fid < 0) {
-    *err = 1;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = 0.0;
-    return;
-  }
-  const BlockInfo bf = blocks[fid];
-  const double* f = u + (int64_t)fid * g.bstride +
-                    pad_index(g, F[0] - bf.lx * g.n1, F[1] - bf.ly * g.n2, F[2] - bf.lz * g.n3);
-  const int64_t sx = 1, sy = g.p1, sz = (int64_t)g.p1 * g.p2;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const double* c = f + (int64_t)v * g.vstride;
-    out[v] = 0.125 * (((c[0] + c[sx]) + (c[sy] + c[sy + sx])) + ((c[sz] + c[sz + sx]) + (c[sz + sy] + c[sz + sy + sx])));
-  }
-}
-
-// The face regions (width 2, active transverse extent) listed in jf as
-// (leaf, face | wall kind << 3) pairs: the faces whose neighbour is on
-// another level or beyond a wall, the only ghost cells the stage kernels
-// read. Across a level jump, the region across one face is
-// one block of the leaf's level, so a face is either wholly inside a
-// coarser leaf or wholly refined. Coarser: the 2-deep slab is one coarse
-// cell deep and aligned to coarse cells; eight lanes share one coarse
-// cell: lane l forms the composite value of stencil point l (the cell, then
-// its -x, +x, -y, +y, -z, +z neighbours; lane 7 repeats the cell), the
-// lanes swap them by shuffles, and lane o writes fine child o. Refined: one
-// thread per ghost cell, restriction of its 8 fine cells.
 __global__ void __launch_bounds__(256) fill_faces_kernel(double* u, const BlockInfo* blocks, Geom g, LevelMaps M,
                                                          DevTime* tm, const int32_t* __restrict__ jf) {
-  const int2 rec = reinterpret_cast<const int2*>(jf)[blockIdx.y];
-  const int b = rec.x, d = (rec.y & 7) >> 1, hi = rec.y & 1, wall = rec.y >> 3;
-  const int n[3] = {g.n1, g.n2, g.n3};
-  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  double* ub = u + (int64_t)b * g.bstride;
-  if (wall) {
-    // a face on the domain boundary: the image of each ghost cell lies in
-    // the leaf itself (the nearest layer for outflow, the mirror layer for
-    // reflection, normal momentum negated)
-    const int area = n[t1] * n[t2];
-    if (q >= 2 * area) return;
-    const int s = q / area, r = q - s * area;
-    int c[3], src[3];
-    c[t1] = src[t1] = r % n[t1];
-    c[t2] = src[t2] = r / n[t1];
-    c[d] = hi ? n[d] + s : s - NG;
-    if (wall == BC_OUTFLOW)
-      src[d] = hi ? n[d] - 1 : 0;
-    else
-      src[d] = hi ? 2 * n[d] - 1 - c[d] : -1 - c[d];
-    const double* sp = ub + pad_index(g, src[0], src[1], src[2]);
-    double* dp = ub + pad_index(g, c[0], c[1], c[2]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double x = sp[v * g.vstride];
-      dp[v * g.vstride] = (wall == BC_REFLECT && v == 1 + d) ? -x : x;
-    }
-    return;
-  }
-  const BlockInfo bi = blocks[b];
-  const int L = bi.level;
-  int bl[3] = {bi.lx, bi.ly, bi.lz};
-  bl[d] = wrap_i(bl[d] + (hi ? 1 : -1), g.nrb[d] << L);
-  const bool coarser = L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0;
-  int err = 0;
-  if (coarser) {
-    // Uniform per workgroup (one face per blockIdx.y): whole 8-lane groups
-    // leave together, so the shuffles below see only live groups.
-    const int m1 = n[t1] >> 1, m2 = n[t2] >> 1;
-    const int cq = q >> 3, l = q & 7;
-    if (cq >= m1 * m2) return;
-    int c[3];  // first fine ghost cell of this group's 2x2x2 children, leaf coordinates
-    c[t1] = 2 * (cq % m1);
-    c[t2] = 2 * (cq / m1);
-    c[d] = hi ? n[d] : -NG;
-    int I[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const int lo = e == 0 ? bi.lx : (e == 1 ? bi.ly : bi.lz);
-      I[e] = wrap_i(lo * n[e] + c[e], (g.nrb[e] * n[e]) << L) >> 1;
-    }
-    const int se = (l - 1) >> 1, sg = (l & 1) ? -1 : 1;  // lanes 1..6: axis and side
-    const bool ctr = l == 0 || l == 7;
-    double val[NV];
-    comp_val(u, blocks, M, g, L - 1, I[0] + (!ctr && se == 0 ? sg : 0), I[1] + (!ctr && se == 1 ? sg : 0),
-             I[2] + (!ctr && se == 2 ? sg : 0), val, &err);
-    const int base = threadIdx.x & ~7 & 63;
-    const int o = l;
-    double outv[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double c0 = __shfl(val[v], base, 64);
-      double t[3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const double mv = __shfl(val[v], base + 1 + 2 * e, 64);
-        const double pv = __shfl(val[v], base + 2 + 2 * e, 64);
-        const double sd = minmod(c0 - mv, pv - c0);
-        t[e] = ((o >> e) & 1) ? sd : -sd;
-      }
-      outv[v] = c0 + 0.25 * ((t[0] + t[1]) + t[2]);
-    }
-    // c[e] is even in every direction, so child o sits on the odd side
-    // along e exactly when bit e of o is set.
-    double* dst = ub + pad_index(g, c[0] + (o & 1), c[1] + ((o >> 1) & 1), c[2] + ((o >> 2) & 1));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) dst[v * g.vstride] = outv[v];
-  } else {
-    const int area = n[t1] * n[t2];
-    if (q >= 2 * area) return;
-    const int s = q / area, r = q - s * area;
-    int c[3];
-    c[t1] = r % n[t1];
-    c[t2] = r / n[t1];
-    c[d] = hi ? n[d] + s : s - NG;
-    const int J[3] = {wrap_i(bi.lx * n[0] + c[0], (g.nrb[0] * n[0]) << L),
-                      wrap_i(bi.ly * n[1] + c[1], (g.nrb[1] * n[1]) << L),
-                      wrap_i(bi.lz * n[2] + c[2], (g.nrb[2] * n[2]) << L)};
-    double val[NV];
-    restrict_val(u, blocks, M, g, L, J, val, &err);
-    double* dst = ub + pad_index(g, c[0], c[1], c[2]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) dst[v * g.vstride] = val[v];
-  }
-  if (err) atomicOr(&tm->err, 2);
+  fill_faces_item(u, blocks, g, M, tm, jf, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
@@ -461,123 +190,14 @@ hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, cons
   return hipGetLastError();
 }
 
-// q-th cell of the outer layer of a block (a coordinate at 0 or n - 1):
-// the two z planes, then for each inner plane its two y rows and the two
-// x ends of each inner row. False past the last one.
-__device__ __forceinline__ bool shell_coord(int q, const Geom& g, int& i, int& j, int& k) {
-  const int plane = g.n1 * g.n2;
-  if (q < 0) return false;
-  if (q < 2 * plane) {
-    const bool top = q >= plane;
-    k = top ? g.n3 - 1 : 0;
-    const int r = top ? q - plane : q;
-    j = r / g.n1;
-    i = r - j * g.n1;
-    return true;
-  }
-  q -= 2 * plane;
-  const int per = 2 * g.n1 + 2 * (g.n2 - 2);
-  if (q >= (g.n3 - 2) * per) return false;
-  k = 1 + q / per;
-  int r = q - (k - 1) * per;
-  if (r < 2 * g.n1) {
-    const bool top = r >= g.n1;
-    j = top ? g.n2 - 1 : 0;
-    i = top ? r - g.n1 : r;
-    return true;
-  }
-  r -= 2 * g.n1;
-  j = 1 + (r >> 1);
-  i = (r & 1) ? g.n1 - 1 : 0;
-  return true;
-}
-
-// ---------------------------------------------------------------------------
-// Flux correction as reflux: on each coarse face bordering finer leaves the
-// coarse flux is replaced by the area mean of the 4 fine fluxes,
-// U += +-beta*dt/dx * (F_own - F_fine). One thread per outer-layer cell of
-// a coarse block that has such faces; a cell on one of them applies all of
-// its faces in x, y, z order, then (corrector stage) contributes to the CFL
-// reduction the stage kernel skipped for it.
-// ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) flux_correct_kernel(double* u, const BlockInfo* blocks,
-                                                           const FineFace* ff,
-                                                           const int32_t* ff_first,
-                                                           const int32_t* cblocks, Geom g,
-                                                           DevTime* tm, double beta, int do_dt,
-                                                           const double* fbuf, const int32_t* nbr) {
+                                                           const FineFace* ff, const int32_t* ff_first,
+                                                           const int32_t* cblocks, Geom g, DevTime* tm,
+                                                           double beta, int do_dt, const double* fbuf) {
   __shared__ double sRed[4];
-  const int c = blockIdx.y;
-  const int b = cblocks[c];
-  const BlockInfo bi = blocks[b];
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  double smax = 0.0;
-  bool bad = false;
-  int i, j, k;
-  if (shell_coord(q, g, i, j, k) &&
-      ((((bi.finer_mask >> XLO) & 1) && i == 0) || (((bi.finer_mask >> XHI) & 1) && i == g.n1 - 1) ||
-       (((bi.finer_mask >> YLO) & 1) && j == 0) || (((bi.finer_mask >> YHI) & 1) && j == g.n2 - 1) ||
-       (((bi.finer_mask >> ZLO) & 1) && k == 0) || (((bi.finer_mask >> ZHI) & 1) && k == g.n3 - 1))) {
-    const int fsz = NV * max(max(g.n1 * g.n2, g.n1 * g.n3), g.n2 * g.n3);
-    bool touched = false;
-    double* cell = u + (int64_t)b * g.bstride + pad_index(g, i, j, k);
-    double uc[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) uc[v] = cell[v * g.vstride];
-    const double coef = beta * tm->dt;
-    for (int e = ff_first[c]; e < ff_first[c + 1]; ++e) {
-      const FineFace rec = ff[e];
-      const int d = rec.face >> 1, s = rec.face & 1;
-      // normal axis d and the two transverse axes in increasing order, as
-      // selects (per-lane indexing of small arrays would put them in
-      // scratch memory)
-      const int cd = d == 0 ? i : (d == 1 ? j : k);
-      const int nd = d == 0 ? g.n1 : (d == 1 ? g.n2 : g.n3);
-      if (cd != (s ? nd - 1 : 0)) continue;
-      touched = true;
-      const int a1 = d == 0 ? j : i, m1 = d == 0 ? g.n2 : g.n1;
-      const int a2 = d == 2 ? j : k, m2 = d == 2 ? g.n2 : g.n3;
-      const int h1 = a1 >= m1 / 2, h2 = a2 >= m2 / 2;
-      const int sub = h1 + 2 * h2;
-      const int fs = sub == 0   ? rec.fine_slot[0]
-                     : sub == 1 ? rec.fine_slot[1]
-                     : sub == 2 ? rec.fine_slot[2]
-                                : rec.fine_slot[3];
-      const double idd = d == 0 ? bi.idx[0] : (d == 1 ? bi.idx[1] : bi.idx[2]);
-      const int f1 = 2 * a1 - h1 * m1, f2 = 2 * a2 - h2 * m2;
-      const double sg = s ? 1.0 : -1.0;
-      for (int v = 0; v < NV; ++v) {
-        const double own = fbuf[(int64_t)rec.own_slot * fsz + ((int64_t)v * m2 + a2) * m1 + a1];
-        const double* fb = fbuf + (int64_t)fs * fsz + (int64_t)v * m2 * m1;
-        const double fine = 0.25 * ((fb[f2 * m1 + f1] + fb[f2 * m1 + f1 + 1]) +
-                                    (fb[(f2 + 1) * m1 + f1] + fb[(f2 + 1) * m1 + f1 + 1]));
-        uc[v] += sg * coef * (own - fine) * idd;
-      }
-    }
-    if (touched) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) cell[v * g.vstride] = uc[v];
-      if (do_dt) {
-        double wn[NV];
-        bad = !to_prim(uc, g.gamma, wn);
-        const double cs = sqrt(g.gamma * wn[4] / wn[0]);
-        smax = fmax(fmax((fabs(wn[1]) + cs) * bi.idx[0], (fabs(wn[2]) + cs) * bi.idx[1]),
-                    (fabs(wn[3]) + cs) * bi.idx[2]);
-      }
-    }
-  }
-  if (do_dt) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off));
-    if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = smax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const double mx = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
-      atomicMax(&tm->smax_bits, (unsigned long long)__double_as_longlong(mx));
-    }
-  }
-  if (bad) atomicOr(&tm->err, 1);
+  flux_correct_item(u, blocks, ff, ff_first, cblocks, g, tm, tm->dt, beta, do_dt, fbuf, blockIdx.x, blockIdx.y,
+                    sRed);
 }
 
 hipError_t launch_flux_correct(double* u, const BlockInfo* blocks, const FineFace* ff,
@@ -588,7 +208,7 @@ hipError_t launch_flux_correct(double* u, const BlockInfo* blocks, const FineFac
   const int nshell = 2 * g.n1 * g.n2 + (g.n3 - 2) * (2 * g.n1 + 2 * (g.n2 - 2));
   dim3 grid((nshell + 255) / 256, ncblocks);
   hipLaunchKernelGGL(flux_correct_kernel, grid, dim3(256), 0, s, u, blocks, ff, ff_first, cblocks,
-                     g, tm, beta, do_dt, fbuf, nbr);
+                     g, tm, beta, do_dt, fbuf);
   return hipGetLastError();
 }
 
@@ -1518,6 +1138,417 @@ hipError_t launch_adj_stage(int recon, const double* U, const double* lam, doubl
                        nblocks, g, dtp, beta);
     launch_xrow<0>(g.n1, gr, s, U, lam, wyz, wstride, xside, blocks, nbr, nblocks, g, dtp, beta, out, add0, add1);
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Face-wise reverse mode of one stage, for meshes with level jumps or walls
+// (also valid on single-level meshes): U_out = U_base - beta dt D(U_in) with
+// the fine-coarse flux correction of every stage, differentiated w.r.t. the
+// active cells of U_in through the ghost faces the stage reads.
+//  1. Each face whose flux enters some update gets its adjoint
+//     mu = beta dt (lam_up w_up / dx_up - lam_lo w_lo / dx_lo); a coarse
+//     cell beside finer leaves sees each fine sub-face with weight 1/4 (its
+//     own flux there is replaced, so it gets none). The face is handled by
+//     the leaf on its fine side, by the lower leaf of a same-level pair, and
+//     by the leaf itself at a wall.
+//  2. mu goes back through HLLE (frozen wave-speed cases), the face states
+//     (frozen MC cases) and the primitive recovery to the stencil cells:
+//     atomically added into a padded primitive-adjoint array, cells beyond a
+//     same-level face into the neighbour's active cells, cells beyond a
+//     level jump or wall into the leaf's own ghost zone.
+//  3. Primitive adjoints become conserved ones at the forward states.
+//  4. Every ghost-zone adjoint moves to the active cells its forward value
+//     came from: the image cell at a wall; 1/8 to each of 8 fine cells for a
+//     restriction; for a prolongation the transposed linear map with the
+//     forward's minmod cases, onto the composite coarse field (coarse leaf
+//     cells, or 1/8 to each fine cell of a restricted composite value).
+//  5. out = add0 + add1 + the active-cell adjoints.
+// ---------------------------------------------------------------------------
+
+// Neighbour kind across face f of leaf bi: 0 same level, 1 coarser, 2 finer,
+// 3 wall.
+__device__ __forceinline__ int face_kind(const BlockInfo& bi, const int32_t* nb27, const Geom& g, int f) {
+  const int d = f >> 1, s = f & 1;
+  if (g.bc[2 * d] != BC_PERIODIC) {
+    const int lo = d == 0 ? bi.lx : (d == 1 ? bi.ly : bi.lz);
+    if ((s == 0 && lo == 0) || (s == 1 && lo == (g.nrb[d] << bi.level) - 1)) return 3;
+  }
+  const int q = (d == 2 ? (s ? 2 : 0) : 1) * 9 + (d == 1 ? (s ? 2 : 0) : 1) * 3 + (d == 0 ? (s ? 2 : 0) : 1);
+  if (nb27[q] >= 0) return 0;
+  if ((bi.finer_mask >> f) & 1) return 2;
+  return 1;
+}
+
+// lam of the coarse cell beside fine leaf bi (level L >= 1) across its face
+// along d on side s, at the fine cell's transverse position c (leaf
+// coordinates, c[d] the fine cell next to the face); writes the coarse
+// leaf's 1/dx_d to *idd. False if no coarse leaf covers it.
+__device__ bool coarse_lam(const double* lam, const BlockInfo* blocks, const LevelMaps& M, const Geom& g,
+                           const BlockInfo& bi, int d, int s, const int c[3], double out[NV], double* idd) {
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const int lo[3] = {bi.lx, bi.ly, bi.lz};
+  int J[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) J[e] = lo[e] * n[e] + c[e] + (e == d ? (s ? 1 : -1) : 0);
+  const int L = bi.level;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) J[e] = wrap_i(J[e], (g.nrb[e] * n[e]) << L) >> 1;
+  const int32_t id = leaf_at(M, L - 1, J[0] / n[0], J[1] / n[1], J[2] / n[2]);
+  if (id < 0) return false;
+  const BlockInfo bc = blocks[id];
+  const int64_t cs = (int64_t)n[0] * n[1] * n[2];
+  const int64_t o = (int64_t)id * NV * cs + ((int64_t)(J[2] - bc.lz * n[2]) * n[1] + (J[1] - bc.ly * n[1])) * n[0] +
+                    (J[0] - bc.lx * n[0]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = lam[o + v * cs];
+  *idd = d == 0 ? bc.idx[0] : (d == 1 ? bc.idx[1] : bc.idx[2]);
+  return true;
+}
+
+template <int RECON>
+__global__ void __launch_bounds__(256) adjf_face_kernel(const double* __restrict__ U, const double* __restrict__ lam,
+                                                        double* gw, const BlockInfo* blocks, const int32_t* nbr,
+                                                        LevelMaps M, Geom g, const double* dtp, double beta,
+                                                        int64_t nfaces, DevTime* tm) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nfaces) return;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const int64_t fx = (int64_t)(n[0] + 1) * n[1] * n[2], fy = (int64_t)n[0] * (n[1] + 1) * n[2],
+                fz = (int64_t)n[0] * n[1] * (n[2] + 1);
+  const int64_t per = fx + fy + fz;
+  const int b = (int)(q / per);
+  int64_t r = q - (int64_t)b * per;
+  const int d = r < fx ? 0 : (r < fx + fy ? 1 : 2);
+  r -= d == 0 ? 0 : (d == 1 ? fx : fx + fy);
+  const int e0 = n[0] + (d == 0), e1 = n[1] + (d == 1);
+  int c[3];  // the face's upper cell (leaf coordinates); c[d] in [0, n_d]
+  c[0] = (int)(r % e0);
+  c[1] = (int)((r / e0) % e1);
+  c[2] = (int)(r / ((int64_t)e0 * e1));
+  const BlockInfo bi = blocks[b];
+  const int32_t* nb27 = nbr + (int64_t)b * 27;
+  const int cd = c[d], nd = n[d];
+  int klo = -1, kup = -1;  // neighbour kinds where the face is a block face
+  if (cd == 0) {
+    klo = face_kind(bi, nb27, g, 2 * d);
+    if (klo == 0 || klo == 2) return;  // handled by the same-level or finer leaf
+  } else if (cd == nd) {
+    kup = face_kind(bi, nb27, g, 2 * d + 1);
+    if (kup == 2) return;
+  }
+  const double dt = *dtp;
+  const double bdt = beta * dt;
+  const double idd = d == 0 ? bi.idx[0] : (d == 1 ? bi.idx[1] : bi.idx[2]);
+  const int64_t cs = (int64_t)n[0] * n[1] * n[2];
+  auto lam_at = [&](int bb, int i, int j, int k, double out[NV]) {
+    const int64_t o = (int64_t)bb * NV * cs + ((int64_t)k * n[1] + j) * n[0] + i;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = lam[o + v * cs];
+  };
+  double mu[NV];
+  double lup[NV], llo[NV];
+  double wup = 0.0, wlo = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) lup[v] = llo[v] = 0.0;
+  int err = 0;
+  // upper cell
+  if (cd < nd) {
+    lam_at(b, c[0], c[1], c[2], lup);
+    wup = idd;
+  } else if (kup == 0) {
+    const int qn = (d == 2 ? 2 : 1) * 9 + (d == 1 ? 2 : 1) * 3 + (d == 0 ? 2 : 1);
+    lam_at(nb27[qn], d == 0 ? 0 : c[0], d == 1 ? 0 : c[1], d == 2 ? 0 : c[2], lup);
+    wup = idd;
+  } else if (kup == 1) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[d] = nd - 1;
+    double ic;
+    if (coarse_lam(lam, blocks, M, g, bi, d, 1, cc, lup, &ic)) wup = 0.25 * ic; else err = 1;
+  }
+  // lower cell
+  if (cd > 0) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[d] -= 1;
+    lam_at(b, cc[0], cc[1], cc[2], llo);
+    wlo = idd;
+  } else if (klo == 1) {
+    double ic;
+    if (coarse_lam(lam, blocks, M, g, bi, d, 0, c, llo, &ic)) wlo = 0.25 * ic; else err = 1;
+  }
+  if (err) atomicOr(&tm->err, 2);
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    mu[v] = bdt * (wup * lup[v] - wlo * llo[v]);
+    any |= mu[v] != 0.0;
+  }
+  if (!any) return;
+  // stencil cells i-2, i-1, i, i+1 along d (DC: i-1, i)
+  const double gam = g.gamma, gm1 = gam - 1.0, igm1 = 1.0 / gm1;
+  int64_t idx[4];
+  double w[4][NV];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (!RECON && (t == 0 || t == 3)) continue;
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[d] += t - 2;
+    idx[t] = nb_index(g, nbr, b, cc[0], cc[1], cc[2]);
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[idx[t] + v * g.vstride];
+    to_prim(u, gam, w[t]);
+  }
+  FState L, R;
+  double wl[NV], wr[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (RECON) {
+      wl[v] = w[1][v] + mc_half(w[1][v] - w[0][v], w[2][v] - w[1][v]);
+      wr[v] = w[2][v] - mc_half(w[2][v] - w[1][v], w[3][v] - w[2][v]);
+    } else {
+      wl[v] = w[1][v];
+      wr[v] = w[2][v];
+    }
+  }
+  L = FState{wl[0], wl[1], wl[2], wl[3], wl[4], 0, 0, 0};
+  R = FState{wr[0], wr[1], wr[2], wr[3], wr[4], 0, 0, 0};
+  complete_state(L, gam, igm1);
+  complete_state(R, gam, igm1);
+  double gL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gR[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  hlle_rev<-1>(L, R, gm1, mu, gL, gR, d);
+  double gwl[NV] = {0, 0, 0, 0, 0}, gwr[NV] = {0, 0, 0, 0, 0};
+  complete_state_rev(L, gam, igm1, gL, gwl);
+  complete_state_rev(R, gam, igm1, gR, gwr);
+  double gq[4][NV];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gq[t][v] = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (RECON) {
+      double ga, gb;
+      mc_branch(w[1][v] - w[0][v], w[2][v] - w[1][v], ga, gb);
+      gq[1][v] += gwl[v] * (1.0 + 0.5 * ga - 0.5 * gb);
+      gq[0][v] -= gwl[v] * 0.5 * ga;
+      gq[2][v] += gwl[v] * 0.5 * gb;
+      mc_branch(w[2][v] - w[1][v], w[3][v] - w[2][v], ga, gb);
+      gq[2][v] += gwr[v] * (1.0 - 0.5 * ga + 0.5 * gb);
+      gq[1][v] += gwr[v] * 0.5 * ga;
+      gq[3][v] -= gwr[v] * 0.5 * gb;
+    } else {
+      gq[1][v] = gwl[v];
+      gq[2][v] = gwr[v];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (!RECON && (t == 0 || t == 3)) continue;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (gq[t][v] != 0.0) atomicAdd(&gw[idx[t] + v * g.vstride], gq[t][v]);
+  }
+}
+
+// Primitive adjoints to conserved ones at the forward state, in place, over
+// every padded cell that received any.
+__global__ void __launch_bounds__(256) adjf_prim_kernel(const double* __restrict__ U, double* gw, int64_t ncells,
+                                                        Geom g) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ncells) return;
+  const int64_t b = q / g.vstride, c = q - b * g.vstride;
+  const int64_t o = b * g.bstride + c;
+  double gp[NV];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    gp[v] = gw[o + v * g.vstride];
+    any |= gp[v] != 0.0;
+  }
+  if (!any) return;
+  double u[NV], gu[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = U[o + v * g.vstride];
+  prim_rev(u, g.gamma, gp, gu);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) gw[o + v * g.vstride] = gu[v];
+}
+
+// Add weight * x (image signs of code applied) to the composite level-L
+// field at global cell J (any integers within a domain length): the level-L
+// leaf's cell, or 1/8 to each of the 8 level-(L+1) cells below it.
+__device__ void comp_scatter(double* gu, const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L,
+                             int J0, int J1, int J2, const double x[NV], double weight, int* err) {
+  int J[3] = {J0, J1, J2};
+  const int code = cell_in_domain(g, L, J);
+  double y[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) y[v] = weight * x[v];
+  apply_image_signs(code, y);
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const int32_t id = leaf_at(M, L, J[0] / n[0], J[1] / n[1], J[2] / n[2]);
+  if (id >= 0) {
+    const BlockInfo bc = blocks[id];
+    double* p = gu + (int64_t)id * g.bstride +
+                pad_index(g, J[0] - bc.lx * n[0], J[1] - bc.ly * n[1], J[2] - bc.lz * n[2]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (y[v] != 0.0) atomicAdd(&p[v * g.vstride], y[v]);
+    return;
+  }
+  if (L + 1 > M.maxl) {
+    *err = 1;
+    return;
+  }
+  for (int cc = 0; cc < 8; ++cc) {
+    const int F0 = 2 * J[0] + (cc & 1), F1 = 2 * J[1] + ((cc >> 1) & 1), F2 = 2 * J[2] + ((cc >> 2) & 1);
+    const int32_t fid = leaf_at(M, L + 1, F0 / n[0], F1 / n[1], F2 / n[2]);
+    if (fid < 0) {
+      *err = 1;
+      return;
+    }
+    const BlockInfo bf = blocks[fid];
+    double* p = gu + (int64_t)fid * g.bstride + pad_index(g, F0 - bf.lx * n[0], F1 - bf.ly * n[1], F2 - bf.lz * n[2]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (y[v] != 0.0) atomicAdd(&p[v * g.vstride], 0.125 * y[v]);
+  }
+}
+
+// Transposed ghost fill of the face records jf (level jumps and walls): one
+// thread per ghost cell of a face slab; gu holds conserved adjoints.
+__global__ void __launch_bounds__(256) adjf_ghost_kernel(const double* __restrict__ U, double* gu,
+                                                         const BlockInfo* blocks, Geom g, LevelMaps M, DevTime* tm,
+                                                         const int32_t* __restrict__ jf) {
+  const int2 rec = reinterpret_cast<const int2*>(jf)[blockIdx.y];
+  const int b = rec.x, d = (rec.y & 7) >> 1, hi = rec.y & 1, wall = rec.y >> 3;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const int area = n[t1] * n[t2];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 2 * area) return;
+  const int s = q / area, r = q - s * area;
+  int c[3];
+  c[t1] = r % n[t1];
+  c[t2] = r / n[t1];
+  c[d] = hi ? n[d] + s : s - NG;
+  double* ub = gu + (int64_t)b * g.bstride;
+  double x[NV];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    x[v] = ub[pad_index(g, c[0], c[1], c[2]) + v * g.vstride];
+    any |= x[v] != 0.0;
+  }
+  if (!any) return;
+  int err = 0;
+  if (wall) {
+    int src[3] = {c[0], c[1], c[2]};
+    src[d] = wall == BC_OUTFLOW ? (hi ? n[d] - 1 : 0) : (hi ? 2 * n[d] - 1 - c[d] : -1 - c[d]);
+    double* p = ub + pad_index(g, src[0], src[1], src[2]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      atomicAdd(&p[v * g.vstride], (wall == BC_REFLECT && v == 1 + d) ? -x[v] : x[v]);
+    return;
+  }
+  const BlockInfo bi = blocks[b];
+  const int L = bi.level;
+  int bl[3] = {bi.lx, bi.ly, bi.lz};
+  bl[d] = wrap_i(bl[d] + (hi ? 1 : -1), g.nrb[d] << L);
+  const bool coarser = L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0;
+  const int lo[3] = {bi.lx, bi.ly, bi.lz};
+  int J[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) J[e] = wrap_i(lo[e] * n[e] + c[e], (g.nrb[e] * n[e]) << L);
+  if (coarser) {
+    // x = C(I) + 1/4 sum_e sigma_e s_e, s_e = minmod(C(I) - C(I-e), C(I+e) - C(I))
+    const int I[3] = {J[0] >> 1, J[1] >> 1, J[2] >> 1};
+    double c0[NV], cm[3][NV], cp[3][NV];
+    comp_val(U, blocks, M, g, L - 1, I[0], I[1], I[2], c0, &err);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      comp_val(U, blocks, M, g, L - 1, I[0] - (e == 0), I[1] - (e == 1), I[2] - (e == 2), cm[e], &err);
+      comp_val(U, blocks, M, g, L - 1, I[0] + (e == 0), I[1] + (e == 1), I[2] + (e == 2), cp[e], &err);
+    }
+    double a0[NV], am[3][NV], ap[3][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double k0 = 1.0;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const double sg = (J[e] & 1) ? 0.25 : -0.25;
+        const double da = c0[v] - cm[e][v], db = cp[e][v] - c0[v];
+        am[e][v] = ap[e][v] = 0.0;
+        if (da * db > 0.0) {
+          if (fabs(da) <= fabs(db)) {  // s = da
+            k0 += sg;
+            am[e][v] = -sg * x[v];
+          } else {  // s = db
+            k0 -= sg;
+            ap[e][v] = sg * x[v];
+          }
+        }
+      }
+      a0[v] = k0 * x[v];
+    }
+    comp_scatter(gu, blocks, M, g, L - 1, I[0], I[1], I[2], a0, 1.0, &err);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      comp_scatter(gu, blocks, M, g, L - 1, I[0] - (e == 0), I[1] - (e == 1), I[2] - (e == 2), am[e], 1.0, &err);
+      comp_scatter(gu, blocks, M, g, L - 1, I[0] + (e == 0), I[1] + (e == 1), I[2] + (e == 2), ap[e], 1.0, &err);
+    }
+  } else {
+    // restriction of the 8 fine cells below J
+    comp_scatter(gu, blocks, M, g, L, J[0], J[1], J[2], x, 1.0, &err);
+  }
+  if (err) atomicOr(&tm->err, 2);
+}
+
+// out (upload layout) = add0 + add1 + the active cells of gu.
+__global__ void __launch_bounds__(256) adjf_out_kernel(const double* __restrict__ gu, double* out,
+                                                       const double* add0, const double* add1, int64_t total,
+                                                       Geom g) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= total) return;
+  const int i = q % g.n1;
+  int64_t r = q / g.n1;
+  const int j = r % g.n2;
+  r /= g.n2;
+  const int k = r % g.n3;
+  r /= g.n3;  // r = block*5 + v
+  double x = gu[r * g.vstride + pad_index(g, i, j, k)];
+  if (add0) x += add0[q];
+  if (add1) x += add1[q];
+  out[q] = x;
+}
+
+hipError_t launch_adj_stage_facewise(int recon, const double* U, const double* lam, double* gw,
+                                     const BlockInfo* blocks, int32_t nblocks, const Geom& g, const int32_t* nbr,
+                                     const LevelMaps& maps, const int32_t* jf, int32_t njf, const double* dtp,
+                                     double beta, double* out, const double* add0, const double* add1,
+                                     DevTime* tm, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(gw, 0, (size_t)nblocks * g.bstride * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  const int64_t nfaces = (int64_t)nblocks * ((int64_t)(g.n1 + 1) * g.n2 * g.n3 + (int64_t)g.n1 * (g.n2 + 1) * g.n3 +
+                                             (int64_t)g.n1 * g.n2 * (g.n3 + 1));
+  const dim3 gf((unsigned)((nfaces + 255) / 256));
+  if (recon)
+    hipLaunchKernelGGL(adjf_face_kernel<1>, gf, dim3(256), 0, s, U, lam, gw, blocks, nbr, maps, g, dtp, beta,
+                       nfaces, tm);
+  else
+    hipLaunchKernelGGL(adjf_face_kernel<0>, gf, dim3(256), 0, s, U, lam, gw, blocks, nbr, maps, g, dtp, beta,
+                       nfaces, tm);
+  const int64_t ncells = (int64_t)nblocks * g.vstride;
+  hipLaunchKernelGGL(adjf_prim_kernel, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s, U, gw, ncells, g);
+  if (njf > 0) {
+    const int area = std::max(std::max(g.n1 * g.n2, g.n1 * g.n3), g.n2 * g.n3);
+    hipLaunchKernelGGL(adjf_ghost_kernel, dim3((2 * area + 255) / 256, njf), dim3(256), 0, s, U, gw, blocks, g, maps,
+                       tm, jf);
+  }
+  const int64_t total = (int64_t)nblocks * NV * g.n1 * g.n2 * g.n3;
+  hipLaunchKernelGGL(adjf_out_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, gw, out, add0, add1,
+                     total, g);
   return hipGetLastError();
 }
 

@@ -487,6 +487,8 @@ int check_err(pkh_mesh* m) {
   DevTime h;
   HIPCHK(hipMemcpyAsync(&h, m->d_time, sizeof h, hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
+  if (h.err & 4)
+    return fail(PKH_ESTATE, "a bounded wait of a persistent batch launch gave up: the state is invalid");
   if (h.err & 2) return fail(PKH_EBALANCE, "a ghost or regrid lookup found no covering leaf");
   if (h.err & 1) return fail(PKH_EPHYS, "unphysical state (rho <= 0, P <= 0 or non-finite)");
   return PKH_OK;
@@ -867,6 +869,8 @@ int pkh_get_time(pkh_mesh* m, double* t, double* dt, int64_t* cycle) {
   if (dt) *dt = h.dt_next;
   if (cycle) *cycle = h.cycle;
   if (h.err & 1) return fail(PKH_EPHYS, "unphysical state (rho <= 0, P <= 0 or non-finite)");
+  if (h.err & 4)
+    return fail(PKH_ESTATE, "a bounded wait of a persistent batch launch gave up: the state is invalid");
   if (h.err & 2) return fail(PKH_EBALANCE, "a ghost or regrid lookup found no covering leaf");
   return PKH_OK;
 }
@@ -1176,6 +1180,10 @@ struct pkh_tape {
   double* xlast = nullptr;       // parts across x faces, 20 doubles per row
   double* lam[3] = {nullptr, nullptr, nullptr};  // active-layout adjoints
   DevTime* d_time = nullptr;     // clock for recomputation (dt from the record)
+  // face-wise reverse (meshes with level jumps or walls; optional otherwise):
+  // one padded adjoint scratch instead of the pencil and row buffers
+  bool facewise = false;
+  double* gw = nullptr;
 };
 
 namespace {
@@ -1194,6 +1202,8 @@ void tape_free(pkh_tape* t) {
   m->dfree(t->d_dts);
   m->dfree(t->wbar);
   m->dfree(t->xlast);
+  m->dfree(t->gw);
+  t->gw = nullptr;
   for (auto& l : t->lam) m->dfree(l);
   m->dfree(t->d_time);
   t->d_dts = nullptr;
@@ -1219,6 +1229,16 @@ int tape_recompute(pkh_tape* t, int c0, int len) {
   s.nbr = m->d_nbr;
   s.tj = m->tj;
   s.do_dt = 0;
+  // the level-jump and wall work of a stage on its output, as in the cycle
+  auto level_jumps = [&](double* u, double beta) -> hipError_t {
+    if (m->ncblocks) {
+      const hipError_t e = launch_flux_correct(u, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks, m->ncblocks,
+                                               m->g, t->d_time, beta, 0, m->d_fbuf, m->d_nbr, m->stream);
+      if (e != hipSuccess) return e;
+    }
+    if (m->njf) return launch_fill_faces(u, m->d_blocks, m->g, m->maps, t->d_time, m->d_jf, m->njf, m->stream);
+    return hipSuccess;
+  };
   for (int q = 0; q < len; ++q) {
     HIPCHK(launch_tape_dt(t->d_time, t->d_dts, c0 + q, 0, m->stream));
     s.uin = t->S[q];
@@ -1227,12 +1247,14 @@ int tape_recompute(pkh_tape* t, int c0, int len) {
     s.beta = 0.5;
     s.recon = m->cfg.stage1_recon;
     HIPCHK(launch_stage(s, m->stream));
+    HIPCHK(level_jumps(t->Us[q], 0.5));
     s.uin = t->Us[q];
     s.ubase = t->S[q];
     s.uout = t->S[q + 1];
     s.beta = 1.0;
     s.recon = PKH_RECON_PLM;
     HIPCHK(launch_stage(s, m->stream));
+    HIPCHK(level_jumps(t->S[q + 1], 1.0));
   }
   return PKH_OK;
 }
@@ -1243,11 +1265,14 @@ extern "C" {
 int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
   if (!m || !out || ckpt_every < 1) return fail(PKH_EINVAL, "bad argument");
   *out = nullptr;
-  if (m->need_fill || m->ncblocks || m->fp32)
-    return fail(PKH_EINVAL, "the reverse mode supports single-level periodic FP64 meshes only");
+  if (m->fp32 || m->nparts > 1)
+    return fail(PKH_EINVAL, "the reverse mode needs an FP64-stored mesh without a partition");
   pkh_tape* t = new pkh_tape();
   t->m = m;
   t->K = ckpt_every;
+  // level jumps or walls: the face-wise reverse; blocks the row kernels do
+  // not cover: the same
+  t->facewise = m->need_fill || m->ncblocks || !adj_xrow_supported(m->g.n1);
   const size_t pb = m->state_bytes();
   bool ok = true;
   for (int q = 0; q <= ckpt_every && ok; ++q) {
@@ -1259,11 +1284,16 @@ int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
     ok = t->Us.back() != nullptr;
   }
   if (ok) {
-    t->wbar = (double*)m->dalloc(2 * pb);
-    t->xlast = (double*)m->dalloc((size_t)m->nb() * m->g.n2 * m->g.n3 * 20 * sizeof(double));
+    if (t->facewise) {
+      t->gw = (double*)m->dalloc(pb);
+    } else {
+      t->wbar = (double*)m->dalloc(2 * pb);
+      t->xlast = (double*)m->dalloc((size_t)m->nb() * m->g.n2 * m->g.n3 * 20 * sizeof(double));
+    }
     for (auto& l : t->lam) l = (double*)m->dalloc(active_bytes(m));
     t->d_time = (DevTime*)m->dalloc(sizeof(DevTime));
-    ok = t->wbar && t->xlast && t->lam[0] && t->lam[1] && t->lam[2] && t->d_time;
+    ok = (t->facewise ? t->gw != nullptr : (t->wbar && t->xlast)) && t->lam[0] && t->lam[1] && t->lam[2] &&
+         t->d_time;
   }
   if (!ok) {
     tape_free(t);
@@ -1285,6 +1315,30 @@ int pkh_tape_destroy(pkh_tape* t) {
   tape_free(t);
   t->m->attached--;
   delete t;
+  return PKH_OK;
+}
+
+int pkh_tape_set_facewise(pkh_tape* t, int32_t on) {
+  if (!t) return fail(PKH_EINVAL, "null tape");
+  pkh_mesh* m = t->m;
+  const bool need = m->need_fill || m->ncblocks || !adj_xrow_supported(m->g.n1);
+  if (!on && need) return fail(PKH_EINVAL, "this mesh needs the face-wise reverse");
+  if ((on != 0) == t->facewise) return PKH_OK;
+  HIPCHK(hipStreamSynchronize(m->stream));
+  const size_t pb = m->state_bytes();
+  m->dfree(t->gw);
+  m->dfree(t->wbar);
+  m->dfree(t->xlast);
+  t->gw = t->wbar = t->xlast = nullptr;
+  t->facewise = on != 0;
+  if (t->facewise) {
+    t->gw = (double*)m->dalloc(pb);
+    if (!t->gw) return fail(PKH_ENOMEM, "tape allocation failed");
+  } else {
+    t->wbar = (double*)m->dalloc(2 * pb);
+    t->xlast = (double*)m->dalloc((size_t)m->nb() * m->g.n2 * m->g.n3 * 20 * sizeof(double));
+    if (!t->wbar || !t->xlast) return fail(PKH_ENOMEM, "tape allocation failed");
+  }
   return PKH_OK;
 }
 
@@ -1344,6 +1398,22 @@ int pkh_adjoint(pkh_mesh* m, pkh_tape* t, const double* lam_final, double* grad_
     if ((rc = tape_recompute(t, c0, len))) return rc;
     for (int q = len - 1; q >= 0; --q) {
       const double* dtp = t->d_dts + c0 + q;
+      if (t->facewise) {
+        {
+          KTimer kt(m, 4, false);
+          HIPCHK(launch_adj_stage_facewise(PKH_RECON_PLM, t->Us[q], lam, t->gw, m->d_blocks, nb, m->g, m->d_nbr,
+                                           m->maps, m->d_jf, m->njf, dtp, 1.0, lam_star, nullptr, nullptr,
+                                           m->d_time, m->stream));
+        }
+        {
+          KTimer kt(m, 4, false);
+          HIPCHK(launch_adj_stage_facewise(m->cfg.stage1_recon, t->S[q], lam_star, t->gw, m->d_blocks, nb, m->g,
+                                           m->d_nbr, m->maps, m->d_jf, m->njf, dtp, 0.5, lam_new, lam, lam_star,
+                                           m->d_time, m->stream));
+        }
+        std::swap(lam, lam_new);
+        continue;
+      }
       {  // corrector: lam* = (dU^{n+1}/dU*)^T lam
         KTimer kt(m, 4, false);
         HIPCHK(launch_adj_stage(PKH_RECON_PLM, t->Us[q], lam, t->wbar, t->xlast, m->d_blocks, nb, m->g, m->d_nbr,
@@ -1384,6 +1454,17 @@ struct pkh_batch {
   DevTime** d_tms = nullptr;        // per mesh clock
   hipGraphExec_t gexec = nullptr;
   int32_t g_cycles = 0;
+  // persistent launch: instance descriptors, progress counters, the items
+  // of one cycle, ticket counter and error word
+  bool p_ok = false;                // every mesh has blocks of 16 or 32 cells per row
+  PInst* d_pinst = nullptr;
+  PSync* d_psync = nullptr;
+  PItem* d_pitems = nullptr;
+  PCtl* d_pctl = nullptr;
+  int32_t npitems = 0;
+  int32_t pwaves = 2;               // waves per SIMD of the persistent kernel (2 or 3)
+  double wait_limit_s = 2.0;        // bound of every wait inside the persistent kernel
+  int32_t wall_khz = 0;             // device wall-clock rate
   bool attached = false;            // counted in every member's attached count
 };
 
@@ -1423,13 +1504,30 @@ int batch_build_items(pkh_batch* b) {
   return PKH_OK;
 }
 
+// The level-jump work of one stage of every multilevel mesh: flux
+// correction, then the ghost faces across level jumps and walls.
+int batch_level_jumps(pkh_batch* b, bool corrector) {
+  for (pkh_mesh* m : b->meshes) {
+    double* u = corrector ? m->A : m->B;
+    if (m->ncblocks)
+      HIPCHK(launch_flux_correct(u, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks, m->ncblocks, m->g,
+                                 m->d_time, corrector ? 1.0 : 0.5, corrector ? 1 : 0, m->d_fbuf, m->d_nbr,
+                                 b->stream));
+    if (m->njf) HIPCHK(launch_fill_faces(u, m->d_blocks, m->g, m->maps, m->d_time, m->d_jf, m->njf, b->stream));
+  }
+  return PKH_OK;
+}
+
 int batch_enqueue_cycle(pkh_batch* b, int mode_after) {
+  int rc;
   for (const auto& gr : b->groups)
     HIPCHK(launch_stage_group(b->meshes[gr.members[0]]->cfg.stage1_recon, gr.n1, gr.tj, b->d_pred, gr.d_items,
                               (int)gr.items.size(), b->stream));
+  if ((rc = batch_level_jumps(b, false))) return rc;
   for (const auto& gr : b->groups)
     HIPCHK(launch_stage_group(PKH_RECON_PLM, gr.n1, gr.tj, b->d_corr, gr.d_items, (int)gr.items.size(),
                               b->stream));
+  if ((rc = batch_level_jumps(b, true))) return rc;
   HIPCHK(launch_clock_group(b->d_tms, (int32_t)b->meshes.size(), mode_after, INFINITY, b->stream));
   return PKH_OK;
 }
@@ -1465,6 +1563,88 @@ int batch_fused(pkh_batch* b, int32_t n, bool graph) {
   }
   for (; c < n; ++c)
     if ((rc = batch_enqueue_cycle(b, CLOCK_END | CLOCK_BEGIN))) return rc;
+  return PKH_OK;
+}
+
+// Descriptors and items of the persistent launch (instances in decreasing
+// order of cells, so the longest ones start first in every phase).
+int batch_build_persistent(pkh_batch* b, const std::vector<StageLaunch>& pred,
+                           const std::vector<StageLaunch>& corr) {
+  pkh_mesh* m0 = b->meshes[0];
+  const int32_t n = (int32_t)b->meshes.size();
+  std::vector<PInst> pin(n);
+  std::vector<int32_t> order(n);
+  for (int32_t q = 0; q < n; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const pkh_mesh *a = b->meshes[x], *c = b->meshes[y];
+    return a->nb() * a->g.n1 * a->g.n2 * a->g.n3 > c->nb() * c->g.n1 * c->g.n2 * c->g.n3;
+  });
+  std::vector<PItem> per[PPHASES];
+  for (int32_t q : order) {
+    pkh_mesh* m = b->meshes[q];
+    PInst& pi = pin[q];
+    pi = PInst{};
+    pi.st[0] = pred[q];
+    pi.st[1] = corr[q];
+    pi.ff = m->d_ff;
+    pi.ff_first = m->d_ff_first;
+    pi.cblocks = m->d_cblocks;
+    pi.jf = m->d_jf;
+    pi.maps = m->maps;
+    pi.n1 = m->g.n1;
+    const int tj = persistent_tile_rows(m->g.n1);
+    for (int32_t blk = 0; blk < (int32_t)m->nb(); ++blk)
+      for (int32_t j0 = 0; j0 < m->g.n2; j0 += tj) {
+        per[0].push_back(PItem{q, 0, blk, j0});
+        per[3].push_back(PItem{q, 3, blk, j0});
+      }
+    pi.cnt[0] = pi.cnt[3] = (int32_t)(m->nb() * (m->g.n2 / tj));
+    const int nshell = 2 * m->g.n1 * m->g.n2 + (m->g.n3 - 2) * (2 * m->g.n1 + 2 * (m->g.n2 - 2));
+    const int nfc = (nshell + 255) / 256;
+    for (int32_t c = 0; c < m->ncblocks; ++c)
+      for (int32_t x = 0; x < nfc; ++x) {
+        per[1].push_back(PItem{q, 1, x, c});
+        per[4].push_back(PItem{q, 4, x, c});
+      }
+    pi.cnt[1] = pi.cnt[4] = m->ncblocks * nfc;
+    const int area = std::max(std::max(m->g.n1 * m->g.n2, m->g.n1 * m->g.n3), m->g.n2 * m->g.n3);
+    const int nff = (2 * area + 255) / 256;
+    for (int32_t f = 0; f < m->njf; ++f)
+      for (int32_t x = 0; x < nff; ++x) {
+        per[2].push_back(PItem{q, 2, x, f});
+        per[5].push_back(PItem{q, 5, x, f});
+      }
+    pi.cnt[2] = pi.cnt[5] = m->njf * nff;
+    pi.last = pi.cnt[5] ? 5 : (pi.cnt[4] ? 4 : 3);
+  }
+  std::vector<PItem> items;
+  for (auto& v : per) items.insert(items.end(), v.begin(), v.end());
+  b->npitems = (int32_t)items.size();
+  int rc;
+  if ((rc = upload_vec(m0, &b->d_pinst, pin)) || (rc = upload_vec(m0, &b->d_pitems, items))) return rc;
+  b->d_psync = (PSync*)m0->dalloc(n * sizeof(PSync));
+  b->d_pctl = (PCtl*)m0->dalloc(sizeof(PCtl));
+  if (!b->d_psync || !b->d_pctl) return fail(PKH_ENOMEM, "persistent batch allocation failed");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&b->wall_khz, hipDeviceAttributeWallClockRate, dev));
+  return PKH_OK;
+}
+
+// n cycles of every instance by persistent launches of up to 50 cycles each.
+int batch_persistent(pkh_batch* b, int32_t n) {
+  if (!b->p_ok) return fail(PKH_EINVAL, "the persistent launch takes blocks of 16 or 32 cells per row only");
+  int rc;
+  if ((rc = batch_prepare(b))) return rc;
+  const int grid = (int)std::min<int64_t>(persistent_grid(b->pwaves), (int64_t)b->npitems * std::min(n, 50));
+  if (grid < 1) return fail(PKH_EHIP, "persistent kernel occupancy query failed");
+  const long long ticks = (long long)(b->wait_limit_s * 1e3 * (double)b->wall_khz);
+  HIPCHK(launch_clock_group(b->d_tms, (int32_t)b->meshes.size(), CLOCK_BEGIN, INFINITY, b->stream));
+  for (int c = 0; c < n; c += 50) {
+    const int K = std::min(50, n - c);
+    HIPCHK(launch_persistent(b->d_pinst, (int32_t)b->meshes.size(), b->d_psync, b->d_pitems, b->npitems, K,
+                             b->d_pctl, b->pwaves, grid, ticks, b->stream));
+  }
   return PKH_OK;
 }
 
@@ -1504,21 +1684,34 @@ const int kTileChoices[] = {4, 8, 16, 2};
 
 extern "C" {
 
-int pkh_batch_create(pkh_mesh* const* meshes, int32_t n, pkh_batch** out) {
+int pkh_batch_create(pkh_mesh* const* meshes, int32_t n, const pkh_tuning* tuning, pkh_batch** out) {
   if (!meshes || n < 1 || !out) return fail(PKH_EINVAL, "bad argument");
   *out = nullptr;
+  for (int32_t q = 0; q < n; ++q)
+    for (int32_t r = 0; r < q; ++r)
+      if (meshes[q] == meshes[r]) return fail(PKH_EINVAL, "a mesh appears twice in the batch");
   pkh_batch* b = new pkh_batch();
   b->meshes.assign(meshes, meshes + n);
-  b->stream = meshes[0]->stream;
+  b->stream = meshes[0] ? meshes[0]->stream : nullptr;
+  b->p_ok = true;
   for (pkh_mesh* m : b->meshes) {
     if (!m || m->stream != b->stream) {
       delete b;
       return fail(PKH_EINVAL, "batched meshes must share one stream");
     }
-    if (m->need_fill || m->ncblocks || m->fp32) {
+    if (m->fp32 || m->nparts > 1) {
       delete b;
-      return fail(PKH_EINVAL, "batches hold single-level periodic FP64 meshes");
+      return fail(PKH_EINVAL, "batches hold FP64-stored meshes without a partition");
     }
+    if (tuning && tuning->tile_rows) {
+      if (stage_tile_rows(m->g.n1, m->g.n2, tuning->tile_rows) != tuning->tile_rows) {
+        delete b;
+        return fail(PKH_EINVAL, "tile_rows %d not available for blocks of %d x %d", tuning->tile_rows, m->g.n1,
+                    m->g.n2);
+      }
+      m->tj = tuning->tile_rows;
+    }
+    b->p_ok &= persistent_tile_rows(m->g.n1) > 0 && m->g.n2 % persistent_tile_rows(m->g.n1) == 0;
   }
   std::vector<StageLaunch> pred(n), corr(n);
   std::vector<DevTime*> tms(n);
@@ -1568,7 +1761,8 @@ int pkh_batch_create(pkh_mesh* const* meshes, int32_t n, pkh_batch** out) {
   pkh_mesh* m0 = b->meshes[0];
   int rc;
   if ((rc = upload_vec(m0, &b->d_pred, pred)) || (rc = upload_vec(m0, &b->d_corr, corr)) ||
-      (rc = upload_vec(m0, &b->d_tms, tms)) || (rc = batch_build_items(b))) {
+      (rc = upload_vec(m0, &b->d_tms, tms)) || (rc = batch_build_items(b)) ||
+      (b->p_ok && (rc = batch_build_persistent(b, pred, corr)))) {
     pkh_batch_destroy(b);
     return rc;
   }
@@ -1587,6 +1781,10 @@ int pkh_batch_destroy(pkh_batch* b) {
   m0->dfree(b->d_pred);
   m0->dfree(b->d_corr);
   m0->dfree(b->d_tms);
+  m0->dfree(b->d_pinst);
+  m0->dfree(b->d_psync);
+  m0->dfree(b->d_pitems);
+  m0->dfree(b->d_pctl);
   if (b->attached)
     for (pkh_mesh* m : b->meshes) m->attached--;
   delete b;
@@ -1594,7 +1792,7 @@ int pkh_batch_destroy(pkh_batch* b) {
 }
 
 int pkh_batch_step(pkh_batch* b, int32_t n, uint32_t mode) {
-  if (!b || n < 0 || mode > PKH_GRAPH) return fail(PKH_EINVAL, "bad argument");
+  if (!b || n < 0 || mode > PKH_PERSISTENT) return fail(PKH_EINVAL, "bad argument");
   if (n == 0) return PKH_OK;
   if (mode == PKH_PLAIN) {
     int rc;
@@ -1603,7 +1801,27 @@ int pkh_batch_step(pkh_batch* b, int32_t n, uint32_t mode) {
         if ((rc = pkh_step(m, 1, INFINITY))) return rc;
     return PKH_OK;
   }
+  if (mode == PKH_PERSISTENT) return batch_persistent(b, n);
   return batch_fused(b, n, mode == PKH_GRAPH);
+}
+
+int pkh_batch_set_tuning(pkh_batch* b, const pkh_batch_tuning* t) {
+  if (!b || !t) return fail(PKH_EINVAL, "null argument");
+  if (t->waves_per_simd != 0 && t->waves_per_simd != 2 && t->waves_per_simd != 3)
+    return fail(PKH_EINVAL, "waves_per_simd must be 0, 2 or 3");
+  if (!(t->wait_limit_s >= 0.0) || t->wait_limit_s > 3600.0)
+    return fail(PKH_EINVAL, "wait_limit_s must be in [0, 3600]");
+  b->pwaves = t->waves_per_simd ? t->waves_per_simd : 2;
+  b->wait_limit_s = t->wait_limit_s > 0.0 ? t->wait_limit_s : 0.0;
+  return PKH_OK;
+}
+
+int pkh_batch_get_tuning(const pkh_batch* b, pkh_batch_tuning* t) {
+  if (!b || !t) return fail(PKH_EINVAL, "null argument");
+  *t = pkh_batch_tuning{};
+  t->waves_per_simd = b->pwaves;
+  t->wait_limit_s = b->wait_limit_s;
+  return PKH_OK;
 }
 
 int pkh_batch_autotune(pkh_batch* b, int32_t trial_cycles, int32_t* tile_rows) {
@@ -1638,6 +1856,25 @@ int pkh_batch_autotune(pkh_batch* b, int32_t trial_cycles, int32_t* tile_rows) {
       }
     }
     gr.tj = best;
+  }
+  if (b->p_ok) {  // waves per SIMD of the persistent kernel
+    int best = b->pwaves;
+    float best_ms = 1e30f;
+    for (int w : {2, 3}) {
+      b->pwaves = w;
+      if ((rc = batch_persistent(b, 1))) return rc;  // warm-up
+      HIPCHK(hipEventRecord(e0, b->stream));
+      if ((rc = batch_persistent(b, trial_cycles))) return rc;
+      HIPCHK(hipEventRecord(e1, b->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = w;
+      }
+    }
+    b->pwaves = best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "pkh_amr.h"
 #include "pkh_device.h"
 
 // Launch options: the corrector prefetches the next plane's inputs and the
@@ -46,6 +47,10 @@
 #ifndef PKH_PRED_PFD
 #define PKH_PRED_PFD 1
 #endif
+// one barrier per plane (double-buffered LDS) where it fits
+#ifndef PKH_SINGLE_BARRIER
+#define PKH_SINGLE_BARRIER 1
+#endif
 
 namespace pkh {
 
@@ -68,17 +73,49 @@ namespace pkh {
 // rounded once when stored; the CFL reduction sees the stored value).
 // ---------------------------------------------------------------------------
 
-// One tile (TJ rows of block blk starting at row j0) of a stage; rot
-// rotates which wave takes the tile's remainder faces.
-template <int RECON, int N1, int TJ, typename S = double>
-__device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0, int rot) {
+// LDS doubles one tile of a stage uses: the staged plane (NQ values per
+// cell of (TJ+4) x (N1+4)), the x and y face fluxes (each twice with one
+// barrier per plane, SB), one slot per wave.
+template <int RECON, int N1, int TJ, bool SB = false>
+constexpr int stage_lds_doubles() {
+  return (SB ? 2 : 1) * ((RECON ? 5 : 8) * (TJ + 2 * NG) * (N1 + 2 * NG) + NV * TJ * (N1 + 1) +
+                         NV * (TJ + 1) * N1) +
+         (N1 * TJ + 63) / 64;
+}
+
+// One barrier per plane (double-buffered plane and fluxes) where the
+// doubled LDS still lets the workgroups that make two waves per SIMD (eight
+// per CU) share a CU's 160 KB.
+template <int RECON, int N1, int TJ>
+constexpr bool stage_single_barrier() {
+#if PKH_SINGLE_BARRIER
+  constexpr int wg_waves = N1 * TJ / 64;
+  constexpr int wgs = wg_waves >= 8 ? 1 : 8 / wg_waves;
+  return stage_lds_doubles<RECON, N1, TJ, true>() * 8 * wgs <= 160 * 1024 - 1024;
+#else
+  return false;
+#endif
+}
+
+// One tile (TJ rows of block blk starting at row j0) of a stage with
+// timestep dt, in LDS at lds (stage_lds_doubles<..., SB> doubles); rot
+// rotates which wave takes the tile's remainder faces. SB: the staged plane
+// and the face fluxes are double-buffered, so each plane needs one barrier:
+// the x/y divergence of plane p-1 is formed after the barrier that follows
+// the staging of plane p, and the faces of plane p are solved into the
+// other flux buffer without waiting for the slowest wave.
+template <int RECON, int N1, int TJ, typename S = double, bool SB = false>
+__device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0, int rot, double dt,
+                                           double* __restrict__ lds) {
   constexpr int NT = N1 * TJ;
   constexpr int P1 = N1 + 2 * NG;
   constexpr int RW = TJ + 2 * NG;
   constexpr int PLANE = RW * P1;
-  // halo cells the faces read: rows -2, -1, TJ, TJ+1 over the active
-  // columns, and the two cells beyond each end of the interior rows
-  constexpr int NHALO = 4 * N1 + 4 * TJ;
+  // halo cells the faces read: HW rows below and above the tile over the
+  // active columns, and HW cells beyond each end of the interior rows (HW =
+  // 2 for the piecewise-linear faces, 1 for donor cell)
+  constexpr int HW = RECON ? 2 : 1;
+  constexpr int NHALO = 2 * HW * N1 + 2 * HW * TJ;
   constexpr int NX = TJ * (N1 + 1);
   constexpr int NY = (TJ + 1) * N1;
   constexpr int LAG = RECON ? 1 : 0;  // z face m is computed at plane m + LAG
@@ -92,10 +129,21 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   constexpr int PFD = PF ? (RECON ? PKH_CORR_PFD : PKH_PRED_PFD) : 1;  // planes in flight
   static_assert(NT % 64 == 0, "whole waves");
 
-  __shared__ double sQ[NQ][PLANE];
-  __shared__ double sFx[NV][NX];
-  __shared__ double sFy[NV][NY];
-  __shared__ double sRed[NWAVE];
+  constexpr int NBUF = SB ? 2 : 1;
+  constexpr int BUF = NQ * PLANE + NV * NX + NV * NY;  // one plane's staging and fluxes
+  static_assert(stage_lds_doubles<RECON, N1, TJ, SB>() == NBUF * BUF + NWAVE, "LDS layout");
+  double* __restrict__ sRed = lds + NBUF * BUF;
+  // the buffers of plane p: the parity of p with SB (p >= -3), else one
+  auto Qb = [&](int p) { return reinterpret_cast<double(*)[PLANE]>(lds + (SB ? ((p + 4) & 1) * BUF : 0)); };
+  auto FXb = [&](int p) {
+    return reinterpret_cast<double(*)[NX]>(lds + (SB ? ((p + 4) & 1) * BUF : 0) + NQ * PLANE);
+  };
+  auto FYb = [&](int p) {
+    return reinterpret_cast<double(*)[NY]>(lds + (SB ? ((p + 4) & 1) * BUF : 0) + NQ * PLANE + NV * NX);
+  };
+  double(*sQ)[PLANE] = Qb(0);
+  double(*sFx)[NX] = FXb(0);
+  double(*sFy)[NY] = FYb(0);
 
   const Geom& g = a.g;
   const int tid = threadIdx.x;
@@ -105,7 +153,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   const double gam = g.gamma;
   const double gm1 = gam - 1.0;
   const double igm1 = 1.0 / gm1;
-  const double coef = a.beta * a.tm->dt;
+  const double coef = a.beta * dt;
   const int64_t vs = g.vstride;
   const S* __restrict__ in = static_cast<const S*>(a.uin) + (int64_t)blk * g.bstride;
   const S* base = static_cast<const S*>(a.ubase) + (int64_t)blk * g.bstride;
@@ -229,25 +277,25 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     }
   };
 
-  // halo cell h of the plane (rows -2,-1 and TJ,TJ+1 of the tile over the
-  // active columns, then the two cells at each end of the interior rows) ->
-  // its LDS slot
+  // halo cell h of the plane (rows -HW..-1 and TJ..TJ+HW-1 of the tile
+  // over the active columns, then the HW cells at each end of the interior
+  // rows) -> its LDS slot
   auto hcell = [&](int h) {
-    if (h < 4 * N1) {
-      const int r = h / N1, i = h - r * N1;
-      return (r < 2 ? r : TJ + r) * P1 + NG + i;
+    if (h < 2 * HW * N1) {
+      const int r = h / N1, i = h - r * N1;  // r < HW: row r - HW, else row TJ + r - HW
+      return (r < HW ? r + NG - HW : TJ + NG + r - HW) * P1 + NG + i;
     }
-    const int hh = h - 4 * N1, r = hh >> 2, s4 = hh & 3;
-    return (r + NG) * P1 + (s4 < 2 ? s4 : P1 - 4 + s4);
+    const int hh = h - 2 * HW * N1, r = hh / (2 * HW), sc = hh - r * 2 * HW;
+    return (r + NG) * P1 + (sc < HW ? sc + NG - HW : N1 + NG + sc - HW);
   };
   // offset from this block's cell to the one halo cell h is read from. The
   // offsets are captured by value so the per-lane choice is a select: taken
   // by reference, they live in scratch memory and every halo load waits for
   // a pointer load first.
   auto hshift = [dxl, dxr, dyl, dyh](int h) -> int64_t {
-    const int64_t sy = h < 2 * N1 ? dyl : dyh;
-    const int64_t sx = ((h - 4 * N1) & 3) < 2 ? dxl : dxr;
-    return h < 4 * N1 ? sy : sx;
+    const int64_t sy = h < HW * N1 ? dyl : dyh;
+    const int64_t sx = ((h - 2 * HW * N1) % (2 * HW)) < HW ? dxl : dxr;
+    return h < 2 * HW * N1 ? sy : sx;
   };
   constexpr int HMAX = PF ? (NHALO + NT - 1) / NT : 1;
   // this lane's halo cells: LDS slot, and offset of the cell read (slot plus
@@ -317,6 +365,11 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   for (int sl = 0; sl < PFD; ++sl) {
     const int p = pb + sl;
     if (p >= p_end) break;  // plane count not a multiple of PFD (uniform)
+    if constexpr (SB) {
+      sQ = Qb(p);
+      sFx = FXb(p - 1);
+      sFy = FYb(p - 1);
+    }
     // --- stage plane p (rows j0-2 .. j0+TJ+1): own cell first, then halo.
     // The predictor takes plane p from registers loaded while plane p-1 was
     // being computed and starts the loads of plane p+1 right away.
@@ -377,6 +430,23 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       }
     }
     __syncthreads();
+
+    if constexpr (SB) {
+      // x/y divergence of plane p - 1 (its fluxes are in the other buffer,
+      // complete since every wave passed the barrier above)
+#pragma unroll
+      for (int s = 0; s < QN - 1; ++s)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
+      if (p - 1 >= 0 && p - 1 < n3) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          dq[QN - 1][v] = (sFx[v][tj * (N1 + 1) + ti + 1] - sFx[v][tj * (N1 + 1) + ti]) * bi.idx[0] +
+                          (sFy[v][(tj + 1) * N1 + ti] - sFy[v][tj * N1 + ti]) * bi.idx[1];
+      }
+      sFx = FXb(p);
+      sFy = FYb(p);
+    }
 
     // --- z face m between cells m-1 and m, then finish cell m-1
     const int m = p - LAG;
@@ -476,26 +546,32 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
                    xf ? bi.fslot[XHI] : (j0 + TJ == n2 ? bi.fslot[YHI] : -1),
                    xf ? (int64_t)p * n2 + j0 + q : (int64_t)p * N1 + iy);
       }
-      __syncthreads();
+      if constexpr (!SB) {
+        __syncthreads();
 #pragma unroll
-      for (int s = 0; s < QN - 1; ++s)
+        for (int s = 0; s < QN - 1; ++s)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
+          for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        dq[QN - 1][v] = (sFx[v][tj * (N1 + 1) + ti + 1] - sFx[v][tj * (N1 + 1) + ti]) * bi.idx[0] +
-                        (sFy[v][(tj + 1) * N1 + ti] - sFy[v][tj * N1 + ti]) * bi.idx[1];
-    } else {
+        for (int v = 0; v < NV; ++v)
+          dq[QN - 1][v] = (sFx[v][tj * (N1 + 1) + ti + 1] - sFx[v][tj * (N1 + 1) + ti]) * bi.idx[0] +
+                          (sFy[v][(tj + 1) * N1 + ti] - sFy[v][tj * N1 + ti]) * bi.idx[1];
+      }
+    } else if constexpr (!SB) {
       // keep the queue aligned with plane numbers on the leading planes
 #pragma unroll
       for (int s = 0; s < QN - 1; ++s)
 #pragma unroll
         for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
     }
-    // no barrier here: the next plane's staging only overwrites the LDS
-    // plane, whose last readers (this plane's x/y faces) finished before the
-    // barrier above, and the next plane's fluxes are written after its first
-    // barrier, which every wave reaches after this divergence
+    // no barrier here. Without SB: the next plane's staging only
+    // overwrites the LDS plane, whose last readers (this plane's x/y faces)
+    // finished before the barrier above, and the next plane's fluxes are
+    // written after its first barrier, which every wave reaches after this
+    // divergence. With SB: the next plane is staged into the other buffer,
+    // last read by the faces of plane p - 1, which every wave finished before
+    // this plane's barrier; this plane's fluxes are read after the next
+    // plane's barrier and overwritten only after the one after it.
   }
 
   if (a.do_dt) {
@@ -526,7 +602,9 @@ __global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAV
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   const int blk = wg / ntj;
   if (blk >= a.nblocks) return;
-  stage_tile<RECON, N1, TJ>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg);
+  constexpr bool SB = stage_single_barrier<RECON, N1, TJ>();
+  __shared__ double lds[stage_lds_doubles<RECON, N1, TJ, SB>()];
+  stage_tile<RECON, N1, TJ, double, SB>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg, a.tm->dt, lds);
 }
 
 // The same over a state stored in FP32.
@@ -536,7 +614,8 @@ __global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAV
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   const int blk = wg / ntj;
   if (blk >= a.nblocks) return;
-  stage_tile<RECON, N1, TJ, float>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg);
+  __shared__ double lds[stage_lds_doubles<RECON, N1, TJ>()];
+  stage_tile<RECON, N1, TJ, float>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg, a.tm->dt, lds);
 }
 
 // Grouped launch: the tiles of many independent meshes (same block width
@@ -547,8 +626,148 @@ __global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAV
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   if (wg >= nitems) return;
   const GroupItem it = items[wg];
-  stage_tile<RECON, N1, TJ>(insts[it.inst], it.blk, it.j0, wg);
+  constexpr bool SB = stage_single_barrier<RECON, N1, TJ>();
+  __shared__ double lds[stage_lds_doubles<RECON, N1, TJ, SB>()];
+  const StageLaunch& a = insts[it.inst];
+  stage_tile<RECON, N1, TJ, double, SB>(a, it.blk, it.j0, wg, a.tm->dt, lds);
 }
+
+// ---------------------------------------------------------------------------
+// Persistent batch kernel. Workgroups take item tickets in order; ticket t
+// is item t % nper of cycle t / nper, the items of a cycle ordered by phase,
+// then instance. An item waits (thread 0, bounded) for the previous phase
+// of its instance in the same cycle, or for the instance's clock to reach
+// the cycle, i.e. only for items of smaller tickets, which are held by
+// running workgroups: no deadlock whatever the grid. Visibility across
+// XCDs: every thread releases its stores at device scope before thread 0
+// counts the item done; thread 0 acquires at device scope after its wait.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned int ld_acq(const unsigned int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *p >= target; false when ctl->err is set or wait_ticks of the
+// device wall clock pass first.
+__device__ bool persistent_wait(const unsigned int* p, unsigned int target, const int* err, long long wait_ticks) {
+  if (ld_acq(p) >= target) return true;
+  const long long t0 = (long long)wall_clock64();
+  for (;;) {
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if ((long long)wall_clock64() - t0 > wait_ticks) return false;
+    __builtin_amdgcn_s_sleep(4);
+    if (ld_acq(p) >= target) return true;
+  }
+}
+
+// Close a cycle of one instance and open the next (the batched clock with
+// no end time): dt_next = CFL / max signal speed, t += dt, cycle + 1,
+// dt = dt_next, reduction reset. Fields are read and written with device
+// scope atomics so no stale cached copy is used on any XCD.
+__device__ void persistent_clock(DevTime* tm) {
+  const unsigned long long sb = __hip_atomic_load(&tm->smax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double cfl = __hip_atomic_load(&tm->cfl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double t = __hip_atomic_load(&tm->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double dt = __hip_atomic_load(&tm->dt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const long long cyc = __hip_atomic_load(&tm->cycle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double dt_next = cfl / __longlong_as_double((long long)sb);
+  __hip_atomic_store(&tm->dt_next, dt_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&tm->t, t + dt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&tm->cycle, cyc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&tm->dt, dt_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&tm->smax_bits, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int persistent_lds_doubles() {
+  return std::max(std::max(stage_lds_doubles<0, 16, 16>(), stage_lds_doubles<1, 16, 16>()),
+                  std::max(stage_lds_doubles<0, 32, 8>(), stage_lds_doubles<1, 32, 8>()));
+}
+
+template <int W>
+__global__ void __launch_bounds__(256, W)
+    persistent_kernel(const PInst* __restrict__ insts, int ninst, PSync* sync, const PItem* __restrict__ items,
+                      int nper, int ncycles, PCtl* ctl, long long wait_ticks) {
+  __shared__ double lds[persistent_lds_doubles()];
+  __shared__ double s_red[4];
+  __shared__ unsigned int s_ticket;
+  __shared__ double s_dt;
+  __shared__ int s_ok;
+  const int tid = threadIdx.x;
+  const unsigned int total = (unsigned int)nper * (unsigned int)ncycles;
+  for (;;) {
+    if (tid == 0) s_ticket = atomicAdd(&ctl->ticket, 1u);
+    __syncthreads();
+    const unsigned int tk = s_ticket;
+    if (tk >= total) break;  // uniform: every wave of the workgroup leaves
+    const unsigned int c = tk / (unsigned int)nper;
+    const PItem it = items[tk - c * (unsigned int)nper];
+    const PInst& in = insts[it.inst];
+    PSync* ps = sync + it.inst;
+    if (tid == 0) {
+      int prev = it.phase - 1;
+      while (prev >= 0 && in.cnt[prev] == 0) --prev;
+      const bool ok = prev < 0 ? persistent_wait(&ps->clock, c, &ctl->err, wait_ticks)
+                               : persistent_wait(&ps->done[prev], (c + 1) * (unsigned int)in.cnt[prev], &ctl->err,
+                                                 wait_ticks);
+      if (!ok && atomicCAS(&ctl->err, 0, 1) == 0) {
+        // the first to give up marks every instance's state invalid
+        for (int q = 0; q < ninst; ++q) atomicOr(&insts[q].st[0].tm->err, 4);
+      }
+      __threadfence();  // acquire: the awaited items' stores are visible
+      s_ok = ok;
+      s_dt = __hip_atomic_load(&in.st[0].tm->dt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (s_ok) {
+      const double dt = s_dt;
+      const int ph = it.phase;
+      if (ph == 0 || ph == 3) {
+        const StageLaunch& a = in.st[ph == 3];
+        if (in.n1 == 32) {
+          if (a.recon)
+            stage_tile<1, 32, 8>(a, it.a, it.b, (int)tk, dt, lds);
+          else
+            stage_tile<0, 32, 8>(a, it.a, it.b, (int)tk, dt, lds);
+        } else {
+          if (a.recon)
+            stage_tile<1, 16, 16>(a, it.a, it.b, (int)tk, dt, lds);
+          else
+            stage_tile<0, 16, 16>(a, it.a, it.b, (int)tk, dt, lds);
+        }
+      } else if (ph == 1 || ph == 4) {
+        const StageLaunch& a = in.st[ph == 4];
+        double* u = static_cast<double*>(a.uout);
+        flux_correct_item(u, a.blocks, in.ff, in.ff_first, in.cblocks, a.g, a.tm, dt, a.beta, ph == 4, a.fbuf,
+                          it.a, it.b, s_red);
+      } else {
+        const StageLaunch& a = in.st[ph == 5];
+        fill_faces_item(static_cast<double*>(a.uout), a.blocks, a.g, in.maps, a.tm, in.jf, it.a, it.b);
+      }
+      // release: every thread's stores reach device scope before the item
+      // is counted
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) {
+        const unsigned int old = atomicAdd(&ps->done[ph], 1u);
+        if (ph == in.last && old + 1 == (c + 1) * (unsigned int)in.cnt[ph]) {
+          __threadfence();
+          persistent_clock(in.st[0].tm);
+          __threadfence();
+          __hip_atomic_store(&ps->clock, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    __syncthreads();  // s_ticket, s_ok and s_dt are rewritten next round
+  }
+}
+
+__global__ void persistent_reset_kernel(PSync* sync, int ninst, PCtl* ctl) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < ninst) sync[q] = PSync{};
+  if (q == 0) *ctl = PCtl{};
+}
+
+// ---- host-side launchers: everything below runs on the host ----
 
 template <int RECON, int N1, int TJ>
 static hipError_t launch_group_t(const StageLaunch* insts, const GroupItem* items, int nitems,
@@ -643,6 +862,33 @@ hipError_t launch_stage(const StageLaunch& a, hipStream_t s) {
     default:
       return hipErrorInvalidValue;
   }
+}
+
+
+int persistent_grid(int waves) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -1;
+  hipError_t e = waves == 3
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<3>, 256, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_kernel<2>, 256, 0);
+  if (e != hipSuccess || per < 1) return -1;
+  return per * ncu;
+}
+
+hipError_t launch_persistent(const PInst* insts, int32_t ninst, PSync* sync, const PItem* items, int32_t nper,
+                             int32_t ncycles, PCtl* ctl, int waves, int grid, long long wait_ticks,
+                             hipStream_t s) {
+  if (ninst < 1 || nper < 1 || ncycles < 1 || grid < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(persistent_reset_kernel, dim3((ninst + 255) / 256), dim3(256), 0, s, sync, (int)ninst, ctl);
+  if (waves == 3)
+    hipLaunchKernelGGL(persistent_kernel<3>, dim3(grid), dim3(256), 0, s, insts, (int)ninst, sync, items,
+                       (int)nper, (int)ncycles, ctl, wait_ticks);
+  else
+    hipLaunchKernelGGL(persistent_kernel<2>, dim3(grid), dim3(256), 0, s, insts, (int)ninst, sync, items,
+                       (int)nper, (int)ncycles, ctl, wait_ticks);
+  return hipGetLastError();
 }
 
 }  // namespace pkh

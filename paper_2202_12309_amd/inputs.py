@@ -275,11 +275,45 @@ def _scatter(fields, leaves, n):
     return U
 
 
+def generic_flow(leaves, n, nrb, seed=3, gamma=5.0 / 3.0, xmin=(0, 0, 0), xmax=(1, 1, 1)):
+    """A smooth flow without symmetries, on leaves of any level: each of rho,
+    v_x, v_y, v_z, P is a sum of 4 plane waves with seeded integer wave
+    vectors (components in -2..2) and phases, so no field is constant along
+    any direction and no two neighbouring differences are equal by
+    construction (no exact ties in the limiter or wave-speed choices).
+    rho = 1 + 0.3 f_0, v = 0.3 f_1..3, P = 1 + 0.2 f_4 with |f| <= 1."""
+    rng = np.random.default_rng(seed)
+    modes = [(rng.integers(-2, 3, size=(4, 3)), rng.uniform(0.0, 2.0 * np.pi, size=4)) for _ in range(5)]
+    U = np.empty((len(leaves), 5, n[2], n[1], n[0]))
+    for b, lf in enumerate(leaves):
+        x, y, z = cell_centers(lf, n, nrb, xmin, xmax)
+        f = []
+        for ks, ph in modes:
+            acc = np.zeros_like(x)
+            for k, p in zip(ks, ph):
+                acc += np.sin(2.0 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + p)
+            f.append(acc / 4.0)
+        U[b] = _to_conserved(1.0 + 0.3 * f[0], 0.3 * f[1], 0.3 * f[2], 0.3 * f[3], 1.0 + 0.2 * f[4], gamma)
+    return U
+
+
 def turbulent_box(leaves, n, nrb, seed=2, gamma=5.0 / 3.0, sigma_ln=0.5, mach=0.5, p0=1.0):
     """Log-normal density rho = exp(sigma g - sigma^2/2) from a smoothed
     unit-variance field g, uniform pressure p0, and a velocity of three
     independent smoothed fields scaled to rms |v| = mach * sqrt(gamma p0)."""
     N = (nrb[0] * n[0], nrb[1] * n[1], nrb[2] * n[2])
+    return scatter_global(turbulent_box_global(N, seed, gamma, sigma_ln, mach, p0), leaves, n)
+
+
+def scatter_global(fields, leaves, n):
+    """Level-0 leaves' blocks [nleaves][5][n3][n2][n1] cut from global
+    conserved fields [5][N3][N2][N1]."""
+    return _scatter(fields, leaves, n)
+
+
+def turbulent_box_global(N, seed=2, gamma=5.0 / 3.0, sigma_ln=0.5, mach=0.5, p0=1.0):
+    """The turbulent_box fields on the whole N[0] x N[1] x N[2] grid,
+    [5][N3][N2][N1] (independent of any block decomposition)."""
     g = _smoothed_field(N, seed, 0)
     rho = np.exp(sigma_ln * g - 0.5 * sigma_ln * sigma_ln)
     del g
@@ -287,7 +321,7 @@ def turbulent_box(leaves, n, nrb, seed=2, gamma=5.0 / 3.0, sigma_ln=0.5, mach=0.
     vel = [scale * _smoothed_field(N, seed, 1 + d) for d in range(3)]
     fields = _to_conserved(rho, vel[0], vel[1], vel[2], p0 * np.ones_like(rho), gamma)
     del vel, rho
-    return _scatter(fields, leaves, n)
+    return fields
 
 
 def blast(leaves, n, nrb, p_in=100.0, p_out=0.1, r=0.1, rho0=1.0, center=(0.5, 0.5, 0.5),

@@ -57,6 +57,14 @@ def rel_err(a, b, gamma):
     return d / scales(b, gamma)
 
 
+def rel_err_per_variable(a, b):
+    """The plain per-variable reading: max |a - b| over cells divided by max
+    |b| of the same variable (for a fluid near rest the momentum scale is
+    then the flow's own tiny momentum, not the momentum-flux scale)."""
+    d = np.abs(a - b).reshape(a.shape[0], 5, -1).max(axis=(0, 2))
+    return d / np.abs(b).reshape(b.shape[0], 5, -1).max(axis=(0, 2))
+
+
 def print_case(msg):
     print(f"[case] {msg}", flush=True)
 

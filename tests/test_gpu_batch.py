@@ -1,7 +1,9 @@
 """Batched instances: every instance of the plain per-mesh path, the grouped
-(fused) launches and the captured-graph replays against the oracle element
-by element; the three modes bitwise identical; autotuning leaves states and
-clocks untouched. Runs on an MI355X."""
+(fused) launches, the captured-graph replays and the persistent launch
+against the oracle element by element, on single-level mixes and on a mix
+with multilevel and walled members; the four modes bitwise identical; the
+persistent launch's bounded waits report an error instead of hanging;
+autotuning leaves states and clocks untouched. Runs on an MI355X."""
 import numpy as np
 import pytest
 
@@ -25,7 +27,7 @@ def _make(specs, stream):
     return meshes
 
 
-@pytest.mark.parametrize("mode", ["plain", "fused", "graph"])
+@pytest.mark.parametrize("mode", ["plain", "fused", "graph", "persistent"])
 def test_batch_instances_match_oracle(mode):
     """Six instances of the seeded mix (edges 32-64, blocks of 16^3 and 32^3,
     sound waves and blasts, each with its own timestep): after 1 cycle each
@@ -61,14 +63,14 @@ def test_batch_instances_match_oracle(mode):
     b.close()
 
 
-def test_fused_and_graph_equal_plain_bitwise():
-    print_case("batch plain vs fused vs graph")
+def test_fused_graph_persistent_equal_plain_bitwise():
+    print_case("batch plain vs fused vs graph vs persistent")
     import torch
     from paper_2202_12309_amd.binding import Batch
     specs = inputs.batch_mix(n=6, seed=11, sizes=(32, 48, 64))
     specs[0]["blk"] = 16
     results = {}
-    for mode in ("plain", "fused", "graph"):
+    for mode in ("plain", "fused", "graph", "persistent"):
         stream = torch.cuda.Stream()
         meshes = _make(specs, stream)
         b = Batch(meshes)
@@ -76,7 +78,7 @@ def test_fused_and_graph_equal_plain_bitwise():
         b.step(4, mode)
         results[mode] = [(m.download(), m.time()) for m in meshes]
         b.close()
-    for mode in ("fused", "graph"):
+    for mode in ("fused", "graph", "persistent"):
         for (Ua, ta), (Ub, tb) in zip(results["plain"], results[mode]):
             assert np.array_equal(Ua, Ub), mode
             assert ta == tb, mode
@@ -111,6 +113,7 @@ def test_autotune_keeps_state():
     before = [(m.download(), m.time()) for m in meshes]
     tiles = b.autotune(2)
     assert all(t in (2, 4, 8, 16) for t in tiles)
+    assert b.tuning()["waves_per_simd"] in (2, 3)
     for m, (U, t) in zip(meshes, before):
         assert np.array_equal(m.download(), U)
         assert m.time() == t
@@ -135,3 +138,104 @@ def test_single_mesh_autotune():
     t = m.autotune(2)
     assert t["tile_rows"] in (4, 8, 16)
     assert np.array_equal(m.download(), U0)
+
+
+def _mixed_members(stream):
+    """A two-level blast (64^3 root in 16^3 blocks), a uniform sound wave in
+    one 32^3 block, and a smooth flow between outflow and reflecting walls
+    (32^3 in 16^3 blocks) -- with their oracle twins."""
+    from oracle.oracle import BC_OUTFLOW as OUT, BC_PERIODIC as PER, BC_REFLECT as REF
+    from paper_2202_12309_amd.binding import Mesh
+    out = []
+    nrb, n = (4, 4, 4), (16, 16, 16)
+    lv = inputs.sphere_refined_leaves(nrb, radius=0.3)
+    gm = Mesh((64,) * 3, n, lv, max_level=1, stream=stream)
+    om = OracleMesh(n, nrb, gm.leaves(), max_level=1)
+    out.append((gm, om, inputs.blast(gm.leaves(), n, nrb)))
+    nrb, n = (1, 1, 1), (32, 32, 32)
+    gm = Mesh((32,) * 3, n, inputs.uniform_leaves(nrb), stream=stream)
+    om = OracleMesh(n, nrb, gm.leaves())
+    out.append((gm, om, inputs.sound_wave(gm.leaves(), n, nrb, amp=1e-3, noise=1e-5)))
+    nrb, n = (2, 2, 2), (16, 16, 16)
+    bc = (REF, OUT, PER, PER, OUT, REF)
+    gm = Mesh((32,) * 3, n, inputs.uniform_leaves(nrb), stream=stream, bc=bc)
+    om = OracleMesh(n, nrb, gm.leaves(), bc=bc)
+    out.append((gm, om, inputs.smooth_flow(gm.leaves(), n, nrb)))
+    for gm, om, U0 in out:
+        gm.upload(U0)
+        om.set_state(U0)
+    return out
+
+
+@pytest.mark.parametrize("mode", ["plain", "fused", "graph", "persistent"])
+def test_multilevel_and_walled_members_match_oracle(mode):
+    """A batch holding a two-level mesh (flux correction and level-jump
+    fills between the stages), a one-block mesh and a walled mesh: every
+    member within 1e-12 of the oracle after 1 cycle and 1e-11 after 6, and
+    bitwise equal to the plain path."""
+    print_case(f"batch with multilevel and walled members vs oracle, mode {mode}")
+    import torch
+    from paper_2202_12309_amd.binding import Batch
+    stream = torch.cuda.Stream()
+    mem = _mixed_members(stream)
+    b = Batch([m for m, _, _ in mem])
+    for cyc, tol in ((1, 1e-12), (5, 1e-11)):
+        b.step(cyc, mode)
+        for q, (gm, om, _) in enumerate(mem):
+            om.step(cyc)
+            err = rel_err(gm.download(), om.state(), G)
+            print(f"member {q}: rel err {err}", flush=True)
+            assert np.all(err <= tol), (q, err)
+            To, Ao = om.totals()
+            assert np.all(np.abs(gm.totals() - To) <= 1e-13 * np.maximum(Ao, 1.0))
+    b.close()
+    # bitwise equal to the members' own launches
+    stream2 = torch.cuda.Stream()
+    ref = _mixed_members(stream2)
+    for gm, _, _ in ref:
+        gm.step(6)
+    for (gm, _, _), (rm, _, _) in zip(mem, ref):
+        assert np.array_equal(gm.download(), rm.download())
+        assert gm.time() == rm.time()
+
+
+def test_persistent_wait_bound_reports_instead_of_hanging():
+    """With the wait bound set to zero every wait not met at once gives up:
+    the launch drains and ends, and the members' next synchronising call
+    reports PKH_ESTATE; a fresh upload clears the latch and the default
+    bound runs normally again (equal to the plain path)."""
+    print_case("persistent batch: zero wait bound -> PKH_ESTATE, then recovery")
+    import torch
+    from paper_2202_12309_amd.binding import Batch, PkhError
+    specs = inputs.batch_mix(n=4, seed=14, sizes=(64,))
+    stream = torch.cuda.Stream()
+    meshes = _make(specs, stream)
+    b = Batch(meshes)
+    b.set_tuning(2, 0.0)
+    assert b.tuning() == {"waves_per_simd": 2, "wait_limit_s": 0.0}
+    b.step(3, "persistent")
+    with pytest.raises(PkhError) as e:
+        meshes[0].sync()
+    assert e.value.name == "PKH_ESTATE"
+    b.set_tuning(3, 2.0)
+    for sp, m in zip(specs, meshes):
+        m.upload(inputs.batch_state(sp, m.leaves()))
+    b.step(3, "persistent")
+    ref = _make(specs, torch.cuda.Stream())
+    for m, r in zip(meshes, ref):
+        r.step(3)
+        assert np.array_equal(m.download(), r.download())
+    with pytest.raises(PkhError):
+        b.set_tuning(4, 1.0)
+
+
+def test_persistent_needs_16_or_32_cell_rows():
+    print_case("persistent batch refuses blocks of 8 cells per row")
+    from paper_2202_12309_amd.binding import Batch, Mesh, PkhError
+    m = Mesh((16,) * 3, (8, 8, 8), inputs.uniform_leaves((2, 2, 2)))
+    m.upload(inputs.sound_wave(m.leaves(), (8, 8, 8), (2, 2, 2), amp=1e-3, noise=0.0))
+    b = Batch([m])
+    b.step(1, "fused")
+    with pytest.raises(PkhError) as e:
+        b.step(1, "persistent")
+    assert e.value.name == "PKH_EINVAL"
