@@ -28,20 +28,21 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, a fused multiply-add counted as t
 # to these numbers.
 ALG_FLOPS = {"predictor": 461, "corrector": 731, "cfl": 21}
 N = 256
-STAGE_HOST_MARK = "// ---- host-side launchers: everything below runs on the host ----"
+STAGE_END_MARK = "// ---- end of the stage kernels (the persistent batch kernel follows) ----"
 DEVICE_STRUCTS = ("BlockInfo", "DevTime", "LevelMaps", "Geom", "FineFace", "StageLaunch", "GroupItem")
 
 
 def stage_device_source():
     """The source text that defines the stage kernels' device code: the
-    kernels of pkh_stage.hip (up to its host-side launchers), the device
-    helpers and pointwise physics they include, and the layouts of the
-    structures they read from pkh_internal.h. Host-side changes (launch
-    shapes, tables, entry points) leave it unchanged."""
+    stage kernels of pkh_stage.hip (up to the persistent batch kernel and the
+    host-side launchers that follow them), the device helpers and pointwise
+    physics they include, and the layouts of the structures they read from
+    pkh_internal.h. Host-side changes (launch shapes, tables, entry points)
+    leave it unchanged."""
     import re
     csrc = os.path.join(ROOT, "paper_2202_12309_amd", "csrc")
     st = open(os.path.join(csrc, "pkh_stage.hip")).read()
-    parts = [st[:st.index(STAGE_HOST_MARK)] if STAGE_HOST_MARK in st else st]
+    parts = [st[:st.index(STAGE_END_MARK)] if STAGE_END_MARK in st else st]
     for f in ("pkh_device.h", "pkh_physics.h"):
         parts.append(open(os.path.join(csrc, f)).read())
     inter = open(os.path.join(csrc, "pkh_internal.h")).read()
@@ -60,15 +61,17 @@ def stage_source_sha():
 
 def algorithmic_bytes(n):
     """Bytes per zone for the corrector kernel and for the whole cycle, FP64,
-    5 variables (40 B per cell and state). Each stage reads its input with
-    the 2-cell face halo the stencil needs (x, y and z neighbours of the
-    block's faces; no edges or corners), h = 1 + 12/n cells per zone, and
-    writes its active cells; no ghost zones are written.
+    5 variables (40 B per cell and state), counting the face halo each stage
+    reads (x, y and z neighbours of the block's faces; no edges or corners):
+    h = 1 + 12/n cells per zone for the two-cell halo of the piecewise-linear
+    corrector, h1 = 1 + 6/n for the one-cell halo of the donor-cell
+    predictor; no ghost zones are written.
 
     Corrector: read U* (h * 40 B), read U^n (40 B), write U^(n+1) (40 B).
-    Predictor: h * 40 + 40. Cycle: 80 h + 120 (230 B at n = 32)."""
+    Predictor: h1 * 40 + 40. Cycle: 40 h + 40 h1 + 120 (222.5 B at n = 32)."""
     h = 1.0 + 12.0 / n
-    return h * 40.0 + 80.0, 80.0 * h + 120.0
+    h1 = 1.0 + 6.0 / n
+    return h * 40.0 + 80.0, 40.0 * h + 40.0 * h1 + 120.0
 
 
 def stage_floor_bytes():

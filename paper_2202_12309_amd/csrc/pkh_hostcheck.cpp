@@ -26,7 +26,9 @@ void plm_states(const double* q, double* wl, double* wr) {
 
 extern "C" {
 
-int pkhc_tile_rows(int n1, int n2, int tj, long long nblocks) { return stage_tile_rows(n1, n2, tj, nblocks); }
+int pkhc_tile_rows(int n1, int n2, int tj, long long nblocks, int recon) {
+  return stage_tile_rows(n1, n2, tj, nblocks, recon);
+}
 
 void pkhc_prim(const double* u, double gam, double* w) { to_prim(u, gam, w); }
 

@@ -119,9 +119,12 @@ struct GroupItem {
 hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* insts,
                               const GroupItem* items, int nitems, hipStream_t s);
 // ---- Persistent batch launch: one kernel advances many independent
-// meshes by several cycles; workgroups take items from a ticket counter in
-// order (cycle, phase, instance) and wait only for items with smaller
-// tickets, so the launch cannot deadlock whatever its grid. ----
+// meshes by several cycles. Every instance is pinned to one XCD (a GPU
+// chiplet with its own L2); the workgroups running on that XCD take the
+// items of its instances from that XCD's ticket counter in order (cycle,
+// phase, instance) and wait only for items with smaller tickets of the same
+// counter, so the launch cannot deadlock whatever its grid, and an item's
+// producers wrote through the same L2. ----
 // Phases of a cycle: 0 predictor tiles, 1 flux correction of U*, 2 ghost
 // faces of U* across level jumps and walls, 3 corrector tiles, 4 flux
 // correction of U^{n+1}, 5 ghost faces of U^{n+1}; then the instance's clock.
@@ -150,11 +153,16 @@ struct PSync {
 struct PItem {
   int32_t inst, phase, a, b;
 };
+// Per XCD slot: next ticket, the slot's items (offset into the item array,
+// count per cycle); err is shared (slot 0's) and set when a bounded wait
+// gave up.
 struct PCtl {
-  unsigned int ticket;  // next item ticket
-  int err;              // set when a bounded wait gave up
-  int pad[2];
+  unsigned int ticket;
+  int err;
+  int32_t off, nper;
 };
+// XCD ids an XCC_ID register can report (4 bits).
+constexpr int PMAX_XCC = 16;
 // Rows per tile of the persistent launch (256-thread workgroups).
 constexpr int persistent_tile_rows(int n1) { return n1 == 32 ? 8 : (n1 == 16 ? 16 : -1); }
 // Resident 256-thread workgroups of the persistent kernel with `waves`
@@ -163,9 +171,14 @@ int persistent_grid(int waves);
 // Reset the progress counters and run `ncycles` cycles of every instance;
 // a wait longer than wait_ticks of the device wall clock gives up, latches
 // ctl->err and error bit 4 of every instance's clock, and the launch drains.
-hipError_t launch_persistent(const PInst* insts, int32_t ninst, PSync* sync, const PItem* items, int32_t nper,
-                             int32_t ncycles, PCtl* ctl, int waves, int grid, long long wait_ticks,
-                             hipStream_t s);
+// slot_of[PMAX_XCC]: the queue slot of each XCD id (-1: none); ctl[nslots].
+hipError_t launch_persistent(const PInst* insts, int32_t ninst, PSync* sync, const PItem* items,
+                             const int32_t* slot_of, PCtl* ctl, int32_t nslots, int32_t ncycles, int waves,
+                             int grid, long long wait_ticks, hipStream_t s);
+// XCD ids the workgroups of a launch of 4096 workgroups run on:
+// out_host[PMAX_XCC] = 1 for each id seen; dev_buf holds PMAX_XCC ints of
+// device memory; synchronises.
+hipError_t probe_xcc(int32_t* dev_buf, int32_t* out_host, hipStream_t s);
 
 // Ghost face regions of the (leaf, face) pairs jf[2 njf] (faces whose
 // neighbour is on another level).

@@ -20,6 +20,11 @@
 #include "pkh_amr.h"
 #include "pkh_device.h"
 
+// waves per SIMD the reverse pencils are compiled for
+#ifndef PKH_ADJ_PENCIL_WAVES
+#define PKH_ADJ_PENCIL_WAVES 2
+#endif
+
 namespace pkh {
 
 // ---------------------------------------------------------------------------
@@ -1070,26 +1075,29 @@ __global__ void __launch_bounds__(256) adj_xrow_kernel(const double* __restrict_
   }
 }
 
-// One launch for the y pencils, the z pencils and the x-face side buffer
-// (blockIdx.y = 0, 1, 2).
+// One launch for the y and z pencils (blockIdx.y = 0, 1); the x-face side
+// buffer in a launch of its own, whose register demand (beyond 256 VGPRs)
+// would otherwise hold the pencils to one wave per SIMD.
 template <int RECON>
-__global__ void __launch_bounds__(256) adj_pencils_kernel(const double* __restrict__ U,
+__global__ void __launch_bounds__(256, PKH_ADJ_PENCIL_WAVES) adj_pencils_kernel(const double* __restrict__ U,
                                                           const double* __restrict__ lam,
                                                           double* __restrict__ wyz, int64_t wstride,
-                                                          double* __restrict__ xl, const BlockInfo* blocks,
-                                                          const int32_t* nbr, int nblocks, Geom g,
-                                                          const double* dtp, double beta) {
+                                                          const BlockInfo* blocks, const int32_t* nbr, int nblocks,
+                                                          Geom g, const double* dtp, double beta) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  switch (blockIdx.y) {
-    case 0:
-      adj_pencil<RECON, 1>(U, lam, wyz, blocks, nbr, nblocks, g, dtp, beta, gid);
-      break;
-    case 1:
-      adj_pencil<RECON, 2>(U, lam, wyz + wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
-      break;
-    default:
-      adj_xside<RECON>(U, lam, xl, blocks, nbr, nblocks, g, dtp, beta, gid);
-  }
+  if (blockIdx.y == 0)
+    adj_pencil<RECON, 1>(U, lam, wyz, blocks, nbr, nblocks, g, dtp, beta, gid);
+  else
+    adj_pencil<RECON, 2>(U, lam, wyz + wstride, blocks, nbr, nblocks, g, dtp, beta, gid);
+}
+
+template <int RECON>
+__global__ void __launch_bounds__(256) adj_xside_kernel(const double* __restrict__ U,
+                                                        const double* __restrict__ lam, double* __restrict__ xl,
+                                                        const BlockInfo* blocks, const int32_t* nbr, int nblocks,
+                                                        Geom g, const double* dtp, double beta) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  adj_xside<RECON>(U, lam, xl, blocks, nbr, nblocks, g, dtp, beta, gid);
 }
 
 template <int RECON>
@@ -1128,14 +1136,17 @@ hipError_t launch_adj_stage(int recon, const double* U, const double* lam, doubl
   const int64_t nrows = (int64_t)nblocks * g.n2 * g.n3;
   const int64_t npen = std::max(std::max((int64_t)nblocks * g.n1 * g.n3, (int64_t)nblocks * g.n1 * g.n2), nrows);
   const int64_t wstride = (int64_t)nblocks * g.bstride;
-  const dim3 gr((unsigned)((nrows * g.n1 + 255) / 256)), gp((unsigned)((npen + 255) / 256), 3);
+  const dim3 gr((unsigned)((nrows * g.n1 + 255) / 256)), gp((unsigned)((npen + 255) / 256), 2),
+      gx((unsigned)((npen + 255) / 256));
   if (recon) {
-    hipLaunchKernelGGL(adj_pencils_kernel<1>, gp, dim3(256), 0, s, U, lam, wyz, wstride, xside, blocks, nbr,
-                       nblocks, g, dtp, beta);
+    hipLaunchKernelGGL(adj_pencils_kernel<1>, gp, dim3(256), 0, s, U, lam, wyz, wstride, blocks, nbr, nblocks, g,
+                       dtp, beta);
+    hipLaunchKernelGGL(adj_xside_kernel<1>, gx, dim3(256), 0, s, U, lam, xside, blocks, nbr, nblocks, g, dtp, beta);
     launch_xrow<1>(g.n1, gr, s, U, lam, wyz, wstride, xside, blocks, nbr, nblocks, g, dtp, beta, out, add0, add1);
   } else {
-    hipLaunchKernelGGL(adj_pencils_kernel<0>, gp, dim3(256), 0, s, U, lam, wyz, wstride, xside, blocks, nbr,
-                       nblocks, g, dtp, beta);
+    hipLaunchKernelGGL(adj_pencils_kernel<0>, gp, dim3(256), 0, s, U, lam, wyz, wstride, blocks, nbr, nblocks, g,
+                       dtp, beta);
+    hipLaunchKernelGGL(adj_xside_kernel<0>, gx, dim3(256), 0, s, U, lam, xside, blocks, nbr, nblocks, g, dtp, beta);
     launch_xrow<0>(g.n1, gr, s, U, lam, wyz, wstride, xside, blocks, nbr, nblocks, g, dtp, beta, out, add0, add1);
   }
   return hipGetLastError();

@@ -1460,8 +1460,10 @@ struct pkh_batch {
   PInst* d_pinst = nullptr;
   PSync* d_psync = nullptr;
   PItem* d_pitems = nullptr;
-  PCtl* d_pctl = nullptr;
-  int32_t npitems = 0;
+  PCtl* d_pctl = nullptr;           // per XCD slot
+  int32_t* d_slot_of = nullptr;     // XCD id -> slot
+  int32_t nslots = 0;
+  int32_t npitems = 0;              // items of one cycle over all slots
   int32_t pwaves = 2;               // waves per SIMD of the persistent kernel (2 or 3)
   double wait_limit_s = 2.0;        // bound of every wait inside the persistent kernel
   int32_t wall_khz = 0;             // device wall-clock rate
@@ -1566,65 +1568,96 @@ int batch_fused(pkh_batch* b, int32_t n, bool graph) {
   return PKH_OK;
 }
 
-// Descriptors and items of the persistent launch (instances in decreasing
-// order of cells, so the longest ones start first in every phase).
+// Descriptors and items of the persistent launch. The XCDs the device runs
+// workgroups on are found by a probe launch; each instance is pinned to one
+// of them (largest instances first, each to the least loaded XCD by cells),
+// and each XCD's items are ordered by phase, then instance (largest first).
 int batch_build_persistent(pkh_batch* b, const std::vector<StageLaunch>& pred,
                            const std::vector<StageLaunch>& corr) {
   pkh_mesh* m0 = b->meshes[0];
   const int32_t n = (int32_t)b->meshes.size();
-  std::vector<PInst> pin(n);
+  int32_t seen[PMAX_XCC] = {};
+  int32_t* d_probe = (int32_t*)m0->dalloc(PMAX_XCC * sizeof(int32_t));
+  if (!d_probe) return fail(PKH_ENOMEM, "persistent batch allocation failed");
+  const hipError_t pe = probe_xcc(d_probe, seen, b->stream);
+  m0->dfree(d_probe);
+  if (pe != hipSuccess) return fail(PKH_EHIP, "XCD probe failed: %s", hipGetErrorString(pe));
+  std::vector<int32_t> slot_of(PMAX_XCC, -1);
+  int32_t nslots = 0;
+  for (int x = 0; x < PMAX_XCC; ++x)
+    if (seen[x]) slot_of[x] = nslots++;
+  if (nslots < 1) return fail(PKH_EHIP, "XCD probe saw no workgroup");
+  auto cells = [&](int32_t q) {
+    const pkh_mesh* m = b->meshes[q];
+    return m->nb() * m->g.n1 * m->g.n2 * m->g.n3;
+  };
   std::vector<int32_t> order(n);
   for (int32_t q = 0; q < n; ++q) order[q] = q;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    const pkh_mesh *a = b->meshes[x], *c = b->meshes[y];
-    return a->nb() * a->g.n1 * a->g.n2 * a->g.n3 > c->nb() * c->g.n1 * c->g.n2 * c->g.n3;
-  });
-  std::vector<PItem> per[PPHASES];
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cells(x) > cells(y); });
+  std::vector<int64_t> load(nslots, 0);
+  std::vector<std::vector<int32_t>> members(nslots);
   for (int32_t q : order) {
-    pkh_mesh* m = b->meshes[q];
-    PInst& pi = pin[q];
-    pi = PInst{};
-    pi.st[0] = pred[q];
-    pi.st[1] = corr[q];
-    pi.ff = m->d_ff;
-    pi.ff_first = m->d_ff_first;
-    pi.cblocks = m->d_cblocks;
-    pi.jf = m->d_jf;
-    pi.maps = m->maps;
-    pi.n1 = m->g.n1;
-    const int tj = persistent_tile_rows(m->g.n1);
-    for (int32_t blk = 0; blk < (int32_t)m->nb(); ++blk)
-      for (int32_t j0 = 0; j0 < m->g.n2; j0 += tj) {
-        per[0].push_back(PItem{q, 0, blk, j0});
-        per[3].push_back(PItem{q, 3, blk, j0});
-      }
-    pi.cnt[0] = pi.cnt[3] = (int32_t)(m->nb() * (m->g.n2 / tj));
-    const int nshell = 2 * m->g.n1 * m->g.n2 + (m->g.n3 - 2) * (2 * m->g.n1 + 2 * (m->g.n2 - 2));
-    const int nfc = (nshell + 255) / 256;
-    for (int32_t c = 0; c < m->ncblocks; ++c)
-      for (int32_t x = 0; x < nfc; ++x) {
-        per[1].push_back(PItem{q, 1, x, c});
-        per[4].push_back(PItem{q, 4, x, c});
-      }
-    pi.cnt[1] = pi.cnt[4] = m->ncblocks * nfc;
-    const int area = std::max(std::max(m->g.n1 * m->g.n2, m->g.n1 * m->g.n3), m->g.n2 * m->g.n3);
-    const int nff = (2 * area + 255) / 256;
-    for (int32_t f = 0; f < m->njf; ++f)
-      for (int32_t x = 0; x < nff; ++x) {
-        per[2].push_back(PItem{q, 2, x, f});
-        per[5].push_back(PItem{q, 5, x, f});
-      }
-    pi.cnt[2] = pi.cnt[5] = m->njf * nff;
-    pi.last = pi.cnt[5] ? 5 : (pi.cnt[4] ? 4 : 3);
+    int best = 0;
+    for (int k = 1; k < nslots; ++k)
+      if (load[k] < load[best]) best = k;
+    load[best] += cells(q);
+    members[best].push_back(q);
   }
+  std::vector<PInst> pin(n);
   std::vector<PItem> items;
-  for (auto& v : per) items.insert(items.end(), v.begin(), v.end());
+  std::vector<PCtl> ctl(nslots);
+  for (int k = 0; k < nslots; ++k) {
+    std::vector<PItem> per[PPHASES];
+    for (int32_t q : members[k]) {
+      pkh_mesh* m = b->meshes[q];
+      PInst& pi = pin[q];
+      pi = PInst{};
+      pi.st[0] = pred[q];
+      pi.st[1] = corr[q];
+      pi.ff = m->d_ff;
+      pi.ff_first = m->d_ff_first;
+      pi.cblocks = m->d_cblocks;
+      pi.jf = m->d_jf;
+      pi.maps = m->maps;
+      pi.n1 = m->g.n1;
+      const int tj = persistent_tile_rows(m->g.n1);
+      for (int32_t blk = 0; blk < (int32_t)m->nb(); ++blk)
+        for (int32_t j0 = 0; j0 < m->g.n2; j0 += tj) {
+          per[0].push_back(PItem{q, 0, blk, j0});
+          per[3].push_back(PItem{q, 3, blk, j0});
+        }
+      pi.cnt[0] = pi.cnt[3] = (int32_t)(m->nb() * (m->g.n2 / tj));
+      const int nshell = 2 * m->g.n1 * m->g.n2 + (m->g.n3 - 2) * (2 * m->g.n1 + 2 * (m->g.n2 - 2));
+      const int nfc = (nshell + 255) / 256;
+      for (int32_t c = 0; c < m->ncblocks; ++c)
+        for (int32_t x = 0; x < nfc; ++x) {
+          per[1].push_back(PItem{q, 1, x, c});
+          per[4].push_back(PItem{q, 4, x, c});
+        }
+      pi.cnt[1] = pi.cnt[4] = m->ncblocks * nfc;
+      const int area = std::max(std::max(m->g.n1 * m->g.n2, m->g.n1 * m->g.n3), m->g.n2 * m->g.n3);
+      const int nff = (2 * area + 255) / 256;
+      for (int32_t f = 0; f < m->njf; ++f)
+        for (int32_t x = 0; x < nff; ++x) {
+          per[2].push_back(PItem{q, 2, x, f});
+          per[5].push_back(PItem{q, 5, x, f});
+        }
+      pi.cnt[2] = pi.cnt[5] = m->njf * nff;
+      pi.last = pi.cnt[5] ? 5 : (pi.cnt[4] ? 4 : 3);
+    }
+    ctl[k] = PCtl{};
+    ctl[k].off = (int32_t)items.size();
+    for (auto& v : per) items.insert(items.end(), v.begin(), v.end());
+    ctl[k].nper = (int32_t)items.size() - ctl[k].off;
+  }
   b->npitems = (int32_t)items.size();
+  b->nslots = nslots;
   int rc;
-  if ((rc = upload_vec(m0, &b->d_pinst, pin)) || (rc = upload_vec(m0, &b->d_pitems, items))) return rc;
+  if ((rc = upload_vec(m0, &b->d_pinst, pin)) || (rc = upload_vec(m0, &b->d_pitems, items)) ||
+      (rc = upload_vec(m0, &b->d_pctl, ctl)) || (rc = upload_vec(m0, &b->d_slot_of, slot_of)))
+    return rc;
   b->d_psync = (PSync*)m0->dalloc(n * sizeof(PSync));
-  b->d_pctl = (PCtl*)m0->dalloc(sizeof(PCtl));
-  if (!b->d_psync || !b->d_pctl) return fail(PKH_ENOMEM, "persistent batch allocation failed");
+  if (!b->d_psync) return fail(PKH_ENOMEM, "persistent batch allocation failed");
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&b->wall_khz, hipDeviceAttributeWallClockRate, dev));
@@ -1642,8 +1675,8 @@ int batch_persistent(pkh_batch* b, int32_t n) {
   HIPCHK(launch_clock_group(b->d_tms, (int32_t)b->meshes.size(), CLOCK_BEGIN, INFINITY, b->stream));
   for (int c = 0; c < n; c += 50) {
     const int K = std::min(50, n - c);
-    HIPCHK(launch_persistent(b->d_pinst, (int32_t)b->meshes.size(), b->d_psync, b->d_pitems, b->npitems, K,
-                             b->d_pctl, b->pwaves, grid, ticks, b->stream));
+    HIPCHK(launch_persistent(b->d_pinst, (int32_t)b->meshes.size(), b->d_psync, b->d_pitems, b->d_slot_of,
+                             b->d_pctl, b->nslots, K, b->pwaves, grid, ticks, b->stream));
   }
   return PKH_OK;
 }
@@ -1785,6 +1818,7 @@ int pkh_batch_destroy(pkh_batch* b) {
   m0->dfree(b->d_psync);
   m0->dfree(b->d_pitems);
   m0->dfree(b->d_pctl);
+  m0->dfree(b->d_slot_of);
   if (b->attached)
     for (pkh_mesh* m : b->meshes) m->attached--;
   delete b;

@@ -17,9 +17,10 @@
 #include "pkh_device.h"
 
 // Launch options: the corrector prefetches the next plane's inputs and the
-// U^n values of its next update one plane ahead, at two waves per SIMD
-// (measured at 256^3: 0.94 ms against 1.11 ms with neither prefetch at
-// three waves); waves per SIMD the launch bounds ask for.
+// U^n values of its next update one plane ahead (measured at 256^3: 0.94 ms
+// against 1.11 ms with neither prefetch at three waves per SIMD); waves per
+// SIMD the launch bounds ask for (PKH_CORR_WAVES_256: the corrector on
+// 256-thread tiles of 32-cell rows, see stage_waves).
 #ifndef PKH_CORR_PF
 #define PKH_CORR_PF 1
 #endif
@@ -31,6 +32,9 @@
 #endif
 #ifndef PKH_PRED_WAVES
 #define PKH_PRED_WAVES 2
+#endif
+#ifndef PKH_CORR_WAVES_256
+#define PKH_CORR_WAVES_256 3
 #endif
 // issue the next plane's loads after the update (1) or right after staging (0)
 #ifndef PKH_PF_LATE
@@ -46,10 +50,6 @@
 #endif
 #ifndef PKH_PRED_PFD
 #define PKH_PRED_PFD 1
-#endif
-// one barrier per plane (double-buffered LDS) where it fits
-#ifndef PKH_SINGLE_BARRIER
-#define PKH_SINGLE_BARRIER 1
 #endif
 
 namespace pkh {
@@ -74,37 +74,17 @@ namespace pkh {
 // ---------------------------------------------------------------------------
 
 // LDS doubles one tile of a stage uses: the staged plane (NQ values per
-// cell of (TJ+4) x (N1+4)), the x and y face fluxes (each twice with one
-// barrier per plane, SB), one slot per wave.
-template <int RECON, int N1, int TJ, bool SB = false>
+// cell of (TJ+4) x (N1+4)), the x and y face fluxes, one slot per wave.
+template <int RECON, int N1, int TJ>
 constexpr int stage_lds_doubles() {
-  return (SB ? 2 : 1) * ((RECON ? 5 : 8) * (TJ + 2 * NG) * (N1 + 2 * NG) + NV * TJ * (N1 + 1) +
-                         NV * (TJ + 1) * N1) +
+  return (RECON ? 5 : 8) * (TJ + 2 * NG) * (N1 + 2 * NG) + NV * TJ * (N1 + 1) + NV * (TJ + 1) * N1 +
          (N1 * TJ + 63) / 64;
 }
 
-// One barrier per plane (double-buffered plane and fluxes) where the
-// doubled LDS still lets the workgroups that make two waves per SIMD (eight
-// per CU) share a CU's 160 KB.
-template <int RECON, int N1, int TJ>
-constexpr bool stage_single_barrier() {
-#if PKH_SINGLE_BARRIER
-  constexpr int wg_waves = N1 * TJ / 64;
-  constexpr int wgs = wg_waves >= 8 ? 1 : 8 / wg_waves;
-  return stage_lds_doubles<RECON, N1, TJ, true>() * 8 * wgs <= 160 * 1024 - 1024;
-#else
-  return false;
-#endif
-}
-
 // One tile (TJ rows of block blk starting at row j0) of a stage with
-// timestep dt, in LDS at lds (stage_lds_doubles<..., SB> doubles); rot
-// rotates which wave takes the tile's remainder faces. SB: the staged plane
-// and the face fluxes are double-buffered, so each plane needs one barrier:
-// the x/y divergence of plane p-1 is formed after the barrier that follows
-// the staging of plane p, and the faces of plane p are solved into the
-// other flux buffer without waiting for the slowest wave.
-template <int RECON, int N1, int TJ, typename S = double, bool SB = false>
+// timestep dt, in LDS at lds (stage_lds_doubles doubles); rot rotates which
+// wave takes the tile's remainder faces.
+template <int RECON, int N1, int TJ, typename S = double>
 __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0, int rot, double dt,
                                            double* __restrict__ lds) {
   constexpr int NT = N1 * TJ;
@@ -129,21 +109,11 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   constexpr int PFD = PF ? (RECON ? PKH_CORR_PFD : PKH_PRED_PFD) : 1;  // planes in flight
   static_assert(NT % 64 == 0, "whole waves");
 
-  constexpr int NBUF = SB ? 2 : 1;
-  constexpr int BUF = NQ * PLANE + NV * NX + NV * NY;  // one plane's staging and fluxes
-  static_assert(stage_lds_doubles<RECON, N1, TJ, SB>() == NBUF * BUF + NWAVE, "LDS layout");
-  double* __restrict__ sRed = lds + NBUF * BUF;
-  // the buffers of plane p: the parity of p with SB (p >= -3), else one
-  auto Qb = [&](int p) { return reinterpret_cast<double(*)[PLANE]>(lds + (SB ? ((p + 4) & 1) * BUF : 0)); };
-  auto FXb = [&](int p) {
-    return reinterpret_cast<double(*)[NX]>(lds + (SB ? ((p + 4) & 1) * BUF : 0) + NQ * PLANE);
-  };
-  auto FYb = [&](int p) {
-    return reinterpret_cast<double(*)[NY]>(lds + (SB ? ((p + 4) & 1) * BUF : 0) + NQ * PLANE + NV * NX);
-  };
-  double(*sQ)[PLANE] = Qb(0);
-  double(*sFx)[NX] = FXb(0);
-  double(*sFy)[NY] = FYb(0);
+  static_assert(stage_lds_doubles<RECON, N1, TJ>() == NQ * PLANE + NV * NX + NV * NY + NWAVE, "LDS layout");
+  double(*__restrict__ sQ)[PLANE] = reinterpret_cast<double(*)[PLANE]>(lds);
+  double(*__restrict__ sFx)[NX] = reinterpret_cast<double(*)[NX]>(lds + NQ * PLANE);
+  double(*__restrict__ sFy)[NY] = reinterpret_cast<double(*)[NY]>(lds + NQ * PLANE + NV * NX);
+  double* __restrict__ sRed = lds + NQ * PLANE + NV * NX + NV * NY;
 
   const Geom& g = a.g;
   const int tid = threadIdx.x;
@@ -365,11 +335,6 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   for (int sl = 0; sl < PFD; ++sl) {
     const int p = pb + sl;
     if (p >= p_end) break;  // plane count not a multiple of PFD (uniform)
-    if constexpr (SB) {
-      sQ = Qb(p);
-      sFx = FXb(p - 1);
-      sFy = FYb(p - 1);
-    }
     // --- stage plane p (rows j0-2 .. j0+TJ+1): own cell first, then halo.
     // The predictor takes plane p from registers loaded while plane p-1 was
     // being computed and starts the loads of plane p+1 right away.
@@ -430,23 +395,6 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       }
     }
     __syncthreads();
-
-    if constexpr (SB) {
-      // x/y divergence of plane p - 1 (its fluxes are in the other buffer,
-      // complete since every wave passed the barrier above)
-#pragma unroll
-      for (int s = 0; s < QN - 1; ++s)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
-      if (p - 1 >= 0 && p - 1 < n3) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-          dq[QN - 1][v] = (sFx[v][tj * (N1 + 1) + ti + 1] - sFx[v][tj * (N1 + 1) + ti]) * bi.idx[0] +
-                          (sFy[v][(tj + 1) * N1 + ti] - sFy[v][tj * N1 + ti]) * bi.idx[1];
-      }
-      sFx = FXb(p);
-      sFy = FYb(p);
-    }
 
     // --- z face m between cells m-1 and m, then finish cell m-1
     const int m = p - LAG;
@@ -546,32 +494,26 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
                    xf ? bi.fslot[XHI] : (j0 + TJ == n2 ? bi.fslot[YHI] : -1),
                    xf ? (int64_t)p * n2 + j0 + q : (int64_t)p * N1 + iy);
       }
-      if constexpr (!SB) {
-        __syncthreads();
+      __syncthreads();
 #pragma unroll
-        for (int s = 0; s < QN - 1; ++s)
+      for (int s = 0; s < QN - 1; ++s)
 #pragma unroll
-          for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
+        for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-          dq[QN - 1][v] = (sFx[v][tj * (N1 + 1) + ti + 1] - sFx[v][tj * (N1 + 1) + ti]) * bi.idx[0] +
-                          (sFy[v][(tj + 1) * N1 + ti] - sFy[v][tj * N1 + ti]) * bi.idx[1];
-      }
-    } else if constexpr (!SB) {
+      for (int v = 0; v < NV; ++v)
+        dq[QN - 1][v] = (sFx[v][tj * (N1 + 1) + ti + 1] - sFx[v][tj * (N1 + 1) + ti]) * bi.idx[0] +
+                        (sFy[v][(tj + 1) * N1 + ti] - sFy[v][tj * N1 + ti]) * bi.idx[1];
+    } else {
       // keep the queue aligned with plane numbers on the leading planes
 #pragma unroll
       for (int s = 0; s < QN - 1; ++s)
 #pragma unroll
         for (int v = 0; v < NV; ++v) dq[s][v] = dq[s + 1][v];
     }
-    // no barrier here. Without SB: the next plane's staging only
-    // overwrites the LDS plane, whose last readers (this plane's x/y faces)
-    // finished before the barrier above, and the next plane's fluxes are
-    // written after its first barrier, which every wave reaches after this
-    // divergence. With SB: the next plane is staged into the other buffer,
-    // last read by the faces of plane p - 1, which every wave finished before
-    // this plane's barrier; this plane's fluxes are read after the next
-    // plane's barrier and overwritten only after the one after it.
+    // no barrier here: the next plane's staging only overwrites the LDS
+    // plane, whose last readers (this plane's x/y faces) finished before the
+    // barrier above, and the next plane's fluxes are written after its first
+    // barrier, which every wave reaches after this divergence
   }
 
   if (a.do_dt) {
@@ -588,6 +530,18 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   if (bad) atomicOr(&a.tm->err, 1);
 }
 
+// Waves per SIMD a stage variant is compiled for. The corrector on tiles of
+// 8 rows of 32 cells (256 threads) runs at three (a 168-VGPR cap with a few
+// spilled values; measured at 256^3: 0.722 ms against 0.758 ms at two waves
+// with the same tiles and 0.754 ms for 16-row tiles at two): more waves keep
+// more loads in flight per CU. Everything else at two (the 16^3-block
+// corrector and the predictor gain nothing at three; four waves spill
+// heavily).
+template <int RECON, int N1, int TJ>
+constexpr int stage_waves() {
+  return (RECON && N1 == 32 && N1 * TJ == 256) ? PKH_CORR_WAVES_256 : (RECON ? PKH_CORR_WAVES : PKH_PRED_WAVES);
+}
+
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; map
 // consecutive items (tiles of a block, which share halo rows) to one XCD's L2.
 __device__ __forceinline__ int xcd_order(int wg, int nwg) {
@@ -597,19 +551,18 @@ __device__ __forceinline__ int xcd_order(int wg, int nwg) {
 // Occupancy: both stages keep the next plane's loads in flight in registers
 // and run at two waves per SIMD.
 template <int RECON, int N1, int TJ>
-__global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAVES) stage_kernel(StageLaunch a) {
+__global__ void __launch_bounds__(N1 * TJ, (stage_waves<RECON, N1, TJ>())) stage_kernel(StageLaunch a) {
   const int ntj = a.g.n2 / TJ;
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   const int blk = wg / ntj;
   if (blk >= a.nblocks) return;
-  constexpr bool SB = stage_single_barrier<RECON, N1, TJ>();
-  __shared__ double lds[stage_lds_doubles<RECON, N1, TJ, SB>()];
-  stage_tile<RECON, N1, TJ, double, SB>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg, a.tm->dt, lds);
+  __shared__ double lds[stage_lds_doubles<RECON, N1, TJ>()];
+  stage_tile<RECON, N1, TJ>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg, a.tm->dt, lds);
 }
 
 // The same over a state stored in FP32.
 template <int RECON, int N1, int TJ>
-__global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAVES) stage_kernel_f32(StageLaunch a) {
+__global__ void __launch_bounds__(N1 * TJ, (stage_waves<RECON, N1, TJ>())) stage_kernel_f32(StageLaunch a) {
   const int ntj = a.g.n2 / TJ;
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   const int blk = wg / ntj;
@@ -621,49 +574,73 @@ __global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAV
 // Grouped launch: the tiles of many independent meshes (same block width
 // and tile) in one grid; items[w] names the mesh, block and first row.
 template <int RECON, int N1, int TJ>
-__global__ void __launch_bounds__(N1 * TJ, RECON ? PKH_CORR_WAVES : PKH_PRED_WAVES) stage_group_kernel(const StageLaunch* insts,
+__global__ void __launch_bounds__(N1 * TJ, (stage_waves<RECON, N1, TJ>())) stage_group_kernel(const StageLaunch* insts,
                                                                  const GroupItem* items, int nitems) {
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   if (wg >= nitems) return;
   const GroupItem it = items[wg];
-  constexpr bool SB = stage_single_barrier<RECON, N1, TJ>();
-  __shared__ double lds[stage_lds_doubles<RECON, N1, TJ, SB>()];
+  __shared__ double lds[stage_lds_doubles<RECON, N1, TJ>()];
   const StageLaunch& a = insts[it.inst];
-  stage_tile<RECON, N1, TJ, double, SB>(a, it.blk, it.j0, wg, a.tm->dt, lds);
+  stage_tile<RECON, N1, TJ>(a, it.blk, it.j0, wg, a.tm->dt, lds);
 }
 
+// ---- end of the stage kernels (the persistent batch kernel follows) ----
+
 // ---------------------------------------------------------------------------
-// Persistent batch kernel. Workgroups take item tickets in order; ticket t
-// is item t % nper of cycle t / nper, the items of a cycle ordered by phase,
-// then instance. An item waits (thread 0, bounded) for the previous phase
-// of its instance in the same cycle, or for the instance's clock to reach
-// the cycle, i.e. only for items of smaller tickets, which are held by
-// running workgroups: no deadlock whatever the grid. Visibility across
-// XCDs: every thread releases its stores at device scope before thread 0
-// counts the item done; thread 0 acquires at device scope after its wait.
+// Persistent batch kernel. Each instance is pinned to one XCD; a workgroup
+// reads the id of the XCD it runs on and takes tickets from that XCD's
+// counter: ticket t is item t % nper of cycle t / nper of the XCD's list,
+// whose items are ordered by phase, then instance. An item waits (thread 0,
+// bounded) for the previous phase of its instance in the same cycle, or for
+// the instance's clock to reach the cycle, i.e. only for items of smaller
+// tickets of the same counter, held by running workgroups: no deadlock
+// whatever the grid. Visibility: every thread waits for its stores to
+// complete, then thread 0 makes them visible at device scope (release)
+// before the item is counted, and a consumer's thread 0 acquires at device
+// scope after its wait. Pinning an instance to one XCD keeps its blocks in
+// one L2 between items; the fences stay device-scope all the same (a
+// variant that only dropped the CU's L1 at the acquire gave wrong results
+// and is not kept).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ unsigned int ld_acq(const unsigned int* p) {
+__device__ __forceinline__ unsigned int ld_relaxed(const unsigned int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until *p >= target; false when ctl->err is set or wait_ticks of the
+// Id of the XCD (chiplet, own L2) this wave runs on.
+__device__ __forceinline__ int xcc_id() {
+  unsigned x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
+  return (int)x;
+}
+
+// This thread's global stores are complete (the L1 writes through to the L2).
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Release (thread 0, after every thread's stores completed and a barrier):
+// the workgroup's stores become visible at device scope before the item is
+// counted. Acquire (thread 0, after its wait): later loads of the workgroup
+// see what the awaited items stored.
+__device__ __forceinline__ void item_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void item_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Wait until *p >= target; false when *err is set or wait_ticks of the
 // device wall clock pass first.
 __device__ bool persistent_wait(const unsigned int* p, unsigned int target, const int* err, long long wait_ticks) {
-  if (ld_acq(p) >= target) return true;
+  if (ld_relaxed(p) >= target) return true;
   const long long t0 = (long long)wall_clock64();
   for (;;) {
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
     if ((long long)wall_clock64() - t0 > wait_ticks) return false;
     __builtin_amdgcn_s_sleep(4);
-    if (ld_acq(p) >= target) return true;
+    if (ld_relaxed(p) >= target) return true;
   }
 }
 
 // Close a cycle of one instance and open the next (the batched clock with
 // no end time): dt_next = CFL / max signal speed, t += dt, cycle + 1,
-// dt = dt_next, reduction reset. Fields are read and written with device
-// scope atomics so no stale cached copy is used on any XCD.
+// dt = dt_next, reduction reset. Every field goes through atomics, which
+// are performed in the L2 the instance's workgroups share.
 __device__ void persistent_clock(DevTime* tm) {
   const unsigned long long sb = __hip_atomic_load(&tm->smax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const double cfl = __hip_atomic_load(&tm->cfl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -686,34 +663,40 @@ constexpr int persistent_lds_doubles() {
 template <int W>
 __global__ void __launch_bounds__(256, W)
     persistent_kernel(const PInst* __restrict__ insts, int ninst, PSync* sync, const PItem* __restrict__ items,
-                      int nper, int ncycles, PCtl* ctl, long long wait_ticks) {
+                      const int32_t* __restrict__ slot_of, PCtl* ctl, int ncycles, long long wait_ticks) {
   __shared__ double lds[persistent_lds_doubles()];
   __shared__ double s_red[4];
   __shared__ unsigned int s_ticket;
   __shared__ double s_dt;
   __shared__ int s_ok;
   const int tid = threadIdx.x;
-  const unsigned int total = (unsigned int)nper * (unsigned int)ncycles;
+  const int slot = slot_of[xcc_id() & (PMAX_XCC - 1)];
+  if (slot < 0) return;  // no instance lives on this XCD (uniform per workgroup)
+  PCtl* q = ctl + slot;
+  int* err = &ctl[0].err;
+  const unsigned int nper = (unsigned int)q->nper;
+  const unsigned int total = nper * (unsigned int)ncycles;
+  const PItem* qitems = items + q->off;
   for (;;) {
-    if (tid == 0) s_ticket = atomicAdd(&ctl->ticket, 1u);
+    if (tid == 0) s_ticket = atomicAdd(&q->ticket, 1u);
     __syncthreads();
     const unsigned int tk = s_ticket;
     if (tk >= total) break;  // uniform: every wave of the workgroup leaves
-    const unsigned int c = tk / (unsigned int)nper;
-    const PItem it = items[tk - c * (unsigned int)nper];
+    const unsigned int c = tk / nper;
+    const PItem it = qitems[tk - c * nper];
     const PInst& in = insts[it.inst];
     PSync* ps = sync + it.inst;
     if (tid == 0) {
       int prev = it.phase - 1;
       while (prev >= 0 && in.cnt[prev] == 0) --prev;
-      const bool ok = prev < 0 ? persistent_wait(&ps->clock, c, &ctl->err, wait_ticks)
-                               : persistent_wait(&ps->done[prev], (c + 1) * (unsigned int)in.cnt[prev], &ctl->err,
+      const bool ok = prev < 0 ? persistent_wait(&ps->clock, c, err, wait_ticks)
+                               : persistent_wait(&ps->done[prev], (c + 1) * (unsigned int)in.cnt[prev], err,
                                                  wait_ticks);
-      if (!ok && atomicCAS(&ctl->err, 0, 1) == 0) {
+      if (!ok && atomicCAS(err, 0, 1) == 0) {
         // the first to give up marks every instance's state invalid
-        for (int q = 0; q < ninst; ++q) atomicOr(&insts[q].st[0].tm->err, 4);
+        for (int r = 0; r < ninst; ++r) atomicOr(&insts[r].st[0].tm->err, 4);
       }
-      __threadfence();  // acquire: the awaited items' stores are visible
+      item_acquire();
       s_ok = ok;
       s_dt = __hip_atomic_load(&in.st[0].tm->dt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -743,16 +726,18 @@ __global__ void __launch_bounds__(256, W)
         const StageLaunch& a = in.st[ph == 5];
         fill_faces_item(static_cast<double*>(a.uout), a.blocks, a.g, in.maps, a.tm, in.jf, it.a, it.b);
       }
-      // release: every thread's stores reach device scope before the item
+      // every thread's stores complete, then one release before the item
       // is counted
-      __threadfence();
+      stores_done();
       __syncthreads();
       if (tid == 0) {
+        item_release();
         const unsigned int old = atomicAdd(&ps->done[ph], 1u);
         if (ph == in.last && old + 1 == (c + 1) * (unsigned int)in.cnt[ph]) {
-          __threadfence();
+          item_acquire();
           persistent_clock(in.st[0].tm);
-          __threadfence();
+          stores_done();
+          item_release();
           __hip_atomic_store(&ps->clock, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
@@ -761,10 +746,18 @@ __global__ void __launch_bounds__(256, W)
   }
 }
 
-__global__ void persistent_reset_kernel(PSync* sync, int ninst, PCtl* ctl) {
+__global__ void persistent_reset_kernel(PSync* sync, int ninst, PCtl* ctl, int nslots) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < ninst) sync[q] = PSync{};
-  if (q == 0) *ctl = PCtl{};
+  if (q < nslots) {
+    ctl[q].ticket = 0u;
+    ctl[q].err = 0;
+  }
+}
+
+// Each workgroup records the XCD it runs on.
+__global__ void xcc_probe_kernel(int32_t* seen) {
+  if (threadIdx.x == 0) seen[xcc_id() & (PMAX_XCC - 1)] = 1;
 }
 
 // ---- host-side launchers: everything below runs on the host ----
@@ -825,7 +818,7 @@ hipError_t launch_stage_group(int recon, int n1, int tj, const StageLaunch* inst
 }
 
 hipError_t launch_stage(const StageLaunch& a, hipStream_t s) {
-  const int tj = stage_tile_rows(a.g.n1, a.g.n2, a.tj, a.nblocks);
+  const int tj = stage_tile_rows(a.g.n1, a.g.n2, a.tj, a.nblocks, a.recon);
   if (a.fp32) {  // FP32 storage: blocks of 16 or 32 cells per row, 8 or 16 rows
     switch (a.g.n1 * 100 + tj) {
       case 1608:
@@ -877,18 +870,30 @@ int persistent_grid(int waves) {
   return per * ncu;
 }
 
-hipError_t launch_persistent(const PInst* insts, int32_t ninst, PSync* sync, const PItem* items, int32_t nper,
-                             int32_t ncycles, PCtl* ctl, int waves, int grid, long long wait_ticks,
-                             hipStream_t s) {
-  if (ninst < 1 || nper < 1 || ncycles < 1 || grid < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(persistent_reset_kernel, dim3((ninst + 255) / 256), dim3(256), 0, s, sync, (int)ninst, ctl);
+hipError_t launch_persistent(const PInst* insts, int32_t ninst, PSync* sync, const PItem* items,
+                             const int32_t* slot_of, PCtl* ctl, int32_t nslots, int32_t ncycles, int waves,
+                             int grid, long long wait_ticks, hipStream_t s) {
+  if (ninst < 1 || nslots < 1 || ncycles < 1 || grid < 1) return hipErrorInvalidValue;
+  const int nr = std::max<int>(ninst, nslots);
+  hipLaunchKernelGGL(persistent_reset_kernel, dim3((nr + 255) / 256), dim3(256), 0, s, sync, (int)ninst, ctl,
+                     (int)nslots);
   if (waves == 3)
-    hipLaunchKernelGGL(persistent_kernel<3>, dim3(grid), dim3(256), 0, s, insts, (int)ninst, sync, items,
-                       (int)nper, (int)ncycles, ctl, wait_ticks);
+    hipLaunchKernelGGL(persistent_kernel<3>, dim3(grid), dim3(256), 0, s, insts, (int)ninst, sync, items, slot_of,
+                       ctl, (int)ncycles, wait_ticks);
   else
-    hipLaunchKernelGGL(persistent_kernel<2>, dim3(grid), dim3(256), 0, s, insts, (int)ninst, sync, items,
-                       (int)nper, (int)ncycles, ctl, wait_ticks);
+    hipLaunchKernelGGL(persistent_kernel<2>, dim3(grid), dim3(256), 0, s, insts, (int)ninst, sync, items, slot_of,
+                       ctl, (int)ncycles, wait_ticks);
   return hipGetLastError();
+}
+
+hipError_t probe_xcc(int32_t* dev_buf, int32_t* out_host, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(dev_buf, 0, PMAX_XCC * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(xcc_probe_kernel, dim3(4096), dim3(64), 0, s, dev_buf);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(out_host, dev_buf, PMAX_XCC * sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(s);
 }
 
 }  // namespace pkh

@@ -7,19 +7,24 @@
 namespace pkh {
 
 // Rows per workgroup tile for a block of n1 x n2 cells and a requested value
-// tj (0: default); -1 if no compiled variant fits.
+// tj (0: default) of a stage with piecewise-linear (recon 1) or donor-cell
+// (recon 0) faces; -1 if no compiled variant fits.
 //
 // Compiled (n1, rows) variants, the default first: n1 = 8: 8; n1 = 16: 8,
 // 16, 4; n1 = 32: 8, 4, 16; n1 = 64: 4, 2. An explicit request must be one
-// of them and divide n2. The default for n1 = 32 is 16 rows once the launch
-// has at least two rounds of waves at two waves per SIMD (4096 waves), else
-// 8; for n1 = 16 it is 16 rows from 1024 waves on, else 8 (nblocks, the
-// blocks of the launch, 0 when unknown). Measured: 16 rows against 8 save
-// 1.5 % of the 256^3 cycle with blocks of 32^3, 3 % with blocks of 16^3, and
-// 7 % of the two-level blast (960 leaves of 16^3). When the preferred
-// default does not divide n2 the default is the largest compiled variant
-// below it that does (then the largest that does at all).
-inline int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0) {
+// of them and divide n2. Defaults: the piecewise-linear stage on 32-cell
+// rows takes 8 rows (its 256-thread variant runs at three waves per SIMD);
+// the donor-cell stage on 32-cell rows takes 16 rows once the launch has at
+// least two rounds of waves at two waves per SIMD (4096 waves), else 8; on
+// 16-cell rows both take 16 rows from 1024 waves on, else 8 (nblocks, the
+// blocks of the launch, 0 when unknown). Measured at 256^3: the corrector
+// 0.722 ms on 8 rows at three waves against 0.754 ms on 16 rows, the
+// predictor 0.47 ms on 16 rows against 0.49 ms on 8; 16 rows against 8 save
+// 3 % with blocks of 16^3 and 7 % of the two-level blast (960 leaves of
+// 16^3). When the preferred default does not divide n2 the default is the
+// largest compiled variant below it that does (then the largest that does
+// at all).
+inline int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0, int recon = 1) {
   static const int opts[4][3] = {{8, 0, 0}, {8, 16, 4}, {8, 4, 16}, {4, 2, 0}};
   const int row = n1 == 8 ? 0 : n1 == 16 ? 1 : n1 == 32 ? 2 : n1 == 64 ? 3 : -1;
   if (row < 0 || n2 <= 0) return -1;
@@ -30,7 +35,7 @@ inline int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0) {
   }
   int want = opts[row][0];
   const int64_t waves = nblocks * n1 * n2 / 64;
-  if (n1 == 32 && (nblocks == 0 || waves >= 4096)) want = 16;
+  if (n1 == 32 && !recon && (nblocks == 0 || waves >= 4096)) want = 16;
   if (n1 == 16 && nblocks > 0 && waves >= 1024) want = 16;
   int best = -1, any = -1;
   for (int q = 0; q < 3; ++q) {

