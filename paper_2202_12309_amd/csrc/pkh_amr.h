@@ -5,8 +5,7 @@
 // walls, and the fine-coarse flux correction (Parthenon Sec. 3.7).
 #pragma once
 
-#include "pkh_internal.h"
-#include "pkh_physics.h"
+#include "pkh_device.h"
 
 namespace pkh {
 
@@ -27,60 +26,69 @@ __device__ __forceinline__ int64_t pad_index(const Geom& g, int i, int j, int k)
   return ((int64_t)(k + NG) * g.p2 + (j + NG)) * g.p1 + (i + NG);
 }
 
-// Composite value at level L of a global cell J inside the domain, all five
-// variables: leaf value at level L; restriction of the level-(L+1) leaves;
-// or, while regridding, the containing coarser cell (injection).
-__device__ inline void comp_val_inside(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g,
-                                int L, const int J[3], double out[NV], int* err) {
+// Where the composite value at level L of a global cell J inside the domain
+// lives: x the leaf, y the padded index of the cell in it (LOC_CELL bits) —
+// the cell of the leaf at level L, or while regridding the containing cell
+// of a coarser leaf (injection) — or, with LOC_RESTRICT set, the first of
+// the 8 level-(L+1) cells whose mean it is (they lie in one leaf: blocks
+// have even edges). x = LOC_NONE when the mesh has no such cell. Bits 29-31
+// of y are free for the caller (the image's reflected directions).
+constexpr unsigned LOC_NONE = 0xffffffffu, LOC_RESTRICT = 1u << 28, LOC_CELL = LOC_RESTRICT - 1u;
+
+__device__ inline uint2 comp_loc(const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L, const int J[3]) {
   const int n[3] = {g.n1, g.n2, g.n3};
   const int b[3] = {J[0] / n[0], J[1] / n[1], J[2] / n[2]};
   int32_t id = leaf_at(M, L, b[0], b[1], b[2]);
-  if (id >= 0) {
-    const double* c = u + (int64_t)id * g.bstride +
-                      pad_index(g, J[0] - b[0] * n[0], J[1] - b[1] * n[1], J[2] - b[2] * n[2]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = c[v * g.vstride];
-    return;
-  }
+  if (id >= 0)
+    return make_uint2((unsigned)id,
+                      (unsigned)pad_index(g, J[0] - b[0] * n[0], J[1] - b[1] * n[1], J[2] - b[2] * n[2]));
   for (int Lc = L - 1; Lc >= 0; --Lc) {
     const int sh = L - Lc;
     id = leaf_at(M, Lc, b[0] >> sh, b[1] >> sh, b[2] >> sh);
     if (id >= 0) {
       const BlockInfo bc = blocks[id];
-      const double* c = u + (int64_t)id * g.bstride +
-                        pad_index(g, (J[0] >> sh) - bc.lx * n[0], (J[1] >> sh) - bc.ly * n[1],
-                                  (J[2] >> sh) - bc.lz * n[2]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = c[v * g.vstride];
-      return;
+      return make_uint2((unsigned)id, (unsigned)pad_index(g, (J[0] >> sh) - bc.lx * n[0],
+                                                          (J[1] >> sh) - bc.ly * n[1], (J[2] >> sh) - bc.lz * n[2]));
     }
   }
-  if (L + 1 > M.maxl) {
+  if (L + 1 > M.maxl) return make_uint2(LOC_NONE, 0u);
+  const int F0 = 2 * J[0], F1 = 2 * J[1], F2 = 2 * J[2];
+  const int32_t fid = leaf_at(M, L + 1, F0 / n[0], F1 / n[1], F2 / n[2]);
+  if (fid < 0) return make_uint2(LOC_NONE, 0u);
+  const BlockInfo bf = blocks[fid];
+  return make_uint2((unsigned)fid,
+                    (unsigned)pad_index(g, F0 - bf.lx * n[0], F1 - bf.ly * n[1], F2 - bf.lz * n[2]) | LOC_RESTRICT);
+}
+
+// The five values at a location from comp_loc: the cell's, or the mean of
+// the 8 fine cells summed in pairs along x, then y, then z.
+__device__ __forceinline__ void comp_gather(const double* u, const Geom& g, uint2 e, double out[NV], int* err) {
+  if (e.x == LOC_NONE) {
     *err = 1;
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] = 0.0;
     return;
   }
-  const double* fc[8];
+  const double* c = u + (int64_t)e.x * g.bstride + (e.y & LOC_CELL);
+  if (!(e.y & LOC_RESTRICT)) {
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int F0 = 2 * J[0] + (c & 1), F1 = 2 * J[1] + ((c >> 1) & 1), F2 = 2 * J[2] + ((c >> 2) & 1);
-    const int32_t fid = leaf_at(M, L + 1, F0 / n[0], F1 / n[1], F2 / n[2]);
-    if (fid < 0) {
-      *err = 1;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = 0.0;
-      return;
-    }
-    const BlockInfo bf = blocks[fid];
-    fc[c] = u + (int64_t)fid * g.bstride + pad_index(g, F0 - bf.lx * n[0], F1 - bf.ly * n[1], F2 - bf.lz * n[2]);
+    for (int v = 0; v < NV; ++v) out[v] = c[v * g.vstride];
+    return;
   }
+  const int64_t sx = 1, sy = g.p1, sz = (int64_t)g.p1 * g.p2;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const int64_t o = (int64_t)v * g.vstride;
-    out[v] = 0.125 * (((fc[0][o] + fc[1][o]) + (fc[2][o] + fc[3][o])) +
-                      ((fc[4][o] + fc[5][o]) + (fc[6][o] + fc[7][o])));
+    const double* f = c + (int64_t)v * g.vstride;
+    out[v] = 0.125 * (((f[0] + f[sx]) + (f[sy] + f[sy + sx])) + ((f[sz] + f[sz + sx]) + (f[sz + sy] + f[sz + sy + sx])));
   }
+}
+
+// Composite value at level L of a global cell J inside the domain, all five
+// variables: leaf value at level L; restriction of the level-(L+1) leaves;
+// or, while regridding, the containing coarser cell (injection).
+__device__ inline void comp_val_inside(const double* u, const BlockInfo* blocks, const LevelMaps& M, const Geom& g,
+                                int L, const int J[3], double out[NV], int* err) {
+  comp_gather(u, g, comp_loc(blocks, M, g, L, J), out, err);
 }
 
 // Global cell J of level L (at most one domain length outside) brought into
@@ -152,46 +160,85 @@ __device__ inline void prolong_val(const double* u, const BlockInfo* blocks, con
   for (int v = 0; v < NV; ++v) out[v] = c0[v] + 0.25 * ((t[0][v] + t[1][v]) + t[2][v]);
 }
 
-// Restriction at level L, global cell J (in range): the 8 level-(L+1)
-// cells below it lie in one fine leaf (blocks have even edges), so the leaf
-// is looked up once; the sum is paired as in comp_val.
-__device__ __forceinline__ void restrict_val(const double* u, const BlockInfo* blocks, const LevelMaps& M,
-                                             const Geom& g, int L, const int J[3], double out[NV], int* err) {
+// Location of the restriction at level L of global cell J (in range): the 8
+// level-(L+1) cells below it lie in one fine leaf (blocks have even edges),
+// so the leaf is looked up once.
+__device__ __forceinline__ uint2 restrict_loc(const BlockInfo* blocks, const LevelMaps& M, const Geom& g, int L,
+                                              const int J[3]) {
   const int F[3] = {2 * J[0], 2 * J[1], 2 * J[2]};
   const int32_t fid = leaf_at(M, L + 1, F[0] / g.n1, F[1] / g.n2, F[2] / g.n3);
-  if (fid < 0) {
-    *err = 1;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = 0.0;
-    return;
-  }
+  if (fid < 0) return make_uint2(LOC_NONE, 0u);
   const BlockInfo bf = blocks[fid];
-  const double* f = u + (int64_t)fid * g.bstride +
-                    pad_index(g, F[0] - bf.lx * g.n1, F[1] - bf.ly * g.n2, F[2] - bf.lz * g.n3);
-  const int64_t sx = 1, sy = g.p1, sz = (int64_t)g.p1 * g.p2;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const double* c = f + (int64_t)v * g.vstride;
-    out[v] = 0.125 * (((c[0] + c[sx]) + (c[sy] + c[sy + sx])) + ((c[sz] + c[sz + sx]) + (c[sz + sy] + c[sz + sy + sx])));
-  }
+  return make_uint2((unsigned)fid,
+                    (unsigned)pad_index(g, F[0] - bf.lx * g.n1, F[1] - bf.ly * g.n2, F[2] - bf.lz * g.n3) | LOC_RESTRICT);
 }
 
 // The face regions (width 2, active transverse extent) listed in jf as
-// (leaf, face | wall kind << 3) pairs: the faces whose neighbour is on
-// another level or beyond a wall, the only ghost cells the stage kernels
-// read. Across a level jump, the region across one face is
+// (leaf, face | wall kind << 3 | coarser << 6) pairs: the faces whose
+// neighbour is on another level or beyond a wall, the only ghost cells the
+// stage kernels read. Across a level jump, the region across one face is
 // one block of the leaf's level, so a face is either wholly inside a
-// coarser leaf or wholly refined. Coarser: the 2-deep slab is one coarse
-// cell deep and aligned to coarse cells; eight lanes share one coarse
-// cell: lane l forms the composite value of stencil point l (the cell, then
-// its -x, +x, -y, +y, -z, +z neighbours; lane 7 repeats the cell), the
-// lanes swap them by shuffles, and lane o writes fine child o. Refined: one
-// thread per ghost cell, restriction of its 8 fine cells.
-// One 256-thread workgroup's share of it: face record f, cells from 256 x.
-__device__ inline void fill_faces_item(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& M,
-                                       DevTime* tm, const int32_t* __restrict__ jf, int x, int f) {
+// coarser leaf (bit 6) or wholly refined. Coarser: the 2-deep slab is one
+// coarse cell deep and aligned to coarse cells; eight lanes share one
+// coarse cell: lane l forms the composite value of stencil point l (the
+// cell, then its -x, +x, -y, +y, -z, +z neighbours; lane 7 repeats the
+// cell), the lanes swap them by shuffles, and lane o writes fine child o.
+// Refined: one thread per ghost cell, restriction of its 8 fine cells.
+// Threads per face record: fill_faces_stride(g), 256 per workgroup.
+
+// Thread q of face record f: the level-jump case of the record, the ghost
+// cell (coarser: the first of its group's 2x2x2 children) and where the
+// value this thread reads lives, as comp_loc encodes it with the image's
+// reflected directions in bits 29-31. False for a wall record or a thread
+// with no cell.
+__device__ inline bool fill_faces_loc(const BlockInfo* blocks, const Geom& g, const LevelMaps& M, int2 rec, int q,
+                                      uint2* loc) {
+  const int b = rec.x, d = (rec.y & 7) >> 1, hi = rec.y & 1, wall = (rec.y >> 3) & 7;
+  if (wall) return false;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const BlockInfo bi = blocks[b];
+  const int L = bi.level;
+  const int lo[3] = {bi.lx, bi.ly, bi.lz};
+  int c[3];
+  if ((rec.y >> 6) & 1) {
+    const int m1 = n[t1] >> 1, m2 = n[t2] >> 1;
+    const int cq = q >> 3, l = q & 7;
+    if (cq >= m1 * m2) return false;
+    c[t1] = 2 * (cq % m1);
+    c[t2] = 2 * (cq / m1);
+    c[d] = hi ? n[d] : -NG;
+    int J[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) J[e] = wrap_i(lo[e] * n[e] + c[e], (g.nrb[e] * n[e]) << L) >> 1;
+    const int se = (l - 1) >> 1, sg = (l & 1) ? -1 : 1;  // lanes 1..6: axis and side
+    if (l != 0 && l != 7) J[se] += sg;
+    const int code = cell_in_domain(g, L - 1, J);
+    const uint2 e = comp_loc(blocks, M, g, L - 1, J);
+    *loc = make_uint2(e.x, e.y | (unsigned)(code & 7) << 29);
+    return true;
+  }
+  const int area = n[t1] * n[t2];
+  if (q >= 2 * area) return false;
+  const int s = q / area, r = q - s * area;
+  c[t1] = r % n[t1];
+  c[t2] = r / n[t1];
+  c[d] = hi ? n[d] + s : s - NG;
+  int J[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) J[e] = wrap_i(lo[e] * n[e] + c[e], (g.nrb[e] * n[e]) << L);
+  *loc = restrict_loc(blocks, M, g, L, J);
+  return true;
+}
+
+// One 256-thread workgroup's share of face record f: cells from 256 x.
+// plan: the locations fill_faces_loc gives, fill_faces_stride per record,
+// built once per mesh layout, so a thread's reads wait on one load of its
+// location instead of a walk through the block list and level maps.
+__device__ inline void fill_faces_item(double* u, const Geom& g, DevTime* tm, const int32_t* __restrict__ jf,
+                                       const uint2* __restrict__ plan, int x, int f) {
   const int2 rec = reinterpret_cast<const int2*>(jf)[f];
-  const int b = rec.x, d = (rec.y & 7) >> 1, hi = rec.y & 1, wall = rec.y >> 3;
+  const int b = rec.x, d = (rec.y & 7) >> 1, hi = rec.y & 1, wall = (rec.y >> 3) & 7;
   const int n[3] = {g.n1, g.n2, g.n3};
   const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
   const int q = x * 256 + (int)threadIdx.x;
@@ -220,13 +267,8 @@ __device__ inline void fill_faces_item(double* u, const BlockInfo* blocks, const
     }
     return;
   }
-  const BlockInfo bi = blocks[b];
-  const int L = bi.level;
-  int bl[3] = {bi.lx, bi.ly, bi.lz};
-  bl[d] = wrap_i(bl[d] + (hi ? 1 : -1), g.nrb[d] << L);
-  const bool coarser = L > 0 && leaf_at(M, L - 1, bl[0] >> 1, bl[1] >> 1, bl[2] >> 1) >= 0;
   int err = 0;
-  if (coarser) {
+  if ((rec.y >> 6) & 1) {
     // Uniform per workgroup (one face per item): whole 8-lane groups
     // leave together, so the shuffles below see only live groups.
     const int m1 = n[t1] >> 1, m2 = n[t2] >> 1;
@@ -236,17 +278,10 @@ __device__ inline void fill_faces_item(double* u, const BlockInfo* blocks, const
     c[t1] = 2 * (cq % m1);
     c[t2] = 2 * (cq / m1);
     c[d] = hi ? n[d] : -NG;
-    int I[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const int lo = e == 0 ? bi.lx : (e == 1 ? bi.ly : bi.lz);
-      I[e] = wrap_i(lo * n[e] + c[e], (g.nrb[e] * n[e]) << L) >> 1;
-    }
-    const int se = (l - 1) >> 1, sg = (l & 1) ? -1 : 1;  // lanes 1..6: axis and side
-    const bool ctr = l == 0 || l == 7;
+    const uint2 e = plan[(int64_t)f * fill_faces_stride(g) + q];
     double val[NV];
-    comp_val(u, blocks, M, g, L - 1, I[0] + (!ctr && se == 0 ? sg : 0), I[1] + (!ctr && se == 1 ? sg : 0),
-             I[2] + (!ctr && se == 2 ? sg : 0), val, &err);
+    comp_gather(u, g, e, val, &err);
+    apply_image_signs((int)(e.y >> 29), val);
     const int base = threadIdx.x & ~7 & 63;
     const int o = l;
     double outv[NV];
@@ -276,11 +311,9 @@ __device__ inline void fill_faces_item(double* u, const BlockInfo* blocks, const
     c[t1] = r % n[t1];
     c[t2] = r / n[t1];
     c[d] = hi ? n[d] + s : s - NG;
-    const int J[3] = {wrap_i(bi.lx * n[0] + c[0], (g.nrb[0] * n[0]) << L),
-                      wrap_i(bi.ly * n[1] + c[1], (g.nrb[1] * n[1]) << L),
-                      wrap_i(bi.lz * n[2] + c[2], (g.nrb[2] * n[2]) << L)};
+    const uint2 e = plan[(int64_t)f * fill_faces_stride(g) + q];
     double val[NV];
-    restrict_val(u, blocks, M, g, L, J, val, &err);
+    comp_gather(u, g, e, val, &err);
     double* dst = ub + pad_index(g, c[0], c[1], c[2]);
 #pragma unroll
     for (int v = 0; v < NV; ++v) dst[v * g.vstride] = val[v];
@@ -399,7 +432,7 @@ __device__ inline void flux_correct_item(double* u, const BlockInfo* blocks, con
     __syncthreads();
     if (threadIdx.x == 0) {
       const double mx = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
-      atomicMax(&tm->smax_bits, (unsigned long long)__double_as_longlong(mx));
+      reduce_max_speed(tm, mx);
     }
   }
   if (bad) atomicOr(&tm->err, 1);

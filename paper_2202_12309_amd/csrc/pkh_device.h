@@ -7,6 +7,16 @@
 
 namespace pkh {
 
+// Fold a workgroup's largest signal speed per cell width (mx >= 0) into the
+// cycle's CFL reduction. Non-negative doubles order like their bit
+// patterns; the maximum only grows within a cycle, so a workgroup whose
+// value is already covered skips the atomic: launches with many
+// workgroups would otherwise queue thousands of atomics on one address.
+__device__ __forceinline__ void reduce_max_speed(DevTime* tm, double mx) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(mx);
+  if (__hip_atomic_load(&tm->smax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) atomicMax(&tm->smax_bits, b);
+}
+
 // Padded index of cell (i, j, k) of block b, the cell at most one face step
 // outside the block (-2 <= i < n1 + 2 with j, k active, and likewise for y
 // and z): a cell beyond the block comes from the active cells of the

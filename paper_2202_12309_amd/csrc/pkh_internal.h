@@ -135,7 +135,7 @@ struct PInst {
   const int32_t* ff_first;
   const int32_t* cblocks;
   const int32_t* jf;       // ghost face records
-  LevelMaps maps;
+  const uint2* plan;       // their fill plan
   int32_t cnt[PPHASES];    // items of each phase in one cycle
   int32_t last;            // last phase with items (its end closes the cycle)
   int32_t n1;              // block width: 16 (16-row tiles) or 32 (8-row tiles)
@@ -182,8 +182,21 @@ hipError_t probe_xcc(int32_t* dev_buf, int32_t* out_host, hipStream_t s);
 
 // Ghost face regions of the (leaf, face) pairs jf[2 njf] (faces whose
 // neighbour is on another level).
-hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
-                             DevTime* tm, const int32_t* jf, int32_t njf, hipStream_t s);
+// Threads per ghost-face record of the face fill (two cell layers of the
+// largest face, whole 256-thread workgroups).
+__host__ __device__ inline int fill_faces_stride(const Geom& g) {
+  const int a01 = g.n1 * g.n2, a02 = g.n1 * g.n3, a12 = g.n2 * g.n3;
+  const int area = a01 > a02 ? (a01 > a12 ? a01 : a12) : (a02 > a12 ? a02 : a12);
+  return (2 * area + 255) / 256 * 256;
+}
+
+// Ghost faces of the records jf (leaf, face | wall kind << 3 | coarser
+// neighbour << 6); plan from launch_fill_plan on the same tables,
+// njf * fill_faces_stride(g) locations of 8 bytes.
+hipError_t launch_fill_faces(double* u, const Geom& g, DevTime* tm, const int32_t* jf, const uint2* plan,
+                             int32_t njf, hipStream_t s);
+hipError_t launch_fill_plan(uint2* plan, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
+                            const int32_t* jf, int32_t njf, hipStream_t s);
 // skip_same: leave ghost cells whose source is a same-level leaf alone
 // (the stage kernels already wrote them).
 hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,

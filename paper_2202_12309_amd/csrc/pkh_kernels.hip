@@ -20,9 +20,11 @@
 #include "pkh_amr.h"
 #include "pkh_device.h"
 
-// waves per SIMD the reverse pencils are compiled for
+// waves per SIMD the reverse pencils are compiled for: at 1 they take 412
+// VGPRs without spilling; at 2 the 256-register cap spills (156 B a lane)
+// and a reverse stage of the 128^3 workload took 20 % longer
 #ifndef PKH_ADJ_PENCIL_WAVES
-#define PKH_ADJ_PENCIL_WAVES 2
+#define PKH_ADJ_PENCIL_WAVES 1
 #endif
 
 namespace pkh {
@@ -104,17 +106,37 @@ __global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* b
   fill_cell(u, blocks, g, M, tm, b, i, j, k, skip_same);
 }
 
-__global__ void __launch_bounds__(256) fill_faces_kernel(double* u, const BlockInfo* blocks, Geom g, LevelMaps M,
-                                                         DevTime* tm, const int32_t* __restrict__ jf) {
-  fill_faces_item(u, blocks, g, M, tm, jf, blockIdx.x, blockIdx.y);
+__global__ void __launch_bounds__(256) fill_faces_kernel(double* u, Geom g, DevTime* tm,
+                                                         const int32_t* __restrict__ jf,
+                                                         const uint2* __restrict__ plan) {
+  fill_faces_item(u, g, tm, jf, plan, blockIdx.x, blockIdx.y);
 }
 
-hipError_t launch_fill_faces(double* u, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
-                             DevTime* tm, const int32_t* jf, int32_t njf, hipStream_t s) {
+hipError_t launch_fill_faces(double* u, const Geom& g, DevTime* tm, const int32_t* jf, const uint2* plan,
+                             int32_t njf, hipStream_t s) {
   if (njf <= 0) return hipSuccess;
-  const int area = std::max(std::max(g.n1 * g.n2, g.n1 * g.n3), g.n2 * g.n3);
-  dim3 grid((2 * area + 255) / 256, njf);
-  hipLaunchKernelGGL(fill_faces_kernel, grid, dim3(256), 0, s, u, blocks, g, maps, tm, jf);
+  dim3 grid(fill_faces_stride(g) / 256, njf);
+  hipLaunchKernelGGL(fill_faces_kernel, grid, dim3(256), 0, s, u, g, tm, jf, plan);
+  return hipGetLastError();
+}
+
+// The face-fill plan: for every thread of every face record, the location
+// its value is read from (fill_faces_loc), so the fill after each stage
+// reads it instead of walking the level maps. Threads with no cell get
+// LOC_NONE.
+__global__ void __launch_bounds__(256) fill_plan_kernel(uint2* plan, const BlockInfo* blocks, Geom g, LevelMaps M,
+                                                        const int32_t* __restrict__ jf) {
+  const int f = blockIdx.y, q = blockIdx.x * 256 + threadIdx.x;
+  uint2 e = make_uint2(LOC_NONE, 0u);
+  fill_faces_loc(blocks, g, M, reinterpret_cast<const int2*>(jf)[f], q, &e);
+  plan[(int64_t)f * fill_faces_stride(g) + q] = e;
+}
+
+hipError_t launch_fill_plan(uint2* plan, const BlockInfo* blocks, const Geom& g, const LevelMaps& maps,
+                            const int32_t* jf, int32_t njf, hipStream_t s) {
+  if (njf <= 0) return hipSuccess;
+  dim3 grid(fill_faces_stride(g) / 256, njf);
+  hipLaunchKernelGGL(fill_plan_kernel, grid, dim3(256), 0, s, plan, blocks, g, maps, jf);
   return hipGetLastError();
 }
 
@@ -248,7 +270,7 @@ __global__ void __launch_bounds__(256) dt_kernel(const S* u, const BlockInfo* bl
   __syncthreads();
   if (threadIdx.x == 0) {
     const double mx = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
-    atomicMax(&tm->smax_bits, (unsigned long long)__double_as_longlong(mx));
+    reduce_max_speed(tm, mx);
   }
   if (bad) atomicOr(&tm->err, 1);
 }
@@ -524,9 +546,83 @@ __global__ void __launch_bounds__(256) eta_kernel(double* eta, const double* u, 
   if (threadIdx.x == 0) eta[b] = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
 }
 
+// The same indicator with each cell's quantity evaluated once: the
+// workgroup walks the block's z planes and keeps three planes of q (each
+// with its one-cell x/y face ring) in LDS, so a cell's six neighbours are
+// LDS reads instead of six evaluations from memory. The same expressions
+// in the same order give the same bits as eta_kernel.
+__device__ __forceinline__ double eta_q(const double* u, const int32_t* nbr, const Geom& g, int b, int i, int j,
+                                        int k, int quantity, double gm1) {
+  const double* c = u + nb_index(g, nbr, b, i, j, k);
+  return quantity ? c[0] : pressure_nc(c, g.vstride, gm1);
+}
+
+__global__ void __launch_bounds__(256) eta_planes_kernel(double* eta, const double* u, const int32_t* nbr, Geom g,
+                                                         int quantity) {
+#pragma clang fp contract(off)
+  extern __shared__ double sq[];  // 3 planes of (n1 + 2) x (n2 + 2)
+  __shared__ double sRed[4];
+  const int b = blockIdx.x;
+  const int r1 = g.n1 + 2, pl = r1 * (g.n2 + 2);
+  const int ring = 2 * g.n1 + 2 * g.n2;
+  const double gm1 = g.gamma - 1.0;
+  // q of plane k: its active cells, plus the x/y face ring when `ring` is
+  // set (only the plane being evaluated needs it), into slot (k + 3) % 3
+  auto fill = [&](int k, bool with_ring) {
+    double* dst = sq + ((k + 3) % 3) * pl;
+    const int ncell = g.n1 * g.n2 + (with_ring ? ring : 0);
+    for (int q = threadIdx.x; q < ncell; q += 256) {
+      int i, j;
+      if (q < g.n1 * g.n2) {
+        i = q % g.n1;
+        j = q / g.n1;
+      } else {
+        const int r = q - g.n1 * g.n2;
+        if (r < 2 * g.n1) {
+          i = r % g.n1;
+          j = r < g.n1 ? -1 : g.n2;
+        } else {
+          const int t = r - 2 * g.n1;
+          j = t % g.n2;
+          i = t < g.n2 ? -1 : g.n1;
+        }
+      }
+      dst[(j + 1) * r1 + (i + 1)] = eta_q(u, nbr, g, b, i, j, k, quantity, gm1);
+    }
+  };
+  fill(-1, false);
+  fill(0, true);
+  double mx = 0.0;
+  for (int k = 0; k < g.n3; ++k) {
+    fill(k + 1, k + 1 < g.n3);  // the ring of plane k + 1 is needed when it is evaluated
+    __syncthreads();
+    const double* qm = sq + ((k + 2) % 3) * pl;
+    const double* q0 = sq + (k % 3) * pl;
+    const double* qp = sq + ((k + 1) % 3) * pl;
+    for (int q = threadIdx.x; q < g.n1 * g.n2; q += 256) {
+      const int i = q % g.n1, j = q / g.n1;
+      const int c = (j + 1) * r1 + (i + 1);
+      const double px[3] = {q0[c + 1], q0[c + r1], qp[c]};
+      const double pm[3] = {q0[c - 1], q0[c - r1], qm[c]};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) mx = fmax(mx, fabs(px[d] - pm[d]) / (px[d] + pm[d]));
+    }
+    __syncthreads();  // plane k - 1's slot is refilled next
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) eta[b] = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
+}
+
 hipError_t launch_eta(double* eta, const double* u, const int32_t* nbr, int32_t nblocks, const Geom& g,
                       int32_t quantity, hipStream_t s) {
-  hipLaunchKernelGGL(eta_kernel, dim3(nblocks), dim3(256), 0, s, eta, u, nbr, g, (int)quantity);
+  const size_t lds = 3 * sizeof(double) * (size_t)(g.n1 + 2) * (g.n2 + 2);
+  if (lds <= 48 * 1024)
+    hipLaunchKernelGGL(eta_planes_kernel, dim3(nblocks), dim3(256), lds, s, eta, u, nbr, g, (int)quantity);
+  else
+    hipLaunchKernelGGL(eta_kernel, dim3(nblocks), dim3(256), 0, s, eta, u, nbr, g, (int)quantity);
   return hipGetLastError();
 }
 
@@ -1433,7 +1529,7 @@ __global__ void __launch_bounds__(256) adjf_ghost_kernel(const double* __restric
                                                          const BlockInfo* blocks, Geom g, LevelMaps M, DevTime* tm,
                                                          const int32_t* __restrict__ jf) {
   const int2 rec = reinterpret_cast<const int2*>(jf)[blockIdx.y];
-  const int b = rec.x, d = (rec.y & 7) >> 1, hi = rec.y & 1, wall = rec.y >> 3;
+  const int b = rec.x, d = (rec.y & 7) >> 1, hi = rec.y & 1, wall = (rec.y >> 3) & 7;
   const int n[3] = {g.n1, g.n2, g.n3};
   const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
   const int area = n[t1] * n[t2];

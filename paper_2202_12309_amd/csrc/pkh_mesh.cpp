@@ -200,6 +200,7 @@ struct pkh_mesh {
   int32_t* d_nbr = nullptr;   // [leaf][27] same-level neighbours (-1: other level)
   bool need_fill = false;     // some ghost region has a neighbour at another level
   int32_t* d_jf = nullptr;    // (leaf, face) pairs whose face neighbour is on another level
+  uint2* d_plan = nullptr;    // where each ghost-face thread reads (launch_fill_plan)
   int32_t njf = 0;
   // virtual partition into contiguous leaf ranges: same-level faces between
   // parts go through pack / transfer / unpack instead of direct reads
@@ -269,6 +270,7 @@ void free_cycle_tables(pkh_mesh* m) {
   m->dfree(m->d_ff_first);
   m->dfree(m->d_cblocks);
   m->dfree(m->d_jf);
+  m->dfree(m->d_plan);
   m->dfree(m->d_nbr);
   m->dfree(m->d_rf);
   m->dfree(m->d_send);
@@ -278,6 +280,7 @@ void free_cycle_tables(pkh_mesh* m) {
   m->d_ff_first = nullptr;
   m->d_cblocks = nullptr;
   m->d_jf = nullptr;
+  m->d_plan = nullptr;
   m->d_nbr = nullptr;
   m->d_rf = nullptr;
   m->d_send = nullptr;
@@ -402,8 +405,11 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
         int64_t c[3] = {l.lx1, l.lx2, l.lx3};
         c[f >> 1] += (f & 1) ? 1 : -1;
         const int kind = t.inside(l.level, c[0], c[1], c[2]) ? 0 : m->cfg.bc[f];
+        // a level jump to a coarser leaf (2:1 balance: one level up), else
+        // a refined face (t.inside above wrapped c along periodic axes)
+        const int coarser = kind == 0 && l.level > 0 && t.at(l.level - 1, c[0] >> 1, c[1] >> 1, c[2] >> 1) >= 0;
         jf.push_back((int32_t)b);
-        jf.push_back(f | kind << 3);
+        jf.push_back(f | kind << 3 | coarser << 6);
       }
   }
   // remote faces of a partitioned mesh: a same-level face neighbour in another
@@ -457,6 +463,11 @@ int build_tables(pkh_mesh* m, std::vector<BlockInfo>& hb, int32_t** dmap, LevelM
     m->need_fill = need_fill;
     m->njf = (int32_t)(jf.size() / 2);
     if (m->njf && (rc = upload_vec(m, &m->d_jf, jf))) return rc;
+    if (m->njf) {
+      m->d_plan = (uint2*)m->dalloc((size_t)m->njf * fill_faces_stride(m->g) * sizeof(uint2));
+      if (!m->d_plan) return fail(PKH_ENOMEM, "face-fill plan allocation failed");
+      HIPCHK(launch_fill_plan(m->d_plan, m->d_blocks, m->g, lm, m->d_jf, m->njf, m->stream));
+    }
     m->nrf = (int32_t)rf.size();
     m->msgs = msgs;
     m->rf_slot = 2 * (int64_t)NV * std::max({m->g.n1 * m->g.n2, m->g.n1 * m->g.n3, m->g.n2 * m->g.n3});
@@ -599,7 +610,7 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
   if ((rc = exchange_remote(m, m->B, capturing))) return rc;
   if (m->njf) {  // ghost faces across level jumps (same-level halos are read directly)
     KTimer kt(m, 2, capturing);
-    HIPCHK(launch_fill_faces(m->B, m->d_blocks, m->g, m->maps, m->d_time, m->d_jf, m->njf, m->stream));
+    HIPCHK(launch_fill_faces(m->B, m->g, m->d_time, m->d_jf, m->d_plan, m->njf, m->stream));
   }
   // corrector: U^{n+1} = U^n - dt D_PLM(U*), in place; CFL reduction fused
   s.uin = m->B;
@@ -621,7 +632,7 @@ int enqueue_cycle(pkh_mesh* m, int mode_after, double t_end, bool capturing = fa
   if ((rc = exchange_remote(m, m->A, capturing))) return rc;
   if (m->njf) {
     KTimer kt(m, 2, capturing);
-    HIPCHK(launch_fill_faces(m->A, m->d_blocks, m->g, m->maps, m->d_time, m->d_jf, m->njf, m->stream));
+    HIPCHK(launch_fill_faces(m->A, m->g, m->d_time, m->d_jf, m->d_plan, m->njf, m->stream));
   }
   HIPCHK(launch_clock(m->d_time, mode_after, t_end, m->stream));
   return PKH_OK;
@@ -1236,7 +1247,7 @@ int tape_recompute(pkh_tape* t, int c0, int len) {
                                                m->g, t->d_time, beta, 0, m->d_fbuf, m->d_nbr, m->stream);
       if (e != hipSuccess) return e;
     }
-    if (m->njf) return launch_fill_faces(u, m->d_blocks, m->g, m->maps, t->d_time, m->d_jf, m->njf, m->stream);
+    if (m->njf) return launch_fill_faces(u, m->g, t->d_time, m->d_jf, m->d_plan, m->njf, m->stream);
     return hipSuccess;
   };
   for (int q = 0; q < len; ++q) {
@@ -1515,7 +1526,7 @@ int batch_level_jumps(pkh_batch* b, bool corrector) {
       HIPCHK(launch_flux_correct(u, m->d_blocks, m->d_ff, m->d_ff_first, m->d_cblocks, m->ncblocks, m->g,
                                  m->d_time, corrector ? 1.0 : 0.5, corrector ? 1 : 0, m->d_fbuf, m->d_nbr,
                                  b->stream));
-    if (m->njf) HIPCHK(launch_fill_faces(u, m->d_blocks, m->g, m->maps, m->d_time, m->d_jf, m->njf, b->stream));
+    if (m->njf) HIPCHK(launch_fill_faces(u, m->g, m->d_time, m->d_jf, m->d_plan, m->njf, b->stream));
   }
   return PKH_OK;
 }
@@ -1618,7 +1629,7 @@ int batch_build_persistent(pkh_batch* b, const std::vector<StageLaunch>& pred,
       pi.ff_first = m->d_ff_first;
       pi.cblocks = m->d_cblocks;
       pi.jf = m->d_jf;
-      pi.maps = m->maps;
+      pi.plan = m->d_plan;
       pi.n1 = m->g.n1;
       const int tj = persistent_tile_rows(m->g.n1);
       for (int32_t blk = 0; blk < (int32_t)m->nb(); ++blk)
@@ -1635,8 +1646,7 @@ int batch_build_persistent(pkh_batch* b, const std::vector<StageLaunch>& pred,
           per[4].push_back(PItem{q, 4, x, c});
         }
       pi.cnt[1] = pi.cnt[4] = m->ncblocks * nfc;
-      const int area = std::max(std::max(m->g.n1 * m->g.n2, m->g.n1 * m->g.n3), m->g.n2 * m->g.n3);
-      const int nff = (2 * area + 255) / 256;
+      const int nff = fill_faces_stride(m->g) / 256;
       for (int32_t f = 0; f < m->njf; ++f)
         for (int32_t x = 0; x < nff; ++x) {
           per[2].push_back(PItem{q, 2, x, f});

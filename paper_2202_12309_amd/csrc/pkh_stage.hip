@@ -524,7 +524,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     if (tid == 0) {
       double mx = sRed[0];
       for (int q = 1; q < NWAVE; ++q) mx = fmax(mx, sRed[q]);
-      atomicMax(&a.tm->smax_bits, (unsigned long long)__double_as_longlong(mx));
+      reduce_max_speed(a.tm, mx);
     }
   }
   if (bad) atomicOr(&a.tm->err, 1);
@@ -598,9 +598,11 @@ __global__ void __launch_bounds__(N1 * TJ, (stage_waves<RECON, N1, TJ>())) stage
 // complete, then thread 0 makes them visible at device scope (release)
 // before the item is counted, and a consumer's thread 0 acquires at device
 // scope after its wait. Pinning an instance to one XCD keeps its blocks in
-// one L2 between items; the fences stay device-scope all the same (a
-// variant that only dropped the CU's L1 at the acquire gave wrong results
-// and is not kept).
+// one L2 between items; the fences stay device-scope all the same:
+// variants whose acquire only dropped the CU's L1 (with the release at
+// device scope or only the stores' completion) gave wrong results on
+// small instances after a few cycles, so the pinning alone does not make
+// an instance's items see each other's stores, and they are not kept.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ unsigned int ld_relaxed(const unsigned int* p) {
@@ -724,7 +726,7 @@ __global__ void __launch_bounds__(256, W)
                           it.a, it.b, s_red);
       } else {
         const StageLaunch& a = in.st[ph == 5];
-        fill_faces_item(static_cast<double*>(a.uout), a.blocks, a.g, in.maps, a.tm, in.jf, it.a, it.b);
+        fill_faces_item(static_cast<double*>(a.uout), a.g, a.tm, in.jf, in.plan, it.a, it.b);
       }
       // every thread's stores complete, then one release before the item
       // is counted

@@ -355,13 +355,13 @@ def test_tile_rows_do_not_change_results(case):
 
 def test_full_size_bench_configuration_parity():
     """The bench workload itself: 256^3 in 512 blocks of 32^3, the default
-    launch tiles (16 rows for both stages), against the oracle
+    launch tiles (8 rows for the corrector, 16 for the predictor), against the oracle
     element by element after 1, 10 and 100 cycles (about a minute of oracle
     time on 16 threads); clock and totals too."""
     print_case("256^3 turbulent box, 512 blocks of 32^3, bench launch configuration, 100 cycles")
     n, N = (32, 32, 32), 256
     gm, om, nrb = _pair((N, N, N), n, inputs.uniform_leaves((8, 8, 8)))
-    assert gm.tuning()["tile_rows"] == 16
+    assert gm.tuning()["tile_rows"] == 8  # the corrector's default on 32-cell rows
     U0 = inputs.turbulent_box(gm.leaves(), n, nrb, seed=2)
     gm.upload(U0)
     om.set_state(U0)
