@@ -220,7 +220,8 @@ __device__ inline bool fill_faces_loc(const BlockInfo* blocks, const Geom& g, co
   }
   const int area = n[t1] * n[t2];
   if (q >= 2 * area) return false;
-  const int s = q / area, r = q - s * area;
+  // x faces: the two layers of a row on neighbouring lanes (one cache line)
+  const int s = d == 0 ? (q & 1) : q / area, r = d == 0 ? (q >> 1) : q - s * area;
   c[t1] = r % n[t1];
   c[t2] = r / n[t1];
   c[d] = hi ? n[d] + s : s - NG;
@@ -249,7 +250,8 @@ __device__ inline void fill_faces_item(double* u, const Geom& g, DevTime* tm, co
     // reflection, normal momentum negated)
     const int area = n[t1] * n[t2];
     if (q >= 2 * area) return;
-    const int s = q / area, r = q - s * area;
+    // x faces: the two layers of a row on neighbouring lanes (one cache line)
+    const int s = d == 0 ? (q & 1) : q / area, r = d == 0 ? (q >> 1) : q - s * area;
     int c[3], src[3];
     c[t1] = src[t1] = r % n[t1];
     c[t2] = src[t2] = r / n[t1];
@@ -306,7 +308,8 @@ __device__ inline void fill_faces_item(double* u, const Geom& g, DevTime* tm, co
   } else {
     const int area = n[t1] * n[t2];
     if (q >= 2 * area) return;
-    const int s = q / area, r = q - s * area;
+    // x faces: the two layers of a row on neighbouring lanes (one cache line)
+    const int s = d == 0 ? (q & 1) : q / area, r = d == 0 ? (q >> 1) : q - s * area;
     int c[3];
     c[t1] = r % n[t1];
     c[t2] = r / n[t1];
