@@ -16,9 +16,9 @@ REFINE, DEREFINE = 0.1, 0.02
 
 def _blast_pair(nrb, blk=16, radius=0.25):
     from paper_2202_12309_amd.binding import Mesh
-    n = (blk,) * 3
+    n = tuple(blk) if isinstance(blk, tuple) else (blk,) * 3
     leaves = inputs.sphere_refined_leaves(nrb, radius=radius)
-    gm = Mesh(tuple(nrb[d] * blk for d in range(3)), n, leaves, max_level=1)
+    gm = Mesh(tuple(nrb[d] * n[d] for d in range(3)), n, leaves, max_level=1)
     om = OracleMesh(n, nrb, leaves, max_level=1)
     assert np.array_equal(gm.leaves(), om.leaves())
     U0 = inputs.blast(gm.leaves(), n, nrb)
@@ -31,13 +31,24 @@ def _flags(eta):
     return np.where(eta > REFINE, 1, np.where(eta < DEREFINE, -1, 0)).astype(np.int8)
 
 
-def test_pressure_jump_indicator_matches_oracle():
-    print_case("pressure-jump indicator, 128^3 root in 16^3 blocks, two levels, 10 cycles")
-    gm, om = _blast_pair((8, 8, 8))
+@pytest.mark.parametrize("blk,nrb,quantity", [((16, 16, 16), (8, 8, 8), "pressure"),
+                                              ((32, 8, 16), (4, 16, 8), "density"),
+                                              ((64, 64, 8), (2, 2, 16), "pressure")])
+def test_pressure_jump_indicator_matches_oracle(blk, nrb, quantity):
+    """The device jump indicators against the oracle's: cubic 16^3 blocks,
+    flat blocks with the density indicator, and rows of 64 x 64 cells (three
+    planes of the block's face ring exceed the indicator's LDS budget, so the
+    per-cell kernel serves them)."""
+    print_case(f"{quantity}-jump indicator, 128^3 root in blocks of {blk}, two levels, 10 cycles")
+    gm, om = _blast_pair(nrb, blk=blk)
     gm.step(10)
     om.step(10)
-    fg, eg = gm.flag_pressure_jump(REFINE, DEREFINE)
-    eo = om.pressure_jump()
+    if quantity == "pressure":
+        fg, eg = gm.flag_pressure_jump(REFINE, DEREFINE)
+        eo = om.pressure_jump()
+    else:
+        fg, eg = gm.flag_density_jump(REFINE, DEREFINE)
+        eo = om.density_jump()
     assert np.all(np.abs(eg - eo) <= 1e-10 * np.maximum(eo, 1e-3)), np.abs(eg - eo).max()
     fo = _flags(eo)
     # the decision is the same except where eta sits within rounding of a threshold
