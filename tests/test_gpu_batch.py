@@ -239,3 +239,37 @@ def test_persistent_needs_16_or_32_cell_rows():
     with pytest.raises(PkhError) as e:
         b.step(1, "persistent")
     assert e.value.name == "PKH_EINVAL"
+
+
+@pytest.mark.parametrize("mode", ["fused", "persistent"])
+def test_bench_mix_full_size_matches_oracle(mode):
+    """The bench's batch workload itself: the 64-instance mix (seed 4, edges
+    32-128, 49.7 million cells) in the launch configuration the bench times,
+    two cycles, every instance against the oracle run of the same instance
+    (one instance at a time on the oracle side): within 1e-12, equal clocks,
+    totals to 1e-13."""
+    print_case(f"bench batch mix, 64 instances, mode {mode}, 2 cycles")
+    import torch
+    from paper_2202_12309_amd.binding import Batch
+    specs = inputs.batch_mix(n=64, seed=4)
+    stream = torch.cuda.Stream()
+    meshes = _make(specs, stream)
+    b = Batch(meshes)
+    b.step(2, mode)
+    worst = 0.0
+    for q, (sp, m) in enumerate(zip(specs, meshes)):
+        n = (sp["blk"],) * 3
+        nrb = (sp["N"] // sp["blk"],) * 3
+        om = OracleMesh(n, nrb, m.leaves())
+        om.set_state(inputs.batch_state(sp, m.leaves()))
+        om.step(2)
+        err = rel_err(m.download(), om.state(), G)
+        worst = max(worst, float(err.max()))
+        assert np.all(err <= 1e-12), (q, sp, err)
+        tg, to = m.time(), om.time()
+        assert tg[2] == to[2] and abs(tg[0] - to[0]) <= 1e-14 * abs(to[0]), (q, tg, to)
+        To, Ao = om.totals()
+        assert np.all(np.abs(m.totals() - To) <= 1e-13 * np.maximum(Ao, 1.0)), q
+        del om
+    print(f"64 instances: worst rel err {worst:.3g}", flush=True)
+    b.close()
