@@ -536,7 +536,8 @@ def main_leg(args):
     lv = inputs.uniform_leaves(nrb)
     mesh = Mesh((N, N, N), n, lv, graph=args.graph)
     mesh.set_tuning(args.tile_rows)
-    mesh.upload(inputs.turbulent_box(mesh.leaves(), n, nrb, seed=2))
+    U0 = inputs.turbulent_box(mesh.leaves(), n, nrb, seed=2)
+    mesh.upload(U0)
     mesh.step(args.warmup)
     mesh.sync()
 
@@ -554,6 +555,23 @@ def main_leg(args):
     mesh.sync()
     kt = mesh.kernel_times()
     t, dt, cyc = mesh.time()
+    mesh.kernel_timing(0)
+    # Host buffers through the boundary, after the timed region: upload from
+    # host memory (pageable numpy), the same cycles, download to host memory.
+    mesh.sync()
+    h0 = time.perf_counter()
+    mesh.upload(U0)
+    mesh.sync()
+    h1 = time.perf_counter()
+    mesh.step(args.steps)
+    mesh.sync()
+    h2 = time.perf_counter()
+    mesh.download()
+    h3 = time.perf_counter()
+    pcie = {"what": f"upload of the state from host memory, {args.steps} cycles, download to host memory",
+            "upload_s": round(h1 - h0, 4), "cycles_s": round(h2 - h1, 4), "download_s": round(h3 - h2, 4),
+            "state_bytes": int(U0.nbytes),
+            "zone_cycles_per_s": N ** 3 * args.steps / (h3 - h0)}
 
     zc = N ** 3 * args.steps / (ms / 1e3)
     b_corr, b_cycle = algorithmic_bytes(blk)
@@ -617,6 +635,7 @@ def main_leg(args):
         "kernel_avg_ms": {k: (round(v, 4) if v else None) for k, v in avg.items()},
         "sim_time": t,
         "roofline": roof,
+        "pcie_inclusive": pcie,
     }
     del mesh
     torch.cuda.empty_cache()
