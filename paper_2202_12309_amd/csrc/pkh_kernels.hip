@@ -35,21 +35,22 @@ namespace pkh {
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void ghost_coord(int q, const Geom& g, int& i, int& j, int& k) {
-  const int plane = g.p1 * g.p2;
+  const int e1 = g.n1 + 2 * NG;  // x extent with ghosts (the row pitch may be larger)
+  const int plane = e1 * g.p2;
   if (q < 4 * plane) {
     const int s = q / plane, r = q - s * plane;
     k = s < 2 ? s - NG : g.n3 + s - 2;
-    j = r / g.p1 - NG;
-    i = r - (j + NG) * g.p1 - NG;
+    j = r / e1 - NG;
+    i = r - (j + NG) * e1 - NG;
     return;
   }
   q -= 4 * plane;
-  const int rows = 4 * g.p1;
+  const int rows = 4 * e1;
   if (q < g.n3 * rows) {
     k = q / rows;
     const int r = q - k * rows;
-    const int s = r / g.p1;
-    i = r - s * g.p1 - NG;
+    const int s = r / e1;
+    i = r - s * e1 - NG;
     j = s < 2 ? s - NG : g.n2 + s - 2;
     return;
   }
@@ -97,7 +98,7 @@ __device__ __forceinline__ void fill_cell(double* u, const BlockInfo* blocks, co
 // Every ghost region (all 26) of every leaf.
 __global__ void __launch_bounds__(256) fill_kernel(double* u, const BlockInfo* blocks, int nblocks,
                                                    Geom g, LevelMaps M, DevTime* tm, int skip_same) {
-  const int ngc = 4 * g.p1 * g.p2 + 4 * g.n3 * g.p1 + 4 * g.n3 * g.n2;
+  const int ngc = 4 * (g.n1 + 2 * NG) * g.p2 + 4 * g.n3 * (g.n1 + 2 * NG) + 4 * g.n3 * g.n2;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
   if (q >= ngc || b >= nblocks) return;
@@ -210,7 +211,7 @@ hipError_t launch_remote_unpack(double* u, const RemoteFace* rf, int32_t nrf, co
 
 hipError_t launch_fill(double* u, const BlockInfo* blocks, int32_t nblocks, const Geom& g,
                        const LevelMaps& maps, DevTime* tm, int32_t skip_same, hipStream_t s) {
-  const int ngc = 4 * g.p1 * g.p2 + 4 * g.n3 * g.p1 + 4 * g.n3 * g.n2;
+  const int ngc = 4 * (g.n1 + 2 * NG) * g.p2 + 4 * g.n3 * (g.n1 + 2 * NG) + 4 * g.n3 * g.n2;
   dim3 grid((ngc + 255) / 256, nblocks);
   hipLaunchKernelGGL(fill_kernel, grid, dim3(256), 0, s, u, blocks, nblocks, g, maps, tm,
                      (int)skip_same);

@@ -20,6 +20,14 @@
 #include "pkhydro.h"
 #include "pkh_internal.h"
 
+// Row pitch of the state arrays, in doubles: each padded row is rounded up
+// to a multiple of PKH_ROW_ALIGN and the arrays start PKH_ROW_ALIGN - NG
+// doubles into their allocation, so that the active cells of every row
+// begin on a 128-byte line (1: no padding).
+#ifndef PKH_ROW_ALIGN
+#define PKH_ROW_ALIGN 16
+#endif
+
 using namespace pkh;
 
 namespace {
@@ -236,6 +244,16 @@ struct pkh_mesh {
   int64_t nb() const { return (int64_t)tree.leaves.size(); }
   bool fp32 = false;  // state stored in FP32 (single-level periodic meshes)
   size_t state_bytes() const { return (size_t)nb() * g.bstride * (fp32 ? sizeof(float) : sizeof(double)); }
+  // A and B start this many doubles into their allocations (the row
+  // alignment of the active cells)
+  static constexpr int64_t state_head() { return (PKH_ROW_ALIGN - NG % PKH_ROW_ALIGN) % PKH_ROW_ALIGN; }
+  double* state_alloc() {
+    double* raw = (double*)dalloc(state_bytes() + state_head() * sizeof(double));
+    return raw ? raw + state_head() : nullptr;
+  }
+  void state_free(double* p) {
+    if (p) dfree(p - state_head());
+  }
   float* Af() const { return reinterpret_cast<float*>(A); }
 
   void* dalloc(size_t bytes) {
@@ -674,8 +692,8 @@ int check_config(const pkh_config* c) {
 }
 
 int alloc_state(pkh_mesh* m) {
-  m->A = (double*)m->dalloc(m->state_bytes());
-  m->B = (double*)m->dalloc(m->state_bytes());
+  m->A = m->state_alloc();
+  m->B = m->state_alloc();
   if (!m->A || !m->B) return fail(PKH_ENOMEM, "state allocation of 2 x %zu bytes failed", m->state_bytes());
   HIPCHK(hipMemsetAsync(m->A, 0, m->state_bytes(), m->stream));
   HIPCHK(hipMemsetAsync(m->B, 0, m->state_bytes(), m->stream));
@@ -725,7 +743,7 @@ int pkh_mesh_create(const pkh_config* cfg, const pkh_loc* blocks, int64_t nblock
   g.n1 = cfg->nblock[0];
   g.n2 = cfg->nblock[1];
   g.n3 = cfg->nblock[2];
-  g.p1 = g.n1 + 2 * NG;
+  g.p1 = (g.n1 + 2 * NG + PKH_ROW_ALIGN - 1) / PKH_ROW_ALIGN * PKH_ROW_ALIGN;
   g.p2 = g.n2 + 2 * NG;
   g.p3 = g.n3 + 2 * NG;
   g.vstride = (int64_t)g.p1 * g.p2 * g.p3;
@@ -767,8 +785,8 @@ int pkh_mesh_destroy(pkh_mesh* m) {
   drop_graph(m);
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   free_tables(m);
-  m->dfree(m->A);
-  m->dfree(m->B);
+  m->state_free(m->A);
+  m->state_free(m->B);
   m->dfree(m->d_time);
   m->dfree(m->d_partial);
   m->dfree(m->d_tot);
@@ -1059,8 +1077,8 @@ int pkh_regrid(pkh_mesh* m) {
   HIPCHK(hipStreamSynchronize(m->stream));
   m->dfree(d_kind);
   m->dfree(d_src);
-  m->dfree(oldA);
-  m->dfree(oldB);
+  m->state_free(oldA);
+  m->state_free(oldB);
   m->dfree(old_blocks);
   m->dfree(old_map);
   m->flags.assign(m->nb(), 0);

@@ -143,15 +143,18 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     const int32_t nb = nb27 ? nb27[q] : -1;
     return nb >= 0 ? (int64_t)(nb - blk) * g.bstride + within : 0;
   };
+  // the state's row pitch g.p1 (at least N1 + 4; the LDS plane keeps P1)
+  const int gp1 = g.p1;
   const int64_t dxl = nbshift(12, N1), dxr = nbshift(14, -N1);
-  const int64_t dyl = j0 == 0 ? nbshift(10, (int64_t)n2 * P1) : 0;
-  const int64_t dyh = j0 + TJ == n2 ? nbshift(16, -(int64_t)n2 * P1) : 0;
-  const int64_t dzl = nbshift(4, (int64_t)n3 * g.p2 * P1), dzh = nbshift(22, -(int64_t)n3 * g.p2 * P1);
+  const int64_t dyl = j0 == 0 ? nbshift(10, (int64_t)n2 * gp1) : 0;
+  const int64_t dyh = j0 + TJ == n2 ? nbshift(16, -(int64_t)n2 * gp1) : 0;
+  const int64_t dzl = nbshift(4, (int64_t)n3 * g.p2 * gp1), dzh = nbshift(22, -(int64_t)n3 * g.p2 * gp1);
   // offset of plane p (row j0-2) of this block, or of the z neighbour's plane
   auto pofs = [&](int p) -> int64_t {
-    return ((int64_t)(p + NG) * g.p2 + j0) * P1 + (p < 0 ? dzl : (p >= n3 ? dzh : 0));
+    return ((int64_t)(p + NG) * g.p2 + j0) * gp1 + (p < 0 ? dzl : (p >= n3 ? dzh : 0));
   };
-  const int own = (tj + NG) * P1 + ti + NG;  // this thread's cell in the LDS plane
+  const int own = (tj + NG) * P1 + ti + NG;      // this thread's cell in the LDS plane
+  const int own_g = (tj + NG) * gp1 + ti + NG;   // and in the state's plane
 
   FState w[WN];       // z window (column states)
   double uq[UQN][NV];  // predictor: conserved own-cell values awaiting their update
@@ -250,14 +253,16 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   // halo cell h of the plane (rows -HW..-1 and TJ..TJ+HW-1 of the tile
   // over the active columns, then the HW cells at each end of the interior
   // rows) -> its LDS slot
-  auto hcell = [&](int h) {
+  // (pitch: P1 for the LDS plane, gp1 for the state)
+  auto hcell_p = [&](int h, int pitch) {
     if (h < 2 * HW * N1) {
       const int r = h / N1, i = h - r * N1;  // r < HW: row r - HW, else row TJ + r - HW
-      return (r < HW ? r + NG - HW : TJ + NG + r - HW) * P1 + NG + i;
+      return (r < HW ? r + NG - HW : TJ + NG + r - HW) * pitch + NG + i;
     }
     const int hh = h - 2 * HW * N1, r = hh / (2 * HW), sc = hh - r * 2 * HW;
-    return (r + NG) * P1 + (sc < HW ? sc + NG - HW : N1 + NG + sc - HW);
+    return (r + NG) * pitch + (sc < HW ? sc + NG - HW : N1 + NG + sc - HW);
   };
+  auto hcell = [&](int h) { return hcell_p(h, P1); };
   // offset from this block's cell to the one halo cell h is read from. The
   // offsets are captured by value so the per-lane choice is a select: taken
   // by reference, they live in scratch memory and every halo load waits for
@@ -276,7 +281,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   for (int hh = 0; hh < HMAX; ++hh) {
     const int h = min(tid + hh * NT, NHALO - 1);
     hslot[hh] = hcell(h);
-    hoff[hh] = hshift(h) + hslot[hh];
+    hoff[hh] = hshift(h) + hcell_p(h, gp1);
   }
   // ring of PFD planes in flight: plane p is staged from slot (p - p_first)
   // % PFD, which then receives plane p + PFD; the loop below is unrolled by
@@ -289,7 +294,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     if (pn >= p_end) return;
     const S* pl = in + pofs(pn);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own];
+    for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own_g];
   };
   auto prefetch_halo = [&](int sl, int pn) {
     if (pn < 0 || pn >= n3) return;  // the halo is only read on the active planes
@@ -307,7 +312,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     // the update of cell c happens at plane p_first + 2 + 2 LAG + c
 #pragma unroll
     for (int c = 0; c < PFD; ++c) {
-      const int64_t oc = ((int64_t)(c + NG) * g.p2 + (j + NG)) * P1 + ti + NG;
+      const int64_t oc = ((int64_t)(c + NG) * g.p2 + (j + NG)) * gp1 + ti + NG;
 #pragma unroll
       for (int v = 0; v < NV; ++v) ubn[(2 + 2 * LAG + c) % PFD][v] = base[v * vs + oc];
     }
@@ -317,7 +322,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
     for (int sl = 0; sl < PFD; ++sl) {
       const S* pl = in + pofs(p_first + sl);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own];
+      for (int v = 0; v < NV; ++v) pu[sl][v] = pl[v * vs + own_g];
       // the halo is only read on the active planes
       const bool act = p_first + sl >= 0 && p_first + sl < n3;
 #pragma unroll
@@ -346,7 +351,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       } else {
         const S* pl = in + pofs(p);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + own];
+        for (int v = 0; v < NV; ++v) u[v] = pl[v * vs + own_g];
       }
       const FState q = stage_cell(u, own);
 #pragma unroll
@@ -388,9 +393,9 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       for (int h = tid; h < NHALO && p >= 0 && p < n3; h += NT) {
         double u[NV];
         const int c = hcell(h);
-        const int64_t hs = hshift(h);
+        const int64_t hs = hshift(h) + hcell_p(h, gp1);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = in[po + hs + v * vs + c];
+        for (int v = 0; v < NV; ++v) u[v] = in[po + hs + v * vs];
         stage_cell(u, c);
       }
     }
@@ -431,7 +436,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
       }
       if (m >= 1) {
         const int k = m - 1;
-        const int64_t o = ((int64_t)(k + NG) * g.p2 + (j + NG)) * P1 + ti + NG;
+        const int64_t o = ((int64_t)(k + NG) * g.p2 + (j + NG)) * gp1 + ti + NG;
         double un[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -444,7 +449,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
         if constexpr (BPF) {
           if (k + PFD < n3) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) ubn[sl][v] = base[v * vs + o + (int64_t)PFD * g.p2 * P1];
+            for (int v = 0; v < NV; ++v) ubn[sl][v] = base[v * vs + o + (int64_t)PFD * g.p2 * gp1];
           }
         }
         if (a.do_dt) {
