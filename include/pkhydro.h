@@ -304,9 +304,9 @@ int pkh_get_partition(const pkh_mesh *mesh, int32_t *nparts, int32_t *nremote, i
    tile_rows: rows of cells per workgroup tile (0 = default). Compiled
    choices: n1 = 8: 8; n1 = 16: 8, 16, 4; n1 = 32: 8, 4, 16; n1 = 64: 4, 2.
    It must divide nblock[1]. An explicit choice applies to both stages; the
-   default may differ between them (on 32-cell rows: 8 rows for the
-   corrector, 16 for the predictor of a large mesh), and pkh_get_tuning
-   reports the corrector's.
+   default is 8 rows on 32-cell rows and 16 on 16-cell rows of a large mesh
+   (it may differ between the stages of other shapes, and pkh_get_tuning
+   reports the corrector's).
    packs: launches per stage (0 or 1: one launch over every leaf). With
    packs = P > 1 the leaves (in storage order) are cut into P contiguous
    ranges of nearly equal count and each stage is launched once per range,

@@ -12,18 +12,15 @@ namespace pkh {
 //
 // Compiled (n1, rows) variants, the default first: n1 = 8: 8; n1 = 16: 8,
 // 16, 4; n1 = 32: 8, 4, 16; n1 = 64: 4, 2. An explicit request must be one
-// of them and divide n2. Defaults: the piecewise-linear stage on 32-cell
-// rows takes 8 rows (its 256-thread variant runs at three waves per SIMD);
-// the donor-cell stage on 32-cell rows takes 16 rows once the launch has at
-// least two rounds of waves at two waves per SIMD (4096 waves), else 8; on
-// 16-cell rows both take 16 rows from 1024 waves on, else 8 (nblocks, the
-// blocks of the launch, 0 when unknown). Measured at 256^3: the corrector
-// 0.722 ms on 8 rows at three waves against 0.754 ms on 16 rows, the
-// predictor 0.47 ms on 16 rows against 0.49 ms on 8; 16 rows against 8 save
-// 3 % with blocks of 16^3 and 7 % of the two-level blast (960 leaves of
-// 16^3). When the preferred default does not divide n2 the default is the
-// largest compiled variant below it that does (then the largest that does
-// at all).
+// of them and divide n2. Defaults: on 32-cell rows both stages take 8 rows
+// (256 threads, three waves per SIMD); on 16-cell rows both take 16 rows
+// from 1024 waves on, else 8 (nblocks, the blocks of the launch, 0 when
+// unknown). Measured at 256^3 on line-aligned state rows: on 32-cell rows
+// the corrector 0.69-0.71 ms on 8 rows against 0.74 ms on 16 and 0.81 ms on
+// 4, the predictor 0.400 ms on 8 rows against 0.412-0.430 ms on 16; on
+// 16-cell rows 16 rows against 8 save 5 % of the cycle. When the preferred
+// default does not divide n2 the default is the largest compiled variant
+// below it that does (then the largest that does at all).
 inline int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0, int recon = 1) {
   static const int opts[4][3] = {{8, 0, 0}, {8, 16, 4}, {8, 4, 16}, {4, 2, 0}};
   const int row = n1 == 8 ? 0 : n1 == 16 ? 1 : n1 == 32 ? 2 : n1 == 64 ? 3 : -1;
@@ -35,7 +32,6 @@ inline int stage_tile_rows(int n1, int n2, int tj, int64_t nblocks = 0, int reco
   }
   int want = opts[row][0];
   const int64_t waves = nblocks * n1 * n2 / 64;
-  if (n1 == 32 && !recon && (nblocks == 0 || waves >= 4096)) want = 16;
   if (n1 == 16 && nblocks > 0 && waves >= 1024) want = 16;
   int best = -1, any = -1;
   for (int q = 0; q < 3; ++q) {

@@ -31,10 +31,10 @@ def test_default_always_fits(rows):
 def test_default_choices(rows):
     # piecewise-linear stage on 32-cell rows: 8 rows (its three-wave variant)
     assert rows(32, 32, 0, 512) == 8 and rows(32, 32, 0, 0) == 8
-    # donor-cell stage on 32-cell rows: 16 rows for large launches
-    assert rows(32, 32, 0, 512, 0) == 16  # 256^3 in 32^3 blocks: 8192 waves
+    # donor-cell stage on 32-cell rows: 8 rows as well, whatever the launch
+    assert rows(32, 32, 0, 512, 0) == 8   # 256^3 in 32^3 blocks: 8192 waves
     assert rows(32, 32, 0, 8, 0) == 8     # small launch
-    assert rows(32, 32, 0, 0, 0) == 16    # launch size unknown
+    assert rows(32, 32, 0, 0, 0) == 8     # launch size unknown
     for recon in (0, 1):
         assert rows(16, 16, 0, 960, recon) == 16    # two-level blast
         assert rows(16, 16, 0, 8, recon) == 8
@@ -42,7 +42,6 @@ def test_default_choices(rows):
     # 16 rows preferred but not a divisor: the next compiled choice below
     assert rows(32, 24, 0, 4096, 0) == 8
     assert rows(32, 8, 0, 4096, 0) == 8
-    assert rows(32, 24, 0, 0, 0) == 8
     assert rows(16, 24, 0, 1024) == 8
     assert rows(16, 8, 0, 2048) == 8
 
