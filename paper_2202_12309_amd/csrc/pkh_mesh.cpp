@@ -247,13 +247,17 @@ struct pkh_mesh {
   // A and B start this many doubles into their allocations (the row
   // alignment of the active cells)
   static constexpr int64_t state_head() { return (PKH_ROW_ALIGN - NG % PKH_ROW_ALIGN) % PKH_ROW_ALIGN; }
-  double* state_alloc() {
-    double* raw = (double*)dalloc(state_bytes() + state_head() * sizeof(double));
+  // arrays in the padded block layout (states, the tape's recomputed
+  // states and adjoint arrays), line-aligned like A and B
+  double* padded_alloc(size_t bytes) {
+    double* raw = (double*)dalloc(bytes + state_head() * sizeof(double));
     return raw ? raw + state_head() : nullptr;
   }
-  void state_free(double* p) {
+  void padded_free(double* p) {
     if (p) dfree(p - state_head());
   }
+  double* state_alloc() { return padded_alloc(state_bytes()); }
+  void state_free(double* p) { padded_free(p); }
   float* Af() const { return reinterpret_cast<float*>(A); }
 
   void* dalloc(size_t bytes) {
@@ -1223,15 +1227,15 @@ size_t active_bytes(const pkh_mesh* m) {
 void tape_free(pkh_tape* t) {
   pkh_mesh* m = t->m;
   for (double* p : t->ckpt) m->dfree(p);
-  for (double* p : t->S) m->dfree(p);
-  for (double* p : t->Us) m->dfree(p);
+  for (double* p : t->S) m->padded_free(p);
+  for (double* p : t->Us) m->padded_free(p);
   t->ckpt.clear();
   t->S.clear();
   t->Us.clear();
   m->dfree(t->d_dts);
-  m->dfree(t->wbar);
+  m->padded_free(t->wbar);
   m->dfree(t->xlast);
-  m->dfree(t->gw);
+  m->padded_free(t->gw);
   t->gw = nullptr;
   for (auto& l : t->lam) m->dfree(l);
   m->dfree(t->d_time);
@@ -1305,18 +1309,18 @@ int pkh_tape_create(pkh_mesh* m, int32_t ckpt_every, pkh_tape** out) {
   const size_t pb = m->state_bytes();
   bool ok = true;
   for (int q = 0; q <= ckpt_every && ok; ++q) {
-    t->S.push_back((double*)m->dalloc(pb));
+    t->S.push_back(m->padded_alloc(pb));
     ok = t->S.back() != nullptr;
   }
   for (int q = 0; q < ckpt_every && ok; ++q) {
-    t->Us.push_back((double*)m->dalloc(pb));
+    t->Us.push_back(m->padded_alloc(pb));
     ok = t->Us.back() != nullptr;
   }
   if (ok) {
     if (t->facewise) {
-      t->gw = (double*)m->dalloc(pb);
+      t->gw = m->padded_alloc(pb);
     } else {
-      t->wbar = (double*)m->dalloc(2 * pb);
+      t->wbar = m->padded_alloc(2 * pb);
       t->xlast = (double*)m->dalloc((size_t)m->nb() * m->g.n2 * m->g.n3 * 20 * sizeof(double));
     }
     for (auto& l : t->lam) l = (double*)m->dalloc(active_bytes(m));
@@ -1355,16 +1359,16 @@ int pkh_tape_set_facewise(pkh_tape* t, int32_t on) {
   if ((on != 0) == t->facewise) return PKH_OK;
   HIPCHK(hipStreamSynchronize(m->stream));
   const size_t pb = m->state_bytes();
-  m->dfree(t->gw);
-  m->dfree(t->wbar);
+  m->padded_free(t->gw);
+  m->padded_free(t->wbar);
   m->dfree(t->xlast);
   t->gw = t->wbar = t->xlast = nullptr;
   t->facewise = on != 0;
   if (t->facewise) {
-    t->gw = (double*)m->dalloc(pb);
+    t->gw = m->padded_alloc(pb);
     if (!t->gw) return fail(PKH_ENOMEM, "tape allocation failed");
   } else {
-    t->wbar = (double*)m->dalloc(2 * pb);
+    t->wbar = m->padded_alloc(2 * pb);
     t->xlast = (double*)m->dalloc((size_t)m->nb() * m->g.n2 * m->g.n3 * 20 * sizeof(double));
     if (!t->wbar || !t->xlast) return fail(PKH_ENOMEM, "tape allocation failed");
   }
