@@ -7,6 +7,21 @@
 
 namespace pkh {
 
+// Load of a value the whole wave reads at one address, from memory that no
+// thread writes while the kernel runs (block tables, neighbour lists, launch
+// records): read through the constant address space it becomes a scalar
+// load into SGPRs. A generic load inside a loop that also stores to global
+// memory cannot be proven unclobbered, and its result, with everything
+// derived from it, would occupy VGPRs.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T*)p;
+#else
+  return *p;  // the host pass only parses device code
+#endif
+}
+
 // Fold a workgroup's largest signal speed per cell width (mx >= 0) into the
 // cycle's CFL reduction. Non-negative doubles order like their bit
 // patterns; the maximum only grows within a cycle, so a workgroup whose

@@ -83,10 +83,11 @@ constexpr int stage_lds_doubles() {
 
 // One tile (TJ rows of block blk starting at row j0) of a stage with
 // timestep dt, in LDS at lds (stage_lds_doubles doubles); rot rotates which
-// wave takes the tile's remainder faces.
+// wave takes the tile's remainder faces; tid is the thread's index in the
+// workgroup.
 template <int RECON, int N1, int TJ, typename S = double>
 __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0, int rot, double dt,
-                                           double* __restrict__ lds) {
+                                           double* __restrict__ lds, int tid) {
   constexpr int NT = N1 * TJ;
   constexpr int P1 = N1 + 2 * NG;
   constexpr int RW = TJ + 2 * NG;
@@ -116,10 +117,9 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   double* __restrict__ sRed = lds + NQ * PLANE + NV * NX + NV * NY;
 
   const Geom& g = a.g;
-  const int tid = threadIdx.x;
   const int ti = tid % N1, tj = tid / N1;
 
-  const BlockInfo bi = a.blocks[blk];
+  const BlockInfo bi = load_uniform(a.blocks + blk);
   const double gam = g.gamma;
   const double gm1 = gam - 1.0;
   const double igm1 = 1.0 / gm1;
@@ -140,7 +140,7 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
   // another level reads this block's ghost zone, which the fill kernel
   // writes. Offsets from this block's cell to the cell read instead:
   auto nbshift = [&](int q, int64_t within) -> int64_t {
-    const int32_t nb = nb27 ? nb27[q] : -1;
+    const int32_t nb = nb27 ? load_uniform(nb27 + q) : -1;
     return nb >= 0 ? (int64_t)(nb - blk) * g.bstride + within : 0;
   };
   // the state's row pitch g.p1 (at least N1 + 4; the LDS plane keeps P1)
@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(N1 * TJ, (stage_waves<RECON, N1, TJ>())) stage
   const int blk = wg / ntj;
   if (blk >= a.nblocks) return;
   __shared__ double lds[stage_lds_doubles<RECON, N1, TJ>()];
-  stage_tile<RECON, N1, TJ>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg, a.tm->dt, lds);
+  stage_tile<RECON, N1, TJ>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg, a.tm->dt, lds, (int)threadIdx.x);
 }
 
 // The same over a state stored in FP32.
@@ -575,7 +575,7 @@ __global__ void __launch_bounds__(N1 * TJ, (stage_waves<RECON, N1, TJ>())) stage
   const int blk = wg / ntj;
   if (blk >= a.nblocks) return;
   __shared__ double lds[stage_lds_doubles<RECON, N1, TJ>()];
-  stage_tile<RECON, N1, TJ, float>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg, a.tm->dt, lds);
+  stage_tile<RECON, N1, TJ, float>(a, a.b0 + blk, (wg - blk * ntj) * TJ, wg, a.tm->dt, lds, (int)threadIdx.x);
 }
 
 // Grouped launch: the tiles of many independent meshes (same block width
@@ -588,7 +588,7 @@ __global__ void __launch_bounds__(N1 * TJ, (stage_waves<RECON, N1, TJ>())) stage
   const GroupItem it = items[wg];
   __shared__ double lds[stage_lds_doubles<RECON, N1, TJ>()];
   const StageLaunch& a = insts[it.inst];
-  stage_tile<RECON, N1, TJ>(a, it.blk, it.j0, wg, a.tm->dt, lds);
+  stage_tile<RECON, N1, TJ>(a, it.blk, it.j0, wg, a.tm->dt, lds, (int)threadIdx.x);
 }
 
 // ---- end of the stage kernels (the persistent batch kernel follows) ----
@@ -689,10 +689,13 @@ __global__ void __launch_bounds__(256, W)
   for (;;) {
     if (tid == 0) s_ticket = atomicAdd(&q->ticket, 1u);
     __syncthreads();
-    const unsigned int tk = s_ticket;
+    // the item and its instance's records are uniform: kept in SGPRs (a
+    // value read from LDS or a generic load would sit in VGPRs, and so would
+    // every address derived from it inside the tile)
+    const unsigned int tk = __builtin_amdgcn_readfirstlane(s_ticket);
     if (tk >= total) break;  // uniform: every wave of the workgroup leaves
     const unsigned int c = tk / nper;
-    const PItem it = qitems[tk - c * nper];
+    const PItem it = load_uniform(qitems + (tk - c * nper));
     const PInst& in = insts[it.inst];
     PSync* ps = sync + it.inst;
     if (tid == 0) {
@@ -710,21 +713,30 @@ __global__ void __launch_bounds__(256, W)
       s_dt = __hip_atomic_load(&in.st[0].tm->dt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    if (s_ok) {
-      const double dt = s_dt;
+    if (__builtin_amdgcn_readfirstlane(s_ok)) {
+      const long long dtb = __double_as_longlong(s_dt);
+      const double dt = __longlong_as_double(
+          ((long long)__builtin_amdgcn_readfirstlane((int)(dtb >> 32)) << 32) |
+          (unsigned int)__builtin_amdgcn_readfirstlane((int)dtb));
       const int ph = it.phase;
       if (ph == 0 || ph == 3) {
         const StageLaunch& a = in.st[ph == 3];
-        if (in.n1 == 32) {
+        // the thread index as an opaque value: the per-lane set-up of each
+        // tile variant is then formed per item instead of being hoisted out
+        // of the item loop, where it would hold VGPRs for every variant
+        int ltid = tid;
+        asm volatile("" : "+v"(ltid));
+        const int n1 = in.n1;
+        if (n1 == 32) {
           if (a.recon)
-            stage_tile<1, 32, 8>(a, it.a, it.b, (int)tk, dt, lds);
+            stage_tile<1, 32, 8>(a, it.a, it.b, (int)tk, dt, lds, ltid);
           else
-            stage_tile<0, 32, 8>(a, it.a, it.b, (int)tk, dt, lds);
+            stage_tile<0, 32, 8>(a, it.a, it.b, (int)tk, dt, lds, ltid);
         } else {
           if (a.recon)
-            stage_tile<1, 16, 16>(a, it.a, it.b, (int)tk, dt, lds);
+            stage_tile<1, 16, 16>(a, it.a, it.b, (int)tk, dt, lds, ltid);
           else
-            stage_tile<0, 16, 16>(a, it.a, it.b, (int)tk, dt, lds);
+            stage_tile<0, 16, 16>(a, it.a, it.b, (int)tk, dt, lds, ltid);
         }
       } else if (ph == 1 || ph == 4) {
         const StageLaunch& a = in.st[ph == 4];
