@@ -260,7 +260,19 @@ def amr_leg(cycles=200, regrid_every=10):
     from paper_2202_12309_amd.binding import Mesh
     blk, nrb = 16, (8, 8, 8)
     n = (blk,) * 3
-    mesh = Mesh((128,) * 3, n, inputs.sphere_refined_leaves(nrb, radius=0.25), max_level=1)
+    lv = inputs.sphere_refined_leaves(nrb, radius=0.25)
+    # warm-up on a throwaway mesh of the same layout (cycles, indicator,
+    # regrid), so the first launch of each kernel stays out of the timed
+    # region as in the other legs
+    w = Mesh((128,) * 3, n, lv, max_level=1)
+    w.upload(inputs.blast(w.leaves(), n, nrb))
+    w.step(2)
+    w.flag_pressure_jump(0.1, 0.02)
+    w.regrid()
+    w.step(1)
+    w.sync()
+    w.close()
+    mesh = Mesh((128,) * 3, n, lv, max_level=1)
     mesh.upload(inputs.blast(mesh.leaves(), n, nrb))
     mesh.sync()
     leaves0 = mesh.nleaves

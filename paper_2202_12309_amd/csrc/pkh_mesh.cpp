@@ -527,17 +527,24 @@ int check_err(pkh_mesh* m) {
   return PKH_OK;
 }
 
-int do_exchange(pkh_mesh* m) {
-  // an FP32-stored mesh is single-level and periodic: the stage kernels read
-  // every halo cell from a neighbour, so no ghost zone is ever read
-  if (!m->fp32)
-    HIPCHK(launch_fill(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->maps, m->d_time, 0, m->stream));
+// The CFL timestep of the current state (dt_kernel, then the clock).
+int refresh_dt(pkh_mesh* m) {
   HIPCHK(hipMemsetAsync(&m->d_time->smax_bits, 0, sizeof(unsigned long long), m->stream));
   if (m->fp32)
     HIPCHK(launch_dt(m->Af(), m->d_blocks, (int32_t)m->nb(), m->g, m->d_time, m->stream));
   else
     HIPCHK(launch_dt(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->d_time, m->stream));
   HIPCHK(launch_clock(m->d_time, CLOCK_FROM_SMAX, NAN, m->stream));
+  return PKH_OK;
+}
+
+int do_exchange(pkh_mesh* m) {
+  // an FP32-stored mesh is single-level and periodic: the stage kernels read
+  // every halo cell from a neighbour, so no ghost zone is ever read
+  if (!m->fp32)
+    HIPCHK(launch_fill(m->A, m->d_blocks, (int32_t)m->nb(), m->g, m->maps, m->d_time, 0, m->stream));
+  int rc;
+  if ((rc = refresh_dt(m))) return rc;
   m->ghosts_valid = true;
   return PKH_OK;
 }
@@ -695,12 +702,18 @@ int check_config(const pkh_config* c) {
   return PKH_OK;
 }
 
-int alloc_state(pkh_mesh* m) {
+// clear: zero both arrays (at creation). A regrid skips it: the regrid
+// kernel writes every active cell of A, the face fill its ghost faces, and
+// the cycle writes B before reading it; no kernel reads the rest (the
+// other ghost regions, the row padding).
+int alloc_state(pkh_mesh* m, bool clear = true) {
   m->A = m->state_alloc();
   m->B = m->state_alloc();
   if (!m->A || !m->B) return fail(PKH_ENOMEM, "state allocation of 2 x %zu bytes failed", m->state_bytes());
-  HIPCHK(hipMemsetAsync(m->A, 0, m->state_bytes(), m->stream));
-  HIPCHK(hipMemsetAsync(m->B, 0, m->state_bytes(), m->stream));
+  if (clear) {
+    HIPCHK(hipMemsetAsync(m->A, 0, m->state_bytes(), m->stream));
+    HIPCHK(hipMemsetAsync(m->B, 0, m->state_bytes(), m->stream));
+  }
   return PKH_OK;
 }
 
@@ -1073,12 +1086,13 @@ int pkh_regrid(pkh_mesh* m) {
   free_cycle_tables(m);
   m->tree = std::move(nt);
   int32_t *d_kind = nullptr, *d_src = nullptr;
-  if ((rc = build_tables(m, m->h_blocks, &m->d_map, m->maps)) || (rc = alloc_state(m)) ||
+  if ((rc = build_tables(m, m->h_blocks, &m->d_map, m->maps)) || (rc = alloc_state(m, false)) ||
       (rc = upload_vec(m, &d_kind, kind)) || (rc = upload_vec(m, &d_src, src)))
     return rc;
   HIPCHK(launch_regrid_data(m->A, m->d_blocks, d_kind, d_src, (int32_t)m->nb(), oldA, old_blocks,
                             old_maps, m->g, m->d_time, m->stream));
-  HIPCHK(hipStreamSynchronize(m->stream));
+  // frees are ordered after the regrid kernel on the stream (or, with
+  // hipFree, synchronise by themselves)
   m->dfree(d_kind);
   m->dfree(d_src);
   m->state_free(oldA);
@@ -1086,7 +1100,14 @@ int pkh_regrid(pkh_mesh* m) {
   m->dfree(old_blocks);
   m->dfree(old_map);
   m->flags.assign(m->nb(), 0);
-  if ((rc = ensure_partials(m)) || (rc = do_exchange(m))) return rc;
+  if ((rc = ensure_partials(m))) return rc;
+  // the ghost faces the cycle and the indicators read (level jumps, walls,
+  // remote faces; same-level halos are read from the neighbours), then the
+  // new state's CFL timestep
+  if (m->njf) HIPCHK(launch_fill_faces(m->A, m->g, m->d_time, m->d_jf, m->d_plan, m->njf, m->stream));
+  if ((rc = exchange_remote(m, m->A, false))) return rc;
+  if ((rc = refresh_dt(m))) return rc;
+  m->ghosts_valid = true;
   return check_err(m);
 }
 
