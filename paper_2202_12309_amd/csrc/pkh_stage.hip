@@ -538,13 +538,13 @@ __device__ __forceinline__ void stage_tile(const StageLaunch& a, int blk, int j0
 // Waves per SIMD a stage variant is compiled for. The corrector on 256-thread
 // tiles of 16- or 32-cell rows (16 x 16, 32 x 8) runs at three (a 168-VGPR
 // cap with a few spilled values): more waves keep more loads in flight per
-// CU. On 64-cell rows (64 x 4) the cap spills 54 registers and the corrector
-// at 256^3 took 1.33 ms against 0.785 ms at two waves. Measured at 256^3: in 32^3 blocks 0.722 ms against 0.758 ms at two
+// CU. Measured at 256^3: in 32^3 blocks 0.722 ms against 0.758 ms at two
 // waves with the same tiles and 0.754 ms for 16-row tiles at two; in 16^3
-// blocks, on line-aligned rows, 0.722 against 0.789 ms. Everything else at
-// two (the predictor, whose registers allow three anyway, is bound by its
-// memory traffic; the other tile shapes spill more; four waves spill
-// heavily).
+// blocks, on line-aligned rows, 0.722 against 0.789 ms. On 64-cell rows
+// (64 x 4) the cap spills 54 registers: 1.33 ms against 0.785 ms at two.
+// Everything else at two (the predictor, whose registers allow three
+// anyway, is bound by its memory traffic; the other tile shapes spill more;
+// four waves spill heavily).
 template <int RECON, int N1, int TJ>
 constexpr int stage_waves() {
   return (RECON && (N1 == 16 || N1 == 32) && N1 * TJ == 256) ? PKH_CORR_WAVES_256
