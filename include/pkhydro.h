@@ -213,7 +213,9 @@ int pkh_flag_pressure_jump(pkh_mesh *mesh, double refine_above, double derefine_
    when the merged block keeps 2:1. New children get the prolongation of
    the composite field at the parent's level, a merged parent the
    restriction of its children. The tree and all tables are rebuilt on the
-   host, the data moved on the device, ghosts and the timestep recomputed.
+   host, the data moved on the device, the ghost faces the cycle reads
+   (across level jumps, walls and remote faces) filled and the timestep
+   recomputed; pkh_exchange_boundaries fills every ghost region.
    Flags are cleared. Synchronises. PKH_ESTATE while a tape or a batch
    holds the mesh (they keep pointers into its leaf layout): destroy them
    first. */
