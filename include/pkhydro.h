@@ -119,8 +119,10 @@ typedef struct {
 } pkh_loc;
 
 /* Device-memory callbacks. alloc returns device memory of at least `bytes`
-   usable on `stream` (NULL on failure); free releases it. Pass NULL for both
-   to use hipMalloc / hipFree. */
+   usable on `stream` (NULL on failure); free releases it. The library may
+   free memory that work already queued on `stream` still uses: free must
+   release it in stream order (as hipFreeAsync or a stream-ordered caching
+   allocator does). Pass NULL for both to use hipMalloc / hipFree. */
 typedef void *(*pkh_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*pkh_free_fn)(void *ptr, void *stream, void *ctx);
 
